@@ -1,0 +1,253 @@
+/*
+ * mfa.h - C ABI of the MI355X (gfx950) MFA evaluator and ray caster.
+ *
+ * The library evaluates multivariate functional approximation (MFA) models -
+ * tensor products of B-spline functions given by knots and control points
+ * (paper, Sec. III-A) - for value and analytic gradient at arbitrary points
+ * (Sec. III-B; the query interface of Sec. IV-A4), and ray-casts them with
+ * transfer-function lookup, gradient shading and front-to-back "over"
+ * compositing with early ray termination (Sec. IV-A4, IV-A5, IV-B).  Models
+ * are made of blocks from a partition of the volume (Sec. IV-A1), each block
+ * an independent model over its own box, and are kept resident in device
+ * memory (the "fetched to the memory of each target node" step, Sec. IV-A3).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an mfa_status; nothing throws across the ABI.
+ *    On a status other than MFA_OK, mfa_last_error() returns a message for
+ *    the calling thread.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    rejected call has no effect and returns MFA_E_ARG (or MFA_E_NOMEM /
+ *    MFA_E_UNSUPPORTED).
+ *  - Buffers named "device" are caller-owned device memory of the device the
+ *    model was created on; the library never frees them.  Buffers named
+ *    "host" are caller-owned host memory, read or written before the call
+ *    returns.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*, NULL = the default stream) and the call returns without
+ *    synchronising.  A fault during the kernel surfaces as MFA_E_DEVICE from
+ *    a later call that synchronises (or from hipStreamSynchronize).
+ *  - Exact FP64 decisions (span, block, ray schedule) follow the readings of
+ *    the paper stated at each function; values and gradients are FP32.
+ */
+#ifndef MFA_H
+#define MFA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFA_OK = 0,
+  MFA_E_ARG = -1,          /* invalid argument (message says which)           */
+  MFA_E_NOMEM = -2,        /* device or host allocation failed                */
+  MFA_E_DEVICE = -3,       /* HIP runtime error or device fault               */
+  MFA_E_BUDGET = -4,       /* request exceeds the server's memory budget      */
+  MFA_E_BUSY = -5,         /* server queue full                               */
+  MFA_E_NOTFOUND = -6,     /* unknown model id / ticket                       */
+  MFA_E_UNSUPPORTED = -7   /* valid but not implemented (e.g. degree > 7)     */
+} mfa_status;
+
+typedef enum { MFA_F64 = 0, MFA_F32 = 1, MFA_BF16 = 2, MFA_F16 = 3 } mfa_dtype;
+
+typedef struct mfa_model_s* mfa_model;   /* opaque; owns the device copy */
+
+/* ------------------------------------------------------------------ models */
+
+/* World box split into grid[0] x grid[1] x grid[2] blocks (Sec. IV-A1;
+ * Table I lists the paper's partitions).
+ *  grid   : blocks per axis, each >= 1; {1,1,1} is a single-block model.
+ *  lo, hi : world box, lo[a] < hi[a].
+ *  edges  : optional host FP64 block edges per axis, grid[a]+1 strictly
+ *           increasing values with edges[a][0] == lo[a] and
+ *           edges[a][grid[a]] == hi[a]; NULL = lo + (hi-lo) * (i / grid),
+ *           computed in FP64.  Copied during create.
+ *  voxel  : reference voxel size in world units (> 0); a render step of 0
+ *           means half a voxel.                                             */
+typedef struct {
+  int32_t grid[3];
+  double lo[3];
+  double hi[3];
+  const double* edges[3];
+  double voxel;
+} mfa_domain_desc;
+
+/* One block: degree and control-point count per axis, knots, coefficients.
+ *  degree : 1..7 per axis; all blocks of a model share one degree on all
+ *           axes (MFA_E_UNSUPPORTED otherwise).
+ *  n_ctrl : control points per axis, n >= degree + 1.
+ *  knots  : optional host FP64 knot vectors, n + p + 1 nondecreasing values,
+ *           clamped: T[0..p] = 0 and T[n..n+p] = 1, every span inside
+ *           [T[p], T[n]] reachable (T[p] < T[p+1] is not required, spans of
+ *           zero length are skipped by the span rule).  NULL = clamped
+ *           uniform: T[p+j] = j / (n - p), one FP64 division each.
+ *  ctrl   : host, C order [n0][n1][n2] (axis 2 fastest), element type
+ *           ctrl_dtype (MFA_F64 or MFA_F32), all finite.                    */
+typedef struct {
+  int32_t degree[3];
+  int32_t n_ctrl[3];
+  const double* knots[3];
+  const void* ctrl;
+  mfa_dtype ctrl_dtype;
+} mfa_block_desc;
+
+/* Creates a model on the current HIP device (Sec. IV-A2/IV-A3: encoded
+ * blocks, fetched once into device memory).
+ *  blocks   : host array of nblocks descriptors in C order over the grid
+ *             (block (b0,b1,b2) at (b0*grid[1] + b1)*grid[2] + b2);
+ *             nblocks must equal grid[0]*grid[1]*grid[2].
+ *  storage  : MFA_F32, MFA_BF16 or MFA_F16.  Stored value =
+ *             RNE(FP64 -> FP32), then RNE(FP32 -> BF16/FP16).
+ *  out      : receives the handle.  Host data are copied; the caller may
+ *             free them on return.  The call synchronises the device.
+ * Errors: MFA_E_ARG (shape, knots, non-finite data), MFA_E_UNSUPPORTED
+ * (degree), MFA_E_NOMEM, MFA_E_DEVICE.                                     */
+mfa_status mfa_model_create(const mfa_domain_desc* domain, const mfa_block_desc* blocks,
+                            int32_t nblocks, mfa_dtype storage, mfa_model* out);
+
+/* Frees the device copy.  The caller must ensure no enqueued work still
+ * uses the model.  NULL is accepted (no-op).                               */
+mfa_status mfa_model_destroy(mfa_model model);
+
+typedef struct {
+  int64_t device_bytes;    /* bytes of device memory held by the model       */
+  int64_t ctrl_bytes;      /* of which stored control points                 */
+  int64_t n_ctrl_total;    /* control points over all blocks                 */
+  int32_t nblocks;
+  int32_t degree;
+  mfa_dtype storage;
+  float vmin, vmax;        /* min / max of the stored control points         */
+  double voxel;
+  int32_t device;          /* HIP device ordinal                             */
+} mfa_model_info_t;
+
+mfa_status mfa_model_info(mfa_model model, mfa_model_info_t* info);
+
+/* Copies the stored control points of one block back to host memory
+ * (stored bits: 4 bytes per point for MFA_F32, 2 for BF16/FP16), C order.
+ * dst_bytes must be at least n0*n1*n2*elem_size.  Synchronises the device. */
+mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst, int64_t dst_bytes);
+
+/* ------------------------------------------------------------------ decode */
+
+/* Value and gradient at n world points (the value/gradient query of
+ * Sec. IV-A4; analytic derivatives, Sec. III-B).
+ *  xyz   : device FP32, structure of arrays [3][n] (x then y then z); each
+ *          coordinate is promoted exactly to FP64.
+ *  n     : 0 <= n < 2^31 (n == 0 is a no-op).
+ *  flags : 0, or MFA_DECODE_SORTED to evaluate in (block, tile) order
+ *          (results are still written in input order; needs scratch memory
+ *          held by the model).
+ *  out   : device FP32 [n][4] = (f, df/dx, df/dy, df/dz) in world units.
+ *  dbg   : NULL, or device int32 [n][4] = (span0, span1, span2, block)
+ *          with block = (b0*grid1 + b1)*grid2 + b2.
+ * Map: xc = clamp(x, E[0], E[G]); owning block b = max{i : E[i] <= xc};
+ * u = clamp((xc - lo_b) * inv_ext_b, 0, 1) with inv_ext_b = 1/(hi_b - lo_b)
+ * (FP64, unfused); span s = max{i in [p, n-1] : T[i] <= u}.               */
+#define MFA_DECODE_SORTED 1u
+mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint32_t flags,
+                             float* out, int32_t* dbg, void* stream);
+
+/* Value and gradient on the tensor grid axis_u[0] x axis_u[1] x axis_u[2]
+ * of parameters of a single-block model (MFA_E_ARG for multi-block).
+ *  axis_u : three device FP64 tables of res[a] parameters (clamped to
+ *           [0,1]); any order, nondecreasing tables are fastest.
+ *  res    : 1 <= res[a], res0*res1*res2 < 2^40.
+ *  out    : device FP32 [res0][res1][res2][4] (axis 2 fastest) =
+ *           (f, df/dx, df/dy, df/dz), gradient in world units.
+ *  spans  : NULL, or device int32 [res0 + res1 + res2]: the span of each
+ *           table entry, axis 0 entries first.                             */
+mfa_status mfa_decode_grid(mfa_model model, const double* const axis_u[3], const int32_t res[3],
+                           float* out, int32_t* spans, void* stream);
+
+/* ------------------------------------------------------------------ render */
+
+enum { MFA_ORTHO = 0, MFA_PERSPECTIVE = 1 };
+
+/* Camera (view-dependent parameters, Sec. IV-B).  right, up, forward form
+ * an orthonormal right-handed basis built by the caller in FP64.  Pixel
+ * (i, j), row j = 0 at the top: px = (2i + 1 - w) * sx,
+ * py = (h - 2j - 1) * sy.  Orthographic: origin (eye + px*right) + py*up,
+ * direction forward.  Perspective: origin eye, direction
+ * (forward + px*right) + py*up, not normalised, so the ray parameter is the
+ * depth along forward.                                                     */
+typedef struct {
+  int32_t kind;
+  double eye[3];
+  double forward[3];
+  double right[3];
+  double up[3];
+  double sx, sy;
+} mfa_camera;
+
+/* Data-dependent parameters (Sec. IV-B: transfer function and shading).
+ *  tf_rgba     : device FP32 [256][4], colour not premultiplied, alpha in
+ *                [0,1].  s = clamp((f - vmin)/(vmax - vmin), 0, 1) * 255,
+ *                linear interpolation between entries floor(s) (<= 254)
+ *                and floor(s) + 1.
+ *  vmin < vmax : transfer-function domain.
+ *  step        : ray-parameter step dt (> 0; 0 = half the model voxel).
+ *  max_samples : cap on samples per ray, >= 1.
+ *  ert_alpha   : stop after the first sample with accumulated opacity
+ *                >= ert_alpha (that sample included); > 1 disables.
+ *  ka, kd, ks, shininess : Phong with a headlight, two-sided:
+ *                c' = rgb * (ka + kd*diff) + ks * diff^shininess,
+ *                diff = |n . L|, n = g / max(|g|, g0), L = -d/|d|.
+ *  g0 > 0      : gradient-norm floor of the normal.
+ * Schedule: slab test of each ray against the model box (FP64); K =
+ * min(floor((t_far - t_near)/dt), max_samples) samples at
+ * t_k = t_near + (k + 1/2) dt, x_k = o + t_k d (FP64, unfused).
+ * Compositing (front to back, premultiplied): C += (1 - A) * alpha * c',
+ * A += (1 - A) * alpha, in FP32 with each operation rounded separately.   */
+typedef struct {
+  const float* tf_rgba;
+  float vmin, vmax;
+  double step;
+  int32_t max_samples;
+  float ert_alpha;
+  float ka, kd, ks, g0;
+  int32_t shininess;
+} mfa_render_params;
+
+/* Optional debug outputs of a render (device memory, NULL = not wanted).
+ *  nsamp        : int32 [h][w][2] = (K scheduled samples, samples used).
+ *  alpha        : FP32 [h][w][alpha_stride]: per-sample opacity after the
+ *                 transfer function, for samples 0..used-1 (rest untouched).
+ *  alpha_stride : >= max_samples when alpha is given.                      */
+typedef struct {
+  int32_t* nsamp;
+  float* alpha;
+  int32_t alpha_stride;
+} mfa_render_debug;
+
+/* Ray-casts the model (MFA-VV, Sec. IV-A4) into a w x h image.
+ *  rgba : device FP32 [h][w][4] = (C_r, C_g, C_b, A), premultiplied, no
+ *         background.
+ *  dbg  : NULL or debug outputs as above.
+ *  1 <= w, h <= 16384.                                                     */
+mfa_status mfa_render_frame(mfa_model model, const mfa_camera* camera, const mfa_render_params* params,
+                            int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                            void* stream);
+
+/* ------------------------------------------------------------------ host utilities */
+
+/* Host-only helpers (no device work): the storage rounding and the default
+ * knot vector the library uses, exported so they can be checked on a CPU.
+ *  mfa_quantize : n FP64 values -> stored bits of dtype (MFA_F32: uint32
+ *                 patterns, MFA_BF16 / MFA_F16: uint16 patterns).
+ *  mfa_default_knots : clamped uniform knots, n + p + 1 values.            */
+mfa_status mfa_quantize(const double* src, int64_t n, mfa_dtype dtype, void* dst);
+mfa_status mfa_default_knots(int32_t n, int32_t p, double* dst);
+
+/* Thread-local message of the last non-OK status on this thread. */
+const char* mfa_last_error(void);
+
+/* Library version string. */
+const char* mfa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFA_H */

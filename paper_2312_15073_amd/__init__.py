@@ -1,0 +1,265 @@
+"""MI355X (gfx950) MFA evaluator and ray caster: Python binding.
+
+Thin wrappers over the C ABI of include/mfa.h.  Device buffers are torch
+tensors on the GPU; work goes on torch's current stream.  Every step of the
+computation runs in the library's HIP kernels; this module only marshals
+arguments.  There is no CPU fallback: without the built library every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import MFAError  # noqa: F401
+
+__all__ = ["Model", "decode_points", "decode_grid", "render_frame", "MFAError",
+           "quantize", "default_knots", "version"]
+
+_DTYPES = {"f32": L.MFA_F32, "bf16": L.MFA_BF16, "f16": L.MFA_F16}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> C.c_void_p:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Model:
+    """A resident model (mfa_model_create).
+
+    spec: an object with attributes grid (3 ints), lo, hi (3 floats), edges
+    (3 arrays of grid[a]+1 floats), voxel, and blocks, each with degree (3
+    ints), knots (3 float64 arrays) and ctrl (float64 or float32 array of
+    shape n0 x n1 x n2).
+    """
+
+    def __init__(self, spec, storage: str = "f32"):
+        if storage not in _DTYPES:
+            raise ValueError(f"storage must be one of {sorted(_DTYPES)}")
+        lib = L.lib()
+        self.storage = storage
+        self._keep = []
+        dom = L.DomainDesc()
+        for a in range(3):
+            dom.grid[a] = int(spec.grid[a])
+            dom.lo[a] = float(spec.lo[a])
+            dom.hi[a] = float(spec.hi[a])
+            e = np.ascontiguousarray(spec.edges[a], dtype=np.float64)
+            self._keep.append(e)
+            dom.edges[a] = e.ctypes.data_as(C.POINTER(C.c_double))
+        dom.voxel = float(spec.voxel)
+        nb = len(spec.blocks)
+        descs = (L.BlockDesc * nb)()
+        for b, blk in enumerate(spec.blocks):
+            ctrl = np.asarray(blk.ctrl)
+            if ctrl.dtype == np.float32:
+                ctrl = np.ascontiguousarray(ctrl)
+                cdt = L.MFA_F32
+            else:
+                ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+                cdt = L.MFA_F64
+            self._keep.append(ctrl)
+            d = descs[b]
+            for a in range(3):
+                d.degree[a] = int(blk.degree[a])
+                d.n_ctrl[a] = int(ctrl.shape[a])
+                if blk.knots is not None and blk.knots[a] is not None:
+                    k = np.ascontiguousarray(blk.knots[a], dtype=np.float64)
+                    self._keep.append(k)
+                    d.knots[a] = k.ctypes.data_as(C.POINTER(C.c_double))
+            d.ctrl = ctrl.ctypes.data
+            d.ctrl_dtype = cdt
+        h = C.c_void_p()
+        L.check(lib.mfa_model_create(C.byref(dom), descs, nb, _DTYPES[storage], C.byref(h)))
+        self._h = h
+        self._keep = []
+        self.grid = [int(g) for g in spec.grid]
+        self.shapes = [tuple(int(s) for s in np.asarray(blk.ctrl).shape) for blk in spec.blocks]
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise RuntimeError("model destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = L.ModelInfo()
+        L.check(L.lib().mfa_model_info(self.handle, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in L.ModelInfo._fields_}
+
+    def export_ctrl(self, block: int = 0) -> np.ndarray:
+        """Stored bits of one block: uint32 (FP32) or uint16 (BF16/FP16)."""
+        shape = self.shapes[block]
+        dt = np.uint32 if self.storage == "f32" else np.uint16
+        out = np.zeros(shape, dtype=dt)
+        L.check(L.lib().mfa_model_export_ctrl(self.handle, block, out.ctypes.data, out.nbytes))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.lib().mfa_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def decode_points(model: Model, xyz, out=None, dbg: bool = False, sorted_order: bool = False,
+                  stream=None):
+    """Value and world gradient at points xyz (CUDA float32, shape (3, n)).
+
+    Returns out (n, 4) float32 = (f, df/dx, df/dy, df/dz) and, if dbg, an
+    int32 (n, 4) tensor of (span0, span1, span2, block).
+    """
+    torch = _torch()
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape (3, n)")
+    n = int(xyz.shape[1])
+    px = _dev_ptr(xyz, torch.float32, name="xyz")
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=xyz.device)
+    po = _dev_ptr(out, torch.float32, (n, 4), "out")
+    d = None
+    pd = C.c_void_p()
+    if dbg:
+        d = torch.empty((n, 4), dtype=torch.int32, device=xyz.device)
+        pd = C.c_void_p(d.data_ptr())
+    flags = L.MFA_DECODE_SORTED if sorted_order else 0
+    L.check(L.lib().mfa_decode_points(model.handle, px, n, flags, po, pd, _stream_ptr(stream)))
+    return (out, d) if dbg else out
+
+
+def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False, stream=None):
+    """Value and world gradient on the tensor grid of three CUDA float64
+    parameter tables.  Returns out (r0, r1, r2, 4) and, if spans, an int32
+    tensor of the r0 + r1 + r2 per-entry spans."""
+    torch = _torch()
+    if len(axis_u) != 3:
+        raise ValueError("need three axis tables")
+    res = (C.c_int32 * 3)(*[int(t.numel()) for t in axis_u])
+    ptrs = (C.c_void_p * 3)(*[_dev_ptr(t, torch.float64, name=f"axis_u[{a}]").value
+                              for a, t in enumerate(axis_u)])
+    shape = (res[0], res[1], res[2], 4)
+    dev = axis_u[0].device
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    po = _dev_ptr(out, torch.float32, shape, "out")
+    sp = None
+    ps = C.c_void_p()
+    if spans:
+        sp = torch.empty((res[0] + res[1] + res[2],), dtype=torch.int32, device=dev)
+        ps = C.c_void_p(sp.data_ptr())
+    L.check(L.lib().mfa_decode_grid(model.handle, ptrs, res, po, ps, _stream_ptr(stream)))
+    return (out, sp) if spans else out
+
+
+def make_camera(cam: dict) -> L.Camera:
+    c = L.Camera()
+    c.kind = int(cam["kind"])
+    for a in range(3):
+        c.eye[a] = float(cam["eye"][a])
+        c.forward[a] = float(cam["forward"][a])
+        c.right[a] = float(cam["right"][a])
+        c.up[a] = float(cam["up"][a])
+    c.sx = float(cam["sx"])
+    c.sy = float(cam["sy"])
+    return c
+
+
+def make_params(params: dict, tf_dev) -> L.RenderParams:
+    torch = _torch()
+    p = L.RenderParams()
+    p.tf_rgba = _dev_ptr(tf_dev, torch.float32, (256, 4), "tf").value
+    p.vmin = float(params["vmin"])
+    p.vmax = float(params["vmax"])
+    p.step = float(params["step"])
+    p.max_samples = int(params["max_samples"])
+    p.ert_alpha = float(params["ert_alpha"])
+    p.ka, p.kd, p.ks = float(params["ka"]), float(params["kd"]), float(params["ks"])
+    p.g0 = float(params["g0"])
+    p.shininess = int(params["shininess"])
+    return p
+
+
+def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=None, out=None,
+                 nsamp: bool = False, alpha: bool = False, stream=None, device=None):
+    """Ray-casts a w x h image.  params as produced by synth.render_params
+    (tf may be given as a CUDA (256,4) float32 tensor in tf_dev).  Returns
+    rgba (h, w, 4) float32 and optional int32 (h, w, 2) sample counts and
+    float32 (h, w, max_samples) per-sample opacities."""
+    torch = _torch()
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    if tf_dev is None:
+        tf_dev = torch.as_tensor(np.ascontiguousarray(params["tf"], dtype=np.float32), device=dev)
+    cobj = make_camera(cam)
+    pobj = make_params(params, tf_dev)
+    if out is None:
+        out = torch.empty((h, w, 4), dtype=torch.float32, device=dev)
+    po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
+    dbg = None
+    extra = []
+    if nsamp or alpha:
+        dbg = L.RenderDebug()
+        if nsamp:
+            ns = torch.zeros((h, w, 2), dtype=torch.int32, device=dev)
+            dbg.nsamp = ns.data_ptr()
+            extra.append(ns)
+        if alpha:
+            ms = int(params["max_samples"])
+            al = torch.zeros((h, w, ms), dtype=torch.float32, device=dev)
+            dbg.alpha = al.data_ptr()
+            dbg.alpha_stride = ms
+            extra.append(al)
+    L.check(L.lib().mfa_render_frame(model.handle, C.byref(cobj), C.byref(pobj), int(w), int(h), po,
+                                     C.byref(dbg) if dbg is not None else None,
+                                     _stream_ptr(stream)))
+    return (out, *extra) if extra else out
+
+
+def quantize(x: np.ndarray, dtype: str) -> np.ndarray:
+    """Host-side storage rounding of the library (no device work)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(x.shape, dtype=np.uint32 if dtype == "f32" else np.uint16)
+    L.check(L.lib().mfa_quantize(x.ctypes.data, x.size, _DTYPES[dtype], out.ctypes.data))
+    return out
+
+
+def default_knots(n: int, p: int) -> np.ndarray:
+    out = np.zeros(n + p + 1)
+    L.check(L.lib().mfa_default_knots(n, p, out.ctypes.data))
+    return out
+
+
+def version() -> str:
+    return L.lib().mfa_version().decode()

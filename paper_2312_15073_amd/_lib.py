@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/mfa.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfa.so")
+
+MFA_OK, MFA_E_ARG, MFA_E_NOMEM, MFA_E_DEVICE = 0, -1, -2, -3
+MFA_E_BUDGET, MFA_E_BUSY, MFA_E_NOTFOUND, MFA_E_UNSUPPORTED = -4, -5, -6, -7
+MFA_F64, MFA_F32, MFA_BF16, MFA_F16 = 0, 1, 2, 3
+MFA_ORTHO, MFA_PERSPECTIVE = 0, 1
+MFA_DECODE_SORTED = 1
+
+STATUS_NAMES = {0: "MFA_OK", -1: "MFA_E_ARG", -2: "MFA_E_NOMEM", -3: "MFA_E_DEVICE",
+                -4: "MFA_E_BUDGET", -5: "MFA_E_BUSY", -6: "MFA_E_NOTFOUND",
+                -7: "MFA_E_UNSUPPORTED"}
+
+D3 = C.c_double * 3
+I3 = C.c_int32 * 3
+
+
+class DomainDesc(C.Structure):
+    _fields_ = [("grid", I3), ("lo", D3), ("hi", D3),
+                ("edges", C.POINTER(C.c_double) * 3), ("voxel", C.c_double)]
+
+
+class BlockDesc(C.Structure):
+    _fields_ = [("degree", I3), ("n_ctrl", I3), ("knots", C.POINTER(C.c_double) * 3),
+                ("ctrl", C.c_void_p), ("ctrl_dtype", C.c_int)]
+
+
+class ModelInfo(C.Structure):
+    _fields_ = [("device_bytes", C.c_int64), ("ctrl_bytes", C.c_int64),
+                ("n_ctrl_total", C.c_int64), ("nblocks", C.c_int32), ("degree", C.c_int32),
+                ("storage", C.c_int), ("vmin", C.c_float), ("vmax", C.c_float),
+                ("voxel", C.c_double), ("device", C.c_int32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("eye", D3), ("forward", D3), ("right", D3), ("up", D3),
+                ("sx", C.c_double), ("sy", C.c_double)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("tf_rgba", C.c_void_p), ("vmin", C.c_float), ("vmax", C.c_float),
+                ("step", C.c_double), ("max_samples", C.c_int32), ("ert_alpha", C.c_float),
+                ("ka", C.c_float), ("kd", C.c_float), ("ks", C.c_float), ("g0", C.c_float),
+                ("shininess", C.c_int32)]
+
+
+class RenderDebug(C.Structure):
+    _fields_ = [("nsamp", C.c_void_p), ("alpha", C.c_void_p), ("alpha_stride", C.c_int32)]
+
+
+# name -> (restype, argtypes); every function declared in include/mfa.h
+SIGNATURES = {
+    "mfa_model_create": (C.c_int, [C.POINTER(DomainDesc), C.POINTER(BlockDesc), C.c_int32, C.c_int,
+                                   C.POINTER(C.c_void_p)]),
+    "mfa_model_destroy": (C.c_int, [C.c_void_p]),
+    "mfa_model_info": (C.c_int, [C.c_void_p, C.POINTER(ModelInfo)]),
+    "mfa_model_export_ctrl": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "mfa_decode_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "mfa_decode_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mfa_render_frame": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
+                                   C.c_int32, C.c_int32, C.c_void_p, C.POINTER(RenderDebug),
+                                   C.c_void_p]),
+    "mfa_quantize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
+    "mfa_default_knots": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
+    "mfa_last_error": (C.c_char_p, []),
+    "mfa_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class MFAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2312_15073_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != MFA_OK:
+        raise MFAError(status, lib().mfa_last_error().decode(errors="replace"))

@@ -1,0 +1,608 @@
+// Host side of the MFA library: argument validation, the model store
+// (storage rounding, knot-span records, per-span basis polynomials, block
+// table, upload) and the C entry points that enqueue the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mfa.h"
+#include "mfa_internal.h"
+
+namespace mfa {
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
+                                int64_t n, float* out, int32_t* dbg, hipStream_t st);
+hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
+                              hipStream_t st);
+hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+                         hipStream_t st);
+}  // namespace mfa
+
+using namespace mfa;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static mfa_status fail(mfa_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+static mfa_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? MFA_E_NOMEM : MFA_E_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ storage rounding
+// FP64 -> FP32 is the C++ conversion (round to nearest even).  FP32 ->
+// BF16 keeps the top half after adding 0x7FFF plus the lowest kept bit;
+// FP32 -> FP16 rounds the significand to 11 bits with gradual underflow.
+static uint32_t f32_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+static uint16_t to_bf16(float f) {
+  const uint32_t u = f32_bits(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu))
+    return (uint16_t)((u >> 16) | 0x0040u);
+  const uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+static uint16_t to_f16(float f) {
+  const uint32_t u = f32_bits(f);
+  const uint32_t sign = (u >> 16) & 0x8000u;
+  const int32_t exp = (int32_t)((u >> 23) & 0xFF);
+  const uint32_t man = u & 0x7FFFFFu;
+  if (exp == 0xFF) return (uint16_t)(sign | 0x7C00u | (man ? 0x200u | (man >> 13) : 0u));
+  const int32_t e16 = exp - 127 + 15;
+  if (e16 >= 31) return (uint16_t)(sign | 0x7C00u);
+  uint32_t sig = exp ? (man | 0x800000u) : man;
+  int shift = e16 >= 1 ? 13 : 14 - e16;
+  if (exp == 0 || shift > 25) return (uint16_t)sign;      // below half the smallest subnormal
+  uint32_t kept = sig >> shift;
+  const uint32_t rem = sig & ((1u << shift) - 1u);
+  const uint32_t half = 1u << (shift - 1);
+  if (rem > half || (rem == half && (kept & 1u))) ++kept;
+  uint32_t mag = e16 >= 1 ? ((uint32_t)e16 << 10) + (kept - 0x400u) : kept;
+  if (mag >= 0x7C00u) mag = 0x7C00u;
+  return (uint16_t)(sign | mag);
+}
+
+static float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+static float f16_value(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+  const uint32_t exp = (h >> 10) & 0x1F, man = h & 0x3FFu;
+  float v;
+  if (exp == 0) v = std::ldexp((float)man, -24);
+  else if (exp == 31) v = man ? NAN : INFINITY;
+  else v = std::ldexp((float)(man | 0x400u), (int)exp - 25);
+  uint32_t u = f32_bits(v) | sign;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+
+static int elem_size(mfa_dtype d) { return d == MFA_F32 ? 4 : 2; }
+
+// ------------------------------------------------------------------ basis polynomials
+// Pieces of the degree-p basis functions active on span s as polynomials in
+// tau = (u - T[s]) / h: the Cox-de Boor recursion applied to polynomials,
+// with u = T[s] + h tau substituted into each linear weight (FP64), then
+// rounded to FP32.  Layout: see mat_stride().
+static std::vector<float> span_table(const double* T, int p, int s) {
+  const double ts = T[s], h = T[s + 1] - T[s];
+  std::vector<std::vector<double>> N(1, std::vector<double>(p + 1, 0.0));
+  N[0][0] = 1.0;
+  for (int q = 1; q <= p; ++q) {
+    std::vector<std::vector<double>> M(q + 1, std::vector<double>(p + 1, 0.0));
+    for (int r = 0; r <= q; ++r) {
+      const int i = s - q + r;
+      if (r >= 1) {
+        const double den = T[i + q] - T[i];
+        if (den != 0.0) {
+          const double a0 = (ts - T[i]) / den, a1 = h / den;   // (u - T_i)/den
+          for (int m = 0; m <= p; ++m) {
+            M[r][m] += a0 * N[r - 1][m];
+            if (m + 1 <= p) M[r][m + 1] += a1 * N[r - 1][m];
+          }
+        }
+      }
+      if (r <= q - 1) {
+        const double den = T[i + q + 1] - T[i + 1];
+        if (den != 0.0) {
+          const double b0 = (T[i + q + 1] - ts) / den, b1 = -h / den;  // (T_{i+q+1} - u)/den
+          for (int m = 0; m <= p; ++m) {
+            M[r][m] += b0 * N[r][m];
+            if (m + 1 <= p) M[r][m + 1] += b1 * N[r][m];
+          }
+        }
+      }
+    }
+    N.swap(M);
+  }
+  std::vector<float> out(mat_stride(p), 0.f);
+  for (int r = 0; r <= p; ++r)
+    for (int m = 0; m <= p; ++m) out[r * (p + 1) + m] = (float)N[r][m];
+  for (int r = 0; r <= p; ++r)
+    for (int m = 0; m < p; ++m) out[(p + 1) * (p + 1) + r * p + m] = (float)((m + 1) * N[r][m + 1]);
+  return out;
+}
+
+// ------------------------------------------------------------------ model
+struct mfa_model_s {
+  int device = 0;
+  int degree = 0;
+  mfa_dtype storage = MFA_F32;
+  int grid[3] = {1, 1, 1};
+  int nblocks = 1;
+  double voxel = 0.0;
+  std::vector<int32_t> n;       // 3 per block
+  std::vector<int64_t> coff;    // element offset per block
+  std::vector<int32_t> rs1;     // row stride per block
+  int64_t n_ctrl_total = 0;
+  float vmin = 0.f, vmax = 0.f;
+  void* d_ctrl = nullptr;
+  int64_t ctrl_bytes = 0;
+  SpanRec* d_rec = nullptr;
+  float* d_mats = nullptr;
+  DevBlock* d_blocks = nullptr;
+  double* d_edges = nullptr;
+  int64_t device_bytes = 0;
+  DevModel dm{};
+};
+
+static void free_model(mfa_model m) {
+  if (!m) return;
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete m;
+}
+
+static bool is_fin(double v) { return std::isfinite(v); }
+
+static mfa_status check_knots(const double* T, int n, int p, int blk, int axis) {
+  for (int i = 0; i < n + p + 1; ++i)
+    if (!is_fin(T[i])) return fail(MFA_E_ARG, "block %d axis %d: knot %d not finite", blk, axis, i);
+  for (int i = 0; i + 1 < n + p + 1; ++i)
+    if (T[i + 1] < T[i]) return fail(MFA_E_ARG, "block %d axis %d: knots decrease at %d", blk, axis, i);
+  for (int i = 0; i <= p; ++i)
+    if (T[i] != 0.0 || T[n + i] != 1.0)
+      return fail(MFA_E_ARG, "block %d axis %d: knots must be clamped to [0,1] (p+1 end knots)", blk,
+                  axis);
+  if (!(T[n - 1] < 1.0))
+    return fail(MFA_E_ARG, "block %d axis %d: last span [T[n-1], T[n]] is empty", blk, axis);
+  return MFA_OK;
+}
+
+static void default_knots(int n, int p, double* T) {
+  for (int i = 0; i <= p; ++i) {
+    T[i] = 0.0;
+    T[n + i] = 1.0;
+  }
+  const double nsp = (double)(n - p);
+  for (int j = 1; j < n - p; ++j) T[p + j] = (double)j / nsp;
+}
+
+template <class Tp>
+static mfa_status upload(Tp** dst, const void* src, size_t bytes, mfa_model m, const char* what) {
+  hipError_t e = hipMalloc((void**)dst, bytes ? bytes : 16);
+  if (e != hipSuccess) return hip_fail(e, what);
+  m->device_bytes += (int64_t)(bytes ? bytes : 16);
+  if (bytes) {
+    e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+  }
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_block_desc* blocks,
+                                       int32_t nblocks, mfa_dtype storage, mfa_model* out) {
+  if (!dom || !blocks || !out) return fail(MFA_E_ARG, "null argument");
+  *out = nullptr;
+  if (storage != MFA_F32 && storage != MFA_BF16 && storage != MFA_F16)
+    return fail(MFA_E_ARG, "storage must be MFA_F32, MFA_BF16 or MFA_F16");
+  int64_t nb = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (dom->grid[a] < 1 || dom->grid[a] > 4096) return fail(MFA_E_ARG, "grid[%d] out of range", a);
+    if (!is_fin(dom->lo[a]) || !is_fin(dom->hi[a]) || !(dom->lo[a] < dom->hi[a]))
+      return fail(MFA_E_ARG, "domain lo/hi invalid on axis %d", a);
+    nb *= dom->grid[a];
+  }
+  if (!(dom->voxel > 0.0) || !is_fin(dom->voxel)) return fail(MFA_E_ARG, "voxel must be > 0");
+  if (nblocks != nb) return fail(MFA_E_ARG, "nblocks %d != grid product %lld", nblocks, (long long)nb);
+  if (nb > (1 << 20)) return fail(MFA_E_UNSUPPORTED, "too many blocks");
+
+  // edges
+  std::vector<double> edges[3];
+  for (int a = 0; a < 3; ++a) {
+    const int G = dom->grid[a];
+    edges[a].resize(G + 1);
+    if (dom->edges[a]) {
+      for (int i = 0; i <= G; ++i) edges[a][i] = dom->edges[a][i];
+      if (edges[a][0] != dom->lo[a] || edges[a][G] != dom->hi[a])
+        return fail(MFA_E_ARG, "edges[%d] must start at lo and end at hi", a);
+      for (int i = 0; i < G; ++i)
+        if (!(edges[a][i] < edges[a][i + 1]) || !is_fin(edges[a][i + 1]))
+          return fail(MFA_E_ARG, "edges[%d] must increase strictly", a);
+    } else {
+      for (int i = 0; i <= G; ++i)
+        edges[a][i] = dom->lo[a] + (dom->hi[a] - dom->lo[a]) * ((double)i / (double)G);
+      edges[a][0] = dom->lo[a];
+      edges[a][G] = dom->hi[a];
+    }
+  }
+
+  const int p = blocks[0].degree[0];
+  if (p < 1 || p > kMaxDegree) return fail(MFA_E_UNSUPPORTED, "degree %d not in 1..%d", p, kMaxDegree);
+  if (p > 5) return fail(MFA_E_UNSUPPORTED, "degree %d: kernels are built for degrees 1..5", p);
+  for (int64_t b = 0; b < nb; ++b) {
+    const mfa_block_desc& B = blocks[b];
+    for (int a = 0; a < 3; ++a) {
+      if (B.degree[a] != p)
+        return fail(MFA_E_UNSUPPORTED, "block %lld axis %d: all axes and blocks must share degree %d",
+                    (long long)b, a, p);
+      if (B.n_ctrl[a] < p + 1 || B.n_ctrl[a] > (1 << 16))
+        return fail(MFA_E_ARG, "block %lld axis %d: n_ctrl %d not in [p+1, 65536]", (long long)b, a,
+                    B.n_ctrl[a]);
+    }
+    if (!B.ctrl) return fail(MFA_E_ARG, "block %lld: ctrl is null", (long long)b);
+    if (B.ctrl_dtype != MFA_F64 && B.ctrl_dtype != MFA_F32)
+      return fail(MFA_E_ARG, "block %lld: ctrl_dtype must be MFA_F64 or MFA_F32", (long long)b);
+  }
+
+  int current = 0;
+  hipError_t he = hipGetDevice(&current);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+
+  mfa_model m = new mfa_model_s();
+  m->device = current;
+  m->degree = p;
+  m->storage = storage;
+  m->nblocks = (int)nb;
+  m->voxel = dom->voxel;
+  for (int a = 0; a < 3; ++a) m->grid[a] = dom->grid[a];
+
+  const int es = elem_size(storage);
+  std::vector<DevBlock> dblk(nb);
+  std::vector<SpanRec> recs;
+  std::vector<float> mats;
+  std::map<std::vector<float>, int> mat_ids;
+  int64_t off = 0;
+  m->n.resize(3 * nb);
+  m->coff.resize(nb);
+  m->rs1.resize(nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    const mfa_block_desc& B = blocks[b];
+    const int b0 = (int)(b / ((int64_t)dom->grid[1] * dom->grid[2]));
+    const int b1 = (int)((b / dom->grid[2]) % dom->grid[1]);
+    const int b2 = (int)(b % dom->grid[2]);
+    const int bi[3] = {b0, b1, b2};
+    DevBlock& D = dblk[b];
+    for (int a = 0; a < 3; ++a) {
+      D.lo[a] = edges[a][bi[a]];
+      D.inv_ext[a] = 1.0 / (edges[a][bi[a] + 1] - edges[a][bi[a]]);
+      D.n[a] = B.n_ctrl[a];
+      D.nsp[a] = B.n_ctrl[a] - p;
+      m->n[3 * b + a] = B.n_ctrl[a];
+    }
+    D.rs1 = (es == 2) ? (B.n_ctrl[2] + (B.n_ctrl[2] & 1)) : B.n_ctrl[2];
+    D.ctrl_off = off;
+    m->coff[b] = off;
+    m->rs1[b] = D.rs1;
+    off += (int64_t)B.n_ctrl[0] * B.n_ctrl[1] * D.rs1;
+    m->n_ctrl_total += (int64_t)B.n_ctrl[0] * B.n_ctrl[1] * B.n_ctrl[2];
+    for (int a = 0; a < 3; ++a) {
+      const int n = B.n_ctrl[a];
+      std::vector<double> T(n + p + 1);
+      if (B.knots[a]) {
+        std::memcpy(T.data(), B.knots[a], sizeof(double) * (n + p + 1));
+        mfa_status st = check_knots(T.data(), n, p, (int)b, a);
+        if (st != MFA_OK) { free_model(m); return st; }
+      } else {
+        default_knots(n, p, T.data());
+      }
+      D.rec_off[a] = (int32_t)recs.size();
+      for (int j = 0; j < n - p; ++j) {
+        const int s = p + j;
+        SpanRec r;
+        r.t = T[s];
+        r.t_next = T[s + 1];
+        r.inv_h = (r.t_next > r.t) ? 1.0 / (r.t_next - r.t) : 0.0;
+        r.dscale = (float)(r.inv_h * D.inv_ext[a]);
+        std::vector<float> tab = (r.t_next > r.t) ? span_table(T.data(), p, s)
+                                                  : std::vector<float>(mat_stride(p), 0.f);
+        auto it = mat_ids.find(tab);
+        if (it == mat_ids.end()) {
+          const int id = (int)mat_ids.size();
+          mat_ids.emplace(tab, id);
+          mats.insert(mats.end(), tab.begin(), tab.end());
+          r.mat = id;
+        } else {
+          r.mat = it->second;
+        }
+        recs.push_back(r);
+      }
+    }
+  }
+  if (recs.size() > (size_t)INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "too many spans"); }
+  const int64_t pool_bytes = off * es + 64;       // tail pad: 16-bit rows read one word ahead
+  if (pool_bytes > 0xFFFFFFFFll) {
+    free_model(m);
+    return fail(MFA_E_UNSUPPORTED, "stored control points exceed 4 GiB per model");
+  }
+
+  // storage rounding
+  std::vector<uint8_t> pool((size_t)pool_bytes, 0);
+  float vmin = INFINITY, vmax = -INFINITY;
+  for (int64_t b = 0; b < nb; ++b) {
+    const mfa_block_desc& B = blocks[b];
+    const int n0 = B.n_ctrl[0], n1 = B.n_ctrl[1], n2 = B.n_ctrl[2];
+    for (int64_t i = 0; i < (int64_t)n0 * n1; ++i) {
+      for (int k = 0; k < n2; ++k) {
+        const int64_t src = i * n2 + k;
+        const double v64 = B.ctrl_dtype == MFA_F64 ? ((const double*)B.ctrl)[src]
+                                                   : (double)((const float*)B.ctrl)[src];
+        if (!is_fin(v64)) {
+          free_model(m);
+          return fail(MFA_E_ARG, "block %lld: control point %lld not finite", (long long)b,
+                      (long long)src);
+        }
+        const float v32 = (float)v64;
+        const int64_t dst = dblk[b].ctrl_off + i * dblk[b].rs1 + k;
+        float stored = v32;
+        if (storage == MFA_F32) {
+          std::memcpy(&pool[dst * 4], &v32, 4);
+        } else if (storage == MFA_BF16) {
+          const uint16_t h = to_bf16(v32);
+          std::memcpy(&pool[dst * 2], &h, 2);
+          stored = bf16_value(h);
+        } else {
+          const uint16_t h = to_f16(v32);
+          if ((h & 0x7C00u) == 0x7C00u) {
+            free_model(m);
+            return fail(MFA_E_ARG, "block %lld: control point %g overflows FP16", (long long)b, v64);
+          }
+          std::memcpy(&pool[dst * 2], &h, 2);
+          stored = f16_value(h);
+        }
+        vmin = std::fmin(vmin, stored);
+        vmax = std::fmax(vmax, stored);
+      }
+    }
+  }
+  m->vmin = vmin;
+  m->vmax = vmax;
+
+  std::vector<double> edge_pool;
+  int edge_off[3];
+  for (int a = 0; a < 3; ++a) {
+    edge_off[a] = (int)edge_pool.size();
+    edge_pool.insert(edge_pool.end(), edges[a].begin(), edges[a].end());
+  }
+
+  mfa_status st;
+  if ((st = upload(&m->d_ctrl, pool.data(), pool.size(), m, "ctrl upload")) != MFA_OK ||
+      (st = upload(&m->d_rec, recs.data(), recs.size() * sizeof(SpanRec), m, "span upload")) != MFA_OK ||
+      (st = upload(&m->d_mats, mats.data(), mats.size() * sizeof(float), m, "basis upload")) != MFA_OK ||
+      (st = upload(&m->d_blocks, dblk.data(), dblk.size() * sizeof(DevBlock), m, "block upload")) != MFA_OK ||
+      (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK) {
+    free_model(m);
+    return st;
+  }
+  m->ctrl_bytes = pool_bytes;
+
+  DevModel& dm = m->dm;
+  dm.ctrl = m->d_ctrl;
+  dm.rec = m->d_rec;
+  dm.mats = m->d_mats;
+  dm.blocks = m->d_blocks;
+  dm.edges = m->d_edges;
+  dm.ctrl_bytes = pool_bytes;
+  for (int a = 0; a < 3; ++a) {
+    dm.edge_off[a] = edge_off[a];
+    dm.grid[a] = dom->grid[a];
+    dm.box_lo[a] = dom->lo[a];
+    dm.box_hi[a] = dom->hi[a];
+    dm.edge_scale[a] = (double)dom->grid[a] / (dom->hi[a] - dom->lo[a]);
+  }
+  dm.nblocks = (int)nb;
+  dm.mat_stride = mat_stride(p);
+  dm.b0 = dblk[0];
+  *out = m;
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_model_destroy(mfa_model m) {
+  free_model(m);
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_model_info(mfa_model m, mfa_model_info_t* info) {
+  if (!m || !info) return fail(MFA_E_ARG, "null argument");
+  info->device_bytes = m->device_bytes;
+  info->ctrl_bytes = m->ctrl_bytes;
+  info->n_ctrl_total = m->n_ctrl_total;
+  info->nblocks = m->nblocks;
+  info->degree = m->degree;
+  info->storage = m->storage;
+  info->vmin = m->vmin;
+  info->vmax = m->vmax;
+  info->voxel = m->voxel;
+  info->device = m->device;
+  return MFA_OK;
+}
+
+static mfa_status check_device(mfa_model m) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != m->device)
+    return fail(MFA_E_ARG, "current device %d is not the model's device %d", cur, m->device);
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_model_export_ctrl(mfa_model m, int32_t block, void* dst, int64_t dst_bytes) {
+  if (!m || !dst) return fail(MFA_E_ARG, "null argument");
+  if (block < 0 || block >= m->nblocks) return fail(MFA_E_ARG, "block %d out of range", block);
+  const int es = elem_size(m->storage);
+  const int n0 = m->n[3 * block], n1 = m->n[3 * block + 1], n2 = m->n[3 * block + 2];
+  const int64_t need = (int64_t)n0 * n1 * n2 * es;
+  if (dst_bytes < need) return fail(MFA_E_ARG, "dst_bytes %lld < %lld", (long long)dst_bytes, (long long)need);
+  mfa_status st = check_device(m);
+  if (st != MFA_OK) return st;
+  const int rs = m->rs1[block];
+  std::vector<uint8_t> tmp((size_t)n0 * n1 * rs * es);
+  hipError_t e = hipMemcpy(tmp.data(), (const uint8_t*)m->d_ctrl + m->coff[block] * es, tmp.size(),
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "export copy");
+  for (int64_t i = 0; i < (int64_t)n0 * n1; ++i)
+    std::memcpy((uint8_t*)dst + i * n2 * es, tmp.data() + i * rs * es, (size_t)n2 * es);
+  return MFA_OK;
+}
+
+// ------------------------------------------------------------------ decode
+static Storage storage_of(mfa_model m) {
+  return m->storage == MFA_F32 ? Storage::F32 : m->storage == MFA_BF16 ? Storage::BF16 : Storage::F16;
+}
+
+extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n, uint32_t flags,
+                                        float* out, int32_t* dbg, void* stream) {
+  if (!m) return fail(MFA_E_ARG, "null model");
+  if (n < 0 || n >= (1ll << 31)) return fail(MFA_E_ARG, "n = %lld out of range", (long long)n);
+  if (flags & ~MFA_DECODE_SORTED) return fail(MFA_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & MFA_DECODE_SORTED) return fail(MFA_E_UNSUPPORTED, "sorted decode not built yet");
+  if (n == 0) return MFA_OK;
+  if (!xyz || !out) return fail(MFA_E_ARG, "null xyz/out");
+  mfa_status st = check_device(m);
+  if (st != MFA_OK) return st;
+  hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), m->nblocks > 1, xyz, n, out,
+                                      dbg, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_points launch");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3], const int32_t res[3],
+                                      float* out, int32_t* spans, void* stream) {
+  if (!m || !axis_u || !res || !out) return fail(MFA_E_ARG, "null argument");
+  if (m->nblocks != 1) return fail(MFA_E_ARG, "grid decode needs a single-block model");
+  int64_t total = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (!axis_u[a]) return fail(MFA_E_ARG, "axis_u[%d] is null", a);
+    if (res[a] < 1) return fail(MFA_E_ARG, "res[%d] = %d < 1", a, res[a]);
+    total *= res[a];
+  }
+  if (res[1] > 4 * 65535 || res[0] > 64 * 65535) return fail(MFA_E_ARG, "res too large for the launch");
+  if (total >= (1ll << 40)) return fail(MFA_E_ARG, "grid too large");
+  mfa_status st = check_device(m);
+  if (st != MFA_OK) return st;
+  GridArgs ga{};
+  for (int a = 0; a < 3; ++a) {
+    ga.axis[a] = axis_u[a];
+    ga.res[a] = res[a];
+  }
+  ga.out = out;
+  ga.spans = spans;
+  hipError_t e = launch_decode_grid(m->dm, m->degree, storage_of(m), ga, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_grid launch");
+  return MFA_OK;
+}
+
+// ------------------------------------------------------------------ render
+extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
+                                       int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                                       void* stream) {
+  if (!m || !cam || !rp || !rgba) return fail(MFA_E_ARG, "null argument");
+  if (w < 1 || h < 1 || w > 16384 || h > 16384) return fail(MFA_E_ARG, "image %dx%d out of range", w, h);
+  if (cam->kind != MFA_ORTHO && cam->kind != MFA_PERSPECTIVE) return fail(MFA_E_ARG, "camera kind");
+  for (int a = 0; a < 3; ++a)
+    if (!is_fin(cam->eye[a]) || !is_fin(cam->forward[a]) || !is_fin(cam->right[a]) || !is_fin(cam->up[a]))
+      return fail(MFA_E_ARG, "camera vectors must be finite");
+  if (!is_fin(cam->sx) || !is_fin(cam->sy)) return fail(MFA_E_ARG, "camera scales must be finite");
+  if (!rp->tf_rgba) return fail(MFA_E_ARG, "tf_rgba is null");
+  if (!(rp->vmin < rp->vmax) || !std::isfinite(rp->vmin) || !std::isfinite(rp->vmax))
+    return fail(MFA_E_ARG, "need finite vmin < vmax");
+  const double step = rp->step == 0.0 ? 0.5 * m->voxel : rp->step;
+  if (!(step > 0.0) || !is_fin(step)) return fail(MFA_E_ARG, "step must be > 0");
+  if (rp->max_samples < 1) return fail(MFA_E_ARG, "max_samples must be >= 1");
+  if (!(rp->g0 > 0.f) || !std::isfinite(rp->g0)) return fail(MFA_E_ARG, "g0 must be > 0");
+  if (rp->shininess < 0 || rp->shininess > 1024) return fail(MFA_E_ARG, "shininess out of range");
+  if (!std::isfinite(rp->ka) || !std::isfinite(rp->kd) || !std::isfinite(rp->ks) ||
+      std::isnan(rp->ert_alpha))
+    return fail(MFA_E_ARG, "shading parameters must be finite");
+  if (dbg && dbg->alpha && dbg->alpha_stride < rp->max_samples)
+    return fail(MFA_E_ARG, "alpha_stride %d < max_samples %d", dbg->alpha_stride, rp->max_samples);
+  mfa_status st = check_device(m);
+  if (st != MFA_OK) return st;
+  RenderArgs r{};
+  r.tf = rp->tf_rgba;
+  r.rgba = rgba;
+  r.nsamp = dbg ? dbg->nsamp : nullptr;
+  r.alpha = dbg ? dbg->alpha : nullptr;
+  r.alpha_stride = dbg ? dbg->alpha_stride : 0;
+  r.w = w;
+  r.h = h;
+  r.kind = cam->kind;
+  r.max_samples = rp->max_samples;
+  r.shininess = rp->shininess;
+  r.vmin = rp->vmin;
+  r.inv_range = (float)(1.0 / ((double)rp->vmax - (double)rp->vmin));
+  r.ert_alpha = rp->ert_alpha;
+  r.ka = rp->ka;
+  r.kd = rp->kd;
+  r.ks = rp->ks;
+  r.g0 = rp->g0;
+  for (int a = 0; a < 3; ++a) {
+    r.eye[a] = cam->eye[a];
+    r.fwd[a] = cam->forward[a];
+    r.right[a] = cam->right[a];
+    r.up[a] = cam->up[a];
+  }
+  r.sx = cam->sx;
+  r.sy = cam->sy;
+  r.step = step;
+  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  return MFA_OK;
+}
+
+// ------------------------------------------------------------------ host utilities
+extern "C" mfa_status mfa_quantize(const double* src, int64_t n, mfa_dtype dtype, void* dst) {
+  if (n < 0 || (n > 0 && (!src || !dst))) return fail(MFA_E_ARG, "bad buffers");
+  if (dtype != MFA_F32 && dtype != MFA_BF16 && dtype != MFA_F16) return fail(MFA_E_ARG, "dtype");
+  for (int64_t i = 0; i < n; ++i) {
+    const float v = (float)src[i];
+    if (dtype == MFA_F32) ((uint32_t*)dst)[i] = f32_bits(v);
+    else if (dtype == MFA_BF16) ((uint16_t*)dst)[i] = to_bf16(v);
+    else ((uint16_t*)dst)[i] = to_f16(v);
+  }
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_default_knots(int32_t n, int32_t p, double* dst) {
+  if (!dst || p < 1 || p > kMaxDegree || n < p + 1) return fail(MFA_E_ARG, "bad n/p");
+  default_knots(n, p, dst);
+  return MFA_OK;
+}
+
+extern "C" const char* mfa_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* mfa_version(void) { return "mfa-gfx950 0.1"; }

@@ -1,0 +1,96 @@
+// Internal layouts shared by the host library and the gfx950 kernels.
+//
+// A model lives in device memory as a handful of pools:
+//   ctrl   : stored control points of all blocks, C order [n0][n1][n2] per
+//            block, blocks back to back (storage type FP32 / BF16 / FP16);
+//   rec    : one SpanRec per (block, axis, span), the FP64 data of the span
+//            rule and of the local coordinate plus the FP32 chain-rule scale;
+//   mats   : deduplicated FP32 tables of the polynomial pieces of the basis
+//            functions on a span (value and d/dtau coefficients);
+//   blocks : one DevBlock per block;
+//   edges  : FP64 block edges per axis.
+// Everything the kernels need about a single-block model (the common case)
+// is also copied into the kernel argument (DevModel::b0) so it is uniform.
+#pragma once
+
+#include <stdint.h>
+
+namespace mfa {
+
+constexpr int kMaxDegree = 7;
+
+// One knot span [t, t_next) of one axis of one block (span index s = p + j).
+struct SpanRec {
+  double t;        // T[s]
+  double t_next;   // T[s+1]
+  double inv_h;    // 1 / (T[s+1] - T[s])  (FP64 division on the host)
+  float dscale;    // (float)(inv_h * inv_ext): d/dtau -> d/dworld
+  int32_t mat;     // index of the basis table in the matrix pool
+};
+static_assert(sizeof(SpanRec) == 32, "SpanRec layout");
+
+struct DevBlock {
+  double lo[3];         // world box of the block
+  double inv_ext[3];    // 1 / (hi - lo), FP64 division on the host
+  int64_t ctrl_off;     // element offset of the block's control points
+  int32_t n[3];         // control points per axis
+  int32_t nsp[3];       // spans per axis = n - p
+  int32_t rec_off[3];   // index of the block's span 0 record per axis
+  int32_t rs1;          // row stride along axis 1 in elements (n2, padded to
+                        // even for 16-bit storage so rows pair into dwords)
+};
+static_assert(sizeof(DevBlock) == 96, "DevBlock layout");
+
+struct DevModel {
+  const void* ctrl;
+  const SpanRec* rec;
+  const float* mats;
+  const DevBlock* blocks;
+  const double* edges;   // axis 0 (grid0+1 values), then axis 1, then axis 2
+  int64_t ctrl_bytes;    // size of the ctrl pool (buffer range)
+  int32_t edge_off[3];
+  int32_t grid[3];
+  int32_t nblocks;
+  int32_t mat_stride;    // floats per basis table
+  double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
+  double box_lo[3];
+  double box_hi[3];
+  DevBlock b0;           // block 0 (the only block of single-block models)
+};
+
+// Storage element types.
+enum class Storage : int { F32 = 1, BF16 = 2, F16 = 3 };
+
+// Basis table of degree p for one span: value coefficients c[r][m]
+// (function r = 0..p, power m = 0..p, ascending) followed by derivative
+// coefficients e[r][m] = (m+1) c[r][m+1] (m = 0..p-1); padded to 4 floats.
+inline constexpr int mat_stride(int p) {
+  return (((p + 1) * (p + 1) + (p + 1) * p) + 3) / 4 * 4;
+}
+
+struct GridArgs {
+  const double* axis[3];
+  int32_t res[3];
+  int32_t ta;            // grid entries along axis 0 per wave
+  float* out;
+  int32_t* spans;
+};
+
+struct RenderArgs {
+  const float* tf;
+  float* rgba;
+  int32_t* nsamp;
+  float* alpha;
+  int32_t alpha_stride;
+  int32_t w, h;
+  int32_t kind;
+  int32_t max_samples;
+  int32_t shininess;
+  float vmin, inv_range;   // TF domain: s = (f - vmin) * inv_range * 255
+  float ert_alpha;
+  float ka, kd, ks, g0;
+  double eye[3], fwd[3], right[3], up[3];
+  double sx, sy, step;
+};
+
+}  // namespace mfa

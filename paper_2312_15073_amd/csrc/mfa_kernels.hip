@@ -1,0 +1,607 @@
+// gfx950 kernels of the MFA evaluator and ray caster.
+//
+// Per sample (paper Sec. III-A model, Sec. IV-A4 query + ray casting):
+//   world x (FP64) -> owning block -> parameter u (FP64) -> knot span (FP64
+//   compares against the stored knots) -> local coordinate tau (FP64, then
+//   FP32) -> basis values and d/dtau from the span's polynomial table (FP32)
+//   -> sum-factorised (p+1)^3 contraction for value and three partials
+//   (FP32 accumulate; control points FP32 / BF16 / FP16) -> chain rule.
+// The renderer adds transfer function, headlight Phong, front-to-back "over"
+// (Sec. IV-A5) and early termination tested once per step on the wave.
+//
+// Exact FP64 steps are written with contraction off so they round exactly
+// like the reference definitions (one rounding per operation).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "mfa_internal.h"
+
+namespace mfa {
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ memory
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int64_t bytes) {
+  const int64_t cap = 0xFFFFFFFFll;
+  const uint32_t nrec = (uint32_t)(bytes < cap ? bytes : cap);
+  // word 3 = 0x00020000: raw (untyped) buffer on gfx9-class targets
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nrec, 0x00020000);
+}
+
+// Loads N consecutive 32-bit words at byte offset vo (per lane) + so (uniform).
+template <int N>
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so,
+                                           uint32_t* w) {
+  if constexpr (N >= 4) {
+    u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0);
+    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+    load_words<N - 4>(rs, vo + 16, so, w + 4);
+  } else if constexpr (N == 3) {
+    u32x3 q = __builtin_amdgcn_raw_buffer_load_b96(rs, vo, so, 0);
+    w[0] = q.x; w[1] = q.y; w[2] = q.z;
+  } else if constexpr (N == 2) {
+    u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0);
+    w[0] = q.x; w[1] = q.y;
+  } else if constexpr (N == 1) {
+    w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
+  }
+}
+
+// One row of P+1 control points along axis 2 starting at element e (per
+// lane) + es (uniform), converted to FP32.
+template <int P, Storage S>
+struct Row;
+
+template <int P>
+struct Row<P, Storage::F32> {
+  static constexpr int kElem = 4;
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
+                                              float (&v)[P + 1]) {
+    uint32_t w[P + 1];
+    load_words<P + 1>(rs, e * 4u, es * 4u, w);
+#pragma unroll
+    for (int k = 0; k <= P; ++k) v[k] = __uint_as_float(w[k]);
+  }
+};
+
+// 16-bit rows: load the dword-aligned window holding elements e..e+P, then
+// funnel-shift by one half-word when e is odd.
+template <int P, Storage S>
+__device__ __forceinline__ void load_halves(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
+                                            uint32_t (&h)[(P + 2) / 2]) {
+  constexpr int kOut = (P + 2) / 2;       // dwords holding P+1 halves
+  constexpr int kIn = kOut + 1;
+  uint32_t w[kIn];
+  load_words<kIn>(rs, (e & ~1u) * 2u, es * 2u, w);
+  const uint32_t sh = (e & 1u) * 16u;
+#pragma unroll
+  for (int q = 0; q < kOut; ++q) h[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
+}
+
+template <int P>
+struct Row<P, Storage::BF16> {
+  static constexpr int kElem = 2;
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
+                                              float (&v)[P + 1]) {
+    uint32_t h[(P + 2) / 2];
+    load_halves<P, Storage::BF16>(rs, e, es, h);
+#pragma unroll
+    for (int k = 0; k <= P; ++k)
+      v[k] = (k & 1) ? __uint_as_float(h[k >> 1] & 0xFFFF0000u) : __uint_as_float(h[k >> 1] << 16);
+  }
+};
+
+template <int P>
+struct Row<P, Storage::F16> {
+  static constexpr int kElem = 2;
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
+                                              float (&v)[P + 1]) {
+    uint32_t h[(P + 2) / 2];
+    load_halves<P, Storage::F16>(rs, e, es, h);
+#pragma unroll
+    for (int k = 0; k <= P; ++k) {
+      const unsigned short bits = (k & 1) ? (unsigned short)(h[k >> 1] >> 16)
+                                          : (unsigned short)(h[k >> 1] & 0xFFFFu);
+      v[k] = __half2float(__ushort_as_half(bits));
+    }
+  }
+};
+
+// ------------------------------------------------------------------ FP64 decisions
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+  return fmin(fmax(v, lo), hi);
+}
+
+// Span rule s = max{ i in [p, n-1] : T[i] <= u } over the span records
+// R[0..nsp-1] of one axis (record j describes span s = p + j).  The guess
+// floor(u * nsp) is corrected by exact comparisons with the stored knots.
+__device__ __forceinline__ int locate_span(const SpanRec* __restrict__ R, int nsp, double u,
+                                           SpanRec& rec) {
+  int j = (int)(u * (double)nsp);
+  j = j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
+  rec = R[j];
+  while (j < nsp - 1 && rec.t_next <= u) { ++j; rec = R[j]; }
+  while (j > 0 && rec.t > u) { --j; rec = R[j]; }
+  return j;
+}
+
+// Local coordinate of u in its span, FP64 then rounded once to FP32.
+__device__ __forceinline__ float local_tau(const SpanRec& rec, double u) {
+#pragma clang fp contract(off)
+  return (float)((u - rec.t) * rec.inv_h);
+}
+
+// Parameter of a world coordinate in its block (clamped box coordinate).
+__device__ __forceinline__ double param_of(double xc, double lo, double inv_ext) {
+#pragma clang fp contract(off)
+  return clampd((xc - lo) * inv_ext, 0.0, 1.0);
+}
+
+// ------------------------------------------------------------------ basis
+// Values N[r] and d/dtau D[r] (r = 0..P) of the basis functions active on a
+// span, by Horner on the span's polynomial table M (see mat_stride()).
+template <int P>
+__device__ __forceinline__ void basis(const float* __restrict__ M, float tau, float (&N)[P + 1],
+                                      float (&D)[P + 1]) {
+  constexpr int kWords = mat_stride(P);
+  float c[kWords];
+#pragma unroll
+  for (int q = 0; q < kWords / 4; ++q) {
+    const float4 v = reinterpret_cast<const float4*>(M)[q];
+    c[4 * q + 0] = v.x;
+    c[4 * q + 1] = v.y;
+    c[4 * q + 2] = v.z;
+    c[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    float v = c[r * (P + 1) + P];
+#pragma unroll
+    for (int m = P - 1; m >= 0; --m) v = fmaf(v, tau, c[r * (P + 1) + m]);
+    N[r] = v;
+    const float* e = c + (P + 1) * (P + 1) + r * P;
+    float d = e[P - 1];
+#pragma unroll
+    for (int m = P - 2; m >= 0; --m) d = fmaf(d, tau, e[m]);
+    D[r] = d;
+  }
+}
+
+// ------------------------------------------------------------------ contraction
+// f = sum_ijk Nx_i Ny_j Nz_k P_ijk and the three partials with one factor
+// replaced by its derivative, summed axis 2 first, then axis 1, then axis 0.
+// e0: element index of P[i0][j0][k0] (per lane); rows at + i*s0 + j*s1.
+// UNIFORM_STRIDES: s0, s1 are wave-uniform and go into the scalar offset.
+template <int P, Storage S, bool UNIFORM_STRIDES>
+__device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0, uint32_t s0,
+                                         uint32_t s1, const float (&Nx)[P + 1],
+                                         const float (&Dx)[P + 1], const float (&Ny)[P + 1],
+                                         const float (&Dy)[P + 1], const float (&Nz)[P + 1],
+                                         const float (&Dz)[P + 1], float& f, float& fx, float& fy,
+                                         float& fz) {
+  f = fx = fy = fz = 0.f;
+#pragma unroll
+  for (int i = 0; i <= P; ++i) {
+    float y = 0.f, yy = 0.f, yz = 0.f;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+      float v[P + 1];
+      if constexpr (UNIFORM_STRIDES)
+        Row<P, S>::load(rs, e0, (uint32_t)i * s0 + (uint32_t)j * s1, v);
+      else
+        Row<P, S>::load(rs, e0 + (uint32_t)i * s0 + (uint32_t)j * s1, 0u, v);
+      float z = 0.f, zd = 0.f;
+#pragma unroll
+      for (int k = 0; k <= P; ++k) {
+        z = fmaf(Nz[k], v[k], z);
+        zd = fmaf(Dz[k], v[k], zd);
+      }
+      y = fmaf(Ny[j], z, y);
+      yy = fmaf(Dy[j], z, yy);
+      yz = fmaf(Ny[j], zd, yz);
+    }
+    f = fmaf(Nx[i], y, f);
+    fx = fmaf(Dx[i], y, fx);
+    fy = fmaf(Nx[i], yy, fy);
+    fz = fmaf(Nx[i], yz, fz);
+  }
+}
+
+// ------------------------------------------------------------------ point evaluation
+struct Eval {
+  float f, gx, gy, gz;
+  int s[3];     // span index s = p + j per axis
+  int block;    // flat block id
+};
+
+// Owning block along one axis: b = max{ i in [0, G-1] : E[i] <= xc }.  The
+// guess from the mean block width is corrected by exact edge comparisons.
+__device__ __forceinline__ int owner(const double* __restrict__ E, int G, double scale, double xc) {
+  int b = (int)((xc - E[0]) * scale);
+  b = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
+  while (b < G - 1 && E[b + 1] <= xc) ++b;
+  while (b > 0 && E[b] > xc) --b;
+  return b;
+}
+
+template <int P, Storage S, bool MULTI>
+__device__ __forceinline__ Eval eval_world(const DevModel& m, __amdgpu_buffer_rsrc_t rs,
+                                           const double (&x)[3]) {
+  Eval r;
+  const DevBlock* B = &m.b0;
+  DevBlock blk;
+  double u[3];
+  if constexpr (MULTI) {
+    int b[3];
+    double xc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double* E = m.edges + m.edge_off[a];
+      xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
+      b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+    }
+    r.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
+    blk = m.blocks[r.block];
+    B = &blk;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
+  } else {
+    r.block = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+  }
+  float N[3][P + 1], D[3][P + 1], ds[3];
+  int j[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    SpanRec rec;
+    j[a] = locate_span(m.rec + B->rec_off[a], B->nsp[a], u[a], rec);
+    r.s[a] = j[a] + P;
+    basis<P>(m.mats + (int64_t)rec.mat * m.mat_stride, local_tau(rec, u[a]), N[a], D[a]);
+    ds[a] = rec.dscale;
+  }
+  const uint32_t n1 = (uint32_t)B->n[1], s1 = (uint32_t)B->rs1;
+  const uint32_t e0 =
+      (uint32_t)B->ctrl_off + ((uint32_t)j[0] * n1 + (uint32_t)j[1]) * s1 + (uint32_t)j[2];
+  float f, fx, fy, fz;
+  contract<P, S, !MULTI>(rs, e0, n1 * s1, s1, N[0], D[0], N[1], D[1], N[2], D[2], f, fx, fy, fz);
+  r.f = f;
+  r.gx = fx * ds[0];
+  r.gy = fy * ds[1];
+  r.gz = fz * ds[2];
+  return r;
+}
+
+// ------------------------------------------------------------------ K1: points
+template <int P, Storage S, bool MULTI>
+__global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
+                                                          int64_t n, float* __restrict__ out,
+                                                          int32_t* __restrict__ dbg) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const double x[3] = {(double)xyz[i], (double)xyz[n + i], (double)xyz[2 * n + i]};
+  const Eval e = eval_world<P, S, MULTI>(m, rs, x);
+  reinterpret_cast<float4*>(out)[i] = make_float4(e.f, e.gx, e.gy, e.gz);
+  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(e.s[0], e.s[1], e.s[2], e.block);
+}
+
+// ------------------------------------------------------------------ K3: grid
+// One wave = 64 consecutive entries c of axis 2 for one entry b of axis 1
+// and a run of up to ga.ta entries a of axis 0.  The axis-0 bases of the
+// run are computed once per workgroup into LDS.  Along the run the wave
+// keeps a window Y[r] (r = 0..P) of axis-2/axis-1 partial sums for control
+// rows i = j_a + r, sliding it when the axis-0 span advances by one.
+template <int P>
+struct ABasis {
+  float N[P + 1];
+  float D[P + 1];
+  float ds;
+  int j;
+};
+
+constexpr int kGridTA = 64;
+
+template <int P>
+__device__ __forceinline__ void axis_basis(const DevModel& m, int a, double uraw, float (&N)[P + 1],
+                                           float (&D)[P + 1], float& ds, int& j) {
+  const double u = clampd(uraw, 0.0, 1.0);
+  SpanRec rec;
+  j = locate_span(m.rec + m.b0.rec_off[a], m.b0.nsp[a], u, rec);
+  basis<P>(m.mats + (int64_t)rec.mat * m.mat_stride, local_tau(rec, u), N, D);
+  ds = rec.dscale;
+}
+
+template <int P, Storage S>
+__global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga) {
+  __shared__ ABasis<P> sa[kGridTA];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int a0 = blockIdx.z * ga.ta;
+  const int na = min(ga.ta, ga.res[0] - a0);
+  for (int t = threadIdx.x; t < na; t += kBlock) {
+    ABasis<P> ab;
+    axis_basis<P>(m, 0, ga.axis[0][a0 + t], ab.N, ab.D, ab.ds, ab.j);
+    sa[t] = ab;
+    if (ga.spans && blockIdx.x == 0 && blockIdx.y == 0) ga.spans[a0 + t] = ab.j + P;
+  }
+  __syncthreads();
+  const int b = blockIdx.y * (kBlock / kWave) + wave;
+  if (b >= ga.res[1]) return;                       // uniform per wave
+  const int c = blockIdx.x * kWave + lane;
+  const bool cvalid = c < ga.res[2];
+  const int cc = cvalid ? c : ga.res[2] - 1;
+  float Ny[P + 1], Dy[P + 1], Nz[P + 1], Dz[P + 1], dsy, dsz;
+  int jy, jz;
+  axis_basis<P>(m, 1, ga.axis[1][b], Ny, Dy, dsy, jy);
+  axis_basis<P>(m, 2, ga.axis[2][cc], Nz, Dz, dsz, jz);
+  jy = __builtin_amdgcn_readfirstlane(jy);          // b is uniform across the wave
+  if (ga.spans) {
+    if (blockIdx.x == 0 && blockIdx.z == 0 && lane == 0) ga.spans[ga.res[0] + b] = jy + P;
+    if (blockIdx.y == 0 && blockIdx.z == 0 && wave == 0 && cvalid)
+      ga.spans[ga.res[0] + ga.res[1] + c] = jz + P;
+  }
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const uint32_t n1 = (uint32_t)m.b0.n[1], s1 = (uint32_t)m.b0.rs1;
+  const uint32_t ez = (uint32_t)jz;                 // per-lane element offset along axis 2
+
+  // Y/YY/YZ partial sums of control row i over axes 2 and 1.
+  auto row = [&](int i, float& y, float& yy, float& yz) {
+    y = yy = yz = 0.f;
+#pragma unroll
+    for (int jj = 0; jj <= P; ++jj) {
+      float v[P + 1];
+      const uint32_t es = ((uint32_t)i * n1 + (uint32_t)(jy + jj)) * s1;
+      Row<P, S>::load(rs, ez, es, v);
+      float z = 0.f, zd = 0.f;
+#pragma unroll
+      for (int k = 0; k <= P; ++k) {
+        z = fmaf(Nz[k], v[k], z);
+        zd = fmaf(Dz[k], v[k], zd);
+      }
+      y = fmaf(Ny[jj], z, y);
+      yy = fmaf(Dy[jj], z, yy);
+      yz = fmaf(Ny[jj], zd, yz);
+    }
+  };
+
+  float Y[P + 1], YY[P + 1], YZ[P + 1];
+  int wj = -(1 << 30);
+  const int64_t plane = (int64_t)ga.res[1] * ga.res[2];
+  float4* out = reinterpret_cast<float4*>(ga.out);
+  for (int t = 0; t < na; ++t) {
+    const int ja = __builtin_amdgcn_readfirstlane(sa[t].j);
+    if (ja != wj) {
+      if (ja == wj + 1) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) { Y[r] = Y[r + 1]; YY[r] = YY[r + 1]; YZ[r] = YZ[r + 1]; }
+        row(ja + P, Y[P], YY[P], YZ[P]);
+      } else {
+#pragma unroll
+        for (int r = 0; r <= P; ++r) row(ja + r, Y[r], YY[r], YZ[r]);
+      }
+      wj = ja;
+    }
+    float f = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+      const float nx = sa[t].N[r], dx = sa[t].D[r];
+      f = fmaf(nx, Y[r], f);
+      fx = fmaf(dx, Y[r], fx);
+      fy = fmaf(nx, YY[r], fy);
+      fz = fmaf(nx, YZ[r], fz);
+    }
+    if (cvalid)
+      out[(int64_t)(a0 + t) * plane + (int64_t)b * ga.res[2] + c] =
+          make_float4(f, fx * sa[t].ds, fy * dsy, fz * dsz);
+  }
+}
+
+// ------------------------------------------------------------------ K4: render
+// One ray per lane; a workgroup covers a 16x16 pixel tile (four 8x8 waves).
+// Workgroup i runs on XCD i % 8, so tiles are dealt to XCDs in contiguous
+// bands: each XCD's L2 then holds the part of the model its rays touch.
+constexpr int kTile = 16;
+
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+struct Ray {
+  double o[3], d[3];
+  double t_near;
+  int K;
+};
+
+__device__ __forceinline__ Ray make_ray(const DevModel& m, const RenderArgs& r, int i, int j) {
+#pragma clang fp contract(off)
+  Ray ray;
+  const double px = (double)(2 * i + 1 - r.w) * r.sx;
+  const double py = (double)(r.h - 2 * j - 1) * r.sy;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (r.kind == 0) {
+      ray.o[a] = (r.eye[a] + px * r.right[a]) + py * r.up[a];
+      ray.d[a] = r.fwd[a];
+    } else {
+      ray.o[a] = r.eye[a];
+      ray.d[a] = (r.fwd[a] + px * r.right[a]) + py * r.up[a];
+    }
+  }
+  double tn = 0.0, tf = __builtin_inf();
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (ray.d[a] == 0.0) {
+      miss |= (ray.o[a] < m.box_lo[a]) || (ray.o[a] > m.box_hi[a]);
+    } else {
+      const double inv = 1.0 / ray.d[a];
+      const double t1 = (m.box_lo[a] - ray.o[a]) * inv;
+      const double t2 = (m.box_hi[a] - ray.o[a]) * inv;
+      tn = fmax(tn, fmin(t1, t2));
+      tf = fmin(tf, fmax(t1, t2));
+    }
+  }
+  miss |= tn >= tf;
+  ray.t_near = tn;
+  ray.K = 0;
+  if (!miss) {
+    const double q = floor((tf - tn) / r.step);
+    ray.K = (int)fmin(q, (double)r.max_samples);
+  }
+  return ray;
+}
+
+__device__ __forceinline__ void sample_point(const Ray& ray, double step, int k, double (&x)[3]) {
+#pragma clang fp contract(off)
+  const double t = ray.t_near + ((double)k + 0.5) * step;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = ray.o[a] + t * ray.d[a];
+}
+
+template <int P, Storage S, bool MULTI>
+__global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
+  __shared__ float4 tf[256];
+  tf[threadIdx.x] = reinterpret_cast<const float4*>(r.tf)[threadIdx.x];
+  __syncthreads();
+  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+  const int tile = xcd_tile(blockIdx.x, tx * ty);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool pix = i < r.w && j < r.h;
+  Ray ray;
+  ray.K = 0;
+  if (pix) ray = make_ray(m, r, i, j);
+  float L[3];
+  if (pix) {
+    const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L[a] = (float)(-ray.d[a] / dn);
+  }
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const int64_t pid = (int64_t)j * r.w + i;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+  int used = 0;
+  bool done = false;
+  for (int k = 0;; ++k) {
+    const bool act = pix && !done && k < ray.K;
+    if (__ballot(act) == 0) break;                 // whole wave finished
+    if (!act) continue;
+    double x[3];
+    sample_point(ray, r.step, k, x);
+    const Eval e = eval_world<P, S, MULTI>(m, rs, x);
+    // transfer function
+    float s = (e.f - r.vmin) * r.inv_range;
+    s = fminf(fmaxf(s, 0.f), 1.f) * 255.f;
+    const int i0 = min((int)floorf(s), 254);
+    const float w = s - (float)i0;
+    const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+    const float cr = fmaf(w, c1.x - c0.x, c0.x);
+    const float cg = fmaf(w, c1.y - c0.y, c0.y);
+    const float cb = fmaf(w, c1.z - c0.z, c0.z);
+    const float alpha = fmaf(w, c1.w - c0.w, c0.w);
+    // headlight Phong, two-sided
+    const float gn = sqrtf(e.gx * e.gx + e.gy * e.gy + e.gz * e.gz);
+    const float inv = 1.f / fmaxf(gn, r.g0);
+    const float diff = fabsf((e.gx * L[0] + e.gy * L[1] + e.gz * L[2]) * inv);
+    float spec = 1.f, bse = diff;
+    for (int ex = r.shininess; ex; ex >>= 1) {
+      if (ex & 1) spec *= bse;
+      bse *= bse;
+    }
+    const float shade = fmaf(r.kd, diff, r.ka);
+    const float ks = r.ks * spec;
+    // front-to-back over; the opacity update rounds each operation
+    const float om = __fsub_rn(1.f, A);
+    const float ta = __fmul_rn(om, alpha);
+    C0 = fmaf(ta, fmaf(cr, shade, ks), C0);
+    C1 = fmaf(ta, fmaf(cg, shade, ks), C1);
+    C2 = fmaf(ta, fmaf(cb, shade, ks), C2);
+    A = __fadd_rn(A, ta);
+    used = k + 1;
+    if (r.alpha) r.alpha[pid * r.alpha_stride + k] = alpha;
+    done = A >= r.ert_alpha;
+  }
+  if (pix) {
+    reinterpret_cast<float4*>(r.rgba)[pid] = make_float4(C0, C1, C2, A);
+    if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, used);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int P, Storage S>
+static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int64_t n, float* out,
+                           int32_t* dbg, hipStream_t st) {
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  if (multi)
+    hipLaunchKernelGGL((decode_points_k<P, S, true>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
+                       out, dbg);
+  else
+    hipLaunchKernelGGL((decode_points_k<P, S, false>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
+                       out, dbg);
+  return hipGetLastError();
+}
+
+template <int P, Storage S>
+static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
+  ga.ta = kGridTA;
+  dim3 grid((ga.res[2] + kWave - 1) / kWave, (ga.res[1] + 3) / 4, (ga.res[0] + kGridTA - 1) / kGridTA);
+  hipLaunchKernelGGL((decode_grid_k<P, S>), grid, dim3(kBlock), 0, st, m, ga);
+  return hipGetLastError();
+}
+
+template <int P, Storage S>
+static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
+  const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  if (multi)
+    hipLaunchKernelGGL((render_k<P, S, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else
+    hipLaunchKernelGGL((render_k<P, S, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  return hipGetLastError();
+}
+
+#define MFA_DISPATCH(FN, ...)                                                        \
+  switch (p) {                                                                       \
+    case 1: return s == Storage::F32 ? FN<1, Storage::F32>(__VA_ARGS__)              \
+                 : s == Storage::BF16 ? FN<1, Storage::BF16>(__VA_ARGS__)            \
+                                      : FN<1, Storage::F16>(__VA_ARGS__);            \
+    case 2: return s == Storage::F32 ? FN<2, Storage::F32>(__VA_ARGS__)              \
+                 : s == Storage::BF16 ? FN<2, Storage::BF16>(__VA_ARGS__)            \
+                                      : FN<2, Storage::F16>(__VA_ARGS__);            \
+    case 3: return s == Storage::F32 ? FN<3, Storage::F32>(__VA_ARGS__)              \
+                 : s == Storage::BF16 ? FN<3, Storage::BF16>(__VA_ARGS__)            \
+                                      : FN<3, Storage::F16>(__VA_ARGS__);            \
+    case 4: return s == Storage::F32 ? FN<4, Storage::F32>(__VA_ARGS__)              \
+                 : s == Storage::BF16 ? FN<4, Storage::BF16>(__VA_ARGS__)            \
+                                      : FN<4, Storage::F16>(__VA_ARGS__);            \
+    case 5: return s == Storage::F32 ? FN<5, Storage::F32>(__VA_ARGS__)              \
+                 : s == Storage::BF16 ? FN<5, Storage::BF16>(__VA_ARGS__)            \
+                                      : FN<5, Storage::F16>(__VA_ARGS__);            \
+    default: return hipErrorInvalidValue;                                            \
+  }
+
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
+                                int64_t n, float* out, int32_t* dbg, hipStream_t st) {
+  MFA_DISPATCH(points_p, m, multi, xyz, n, out, dbg, st)
+}
+
+hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
+                              hipStream_t st) {
+  MFA_DISPATCH(grid_p, m, ga, st)
+}
+
+hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+                         hipStream_t st) {
+  MFA_DISPATCH(render_p, m, multi, r, st)
+}
+
+}  // namespace mfa

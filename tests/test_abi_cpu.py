@@ -1,0 +1,123 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its host-only helpers agree bit for bit with the oracle's
+independent definitions, and argument validation rejects bad calls before
+any device work (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import quant
+from paper_2312_15073_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfa.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(L.LIB_PATH),
+                                reason="libmfa.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfa_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "mfa_render_frame" in names and "mfa_decode_points" in names
+    lib = C.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in mfa.h but not exported"
+    assert set(names) == set(L.SIGNATURES), "binding signatures out of sync with the header"
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_library_storage_rounding_matches_oracle_bits(dtype):
+    import paper_2312_15073_amd as mfa
+    rng = np.random.default_rng(21)
+    x = np.concatenate([
+        rng.standard_normal(50000) * 10.0 ** rng.integers(-9, 5, size=50000),
+        np.array([0.0, -0.0, 1.0, 65504.0, 65519.0, 65520.0, 1e-8, 5.9604644775390625e-08,
+                  2.98e-8, 1 + 2 ** -9, 1 + 3 * 2 ** -9, 1 + 2 ** -12, 1 + 3 * 2 ** -12,
+                  3.0e38, -6.1e-5]),
+        synth.model_c1().blocks[0].ctrl.reshape(-1),
+    ])
+    got = mfa.quantize(x, dtype)
+    want = quant.stored_bits(x, dtype)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,p", [(4, 3), (16, 3), (128, 3), (9, 2), (40, 5), (2, 1)])
+def test_library_default_knots_equal_input_knots(n, p):
+    import paper_2312_15073_amd as mfa
+    np.testing.assert_array_equal(mfa.default_knots(n, p), synth.clamped_uniform_knots(n, p))
+
+
+def _domain(grid=(1, 1, 1)):
+    d = L.DomainDesc()
+    for a in range(3):
+        d.grid[a] = grid[a]
+        d.lo[a] = 0.0
+        d.hi[a] = 1.0
+    d.voxel = 1.0 / 63
+    return d
+
+
+def _block(n=(8, 8, 8), p=3, ctrl=None):
+    b = L.BlockDesc()
+    for a in range(3):
+        b.degree[a] = p
+        b.n_ctrl[a] = n[a]
+    if ctrl is None:
+        ctrl = np.zeros(n)
+    b.ctrl = ctrl.ctypes.data
+    b.ctrl_dtype = L.MFA_F64
+    return b, ctrl
+
+
+def _create(dom, blocks, nb, storage=L.MFA_F32):
+    h = C.c_void_p()
+    arr = (L.BlockDesc * len(blocks))(*blocks)
+    st = L.lib().mfa_model_create(C.byref(dom), arr, nb, storage, C.byref(h))
+    return st, L.lib().mfa_last_error().decode()
+
+
+def test_model_create_rejects_bad_arguments_before_device_work():
+    lib = L.lib()
+    b, keep = _block()
+    st, msg = _create(_domain(), [b], 2)
+    assert st == L.MFA_E_ARG and "nblocks" in msg
+    d = _domain()
+    d.hi[1] = 0.0
+    assert _create(d, [b], 1)[0] == L.MFA_E_ARG
+    d = _domain()
+    d.voxel = 0.0
+    assert _create(d, [b], 1)[0] == L.MFA_E_ARG
+    assert _create(_domain(), [b], 1, storage=L.MFA_F64)[0] == L.MFA_E_ARG
+    b2, k2 = _block(p=6)
+    assert _create(_domain(), [b2], 1)[0] == L.MFA_E_UNSUPPORTED
+    b3, k3 = _block(n=(3, 8, 8))
+    st, msg = _create(_domain(), [b3], 1)
+    assert st == L.MFA_E_ARG and "n_ctrl" in msg
+    b4, k4 = _block()
+    b4.degree[1] = 2
+    assert _create(_domain(), [b4], 1)[0] == L.MFA_E_UNSUPPORTED
+    b5, k5 = _block()
+    b5.ctrl = None
+    assert _create(_domain(), [b5], 1)[0] == L.MFA_E_ARG
+    assert lib.mfa_model_create(None, None, 1, L.MFA_F32, None) == L.MFA_E_ARG
+
+
+def test_null_model_calls_are_rejected():
+    lib = L.lib()
+    assert lib.mfa_decode_points(None, None, 10, 0, None, None, None) == L.MFA_E_ARG
+    assert lib.mfa_render_frame(None, None, None, 4, 4, None, None, None) == L.MFA_E_ARG
+    assert lib.mfa_model_info(None, None) == L.MFA_E_ARG
+    assert lib.mfa_model_destroy(None) == L.MFA_OK
+    assert lib.mfa_quantize(None, 5, L.MFA_F32, None) == L.MFA_E_ARG
+    assert lib.mfa_default_knots(2, 3, None) == L.MFA_E_ARG
+    assert "mfa-gfx950" in lib.mfa_version().decode()

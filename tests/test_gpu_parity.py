@@ -1,0 +1,296 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Small workloads are compared element by element (several tiles plus ragged
+tails); the full-size point / grid / frame workloads are compared on
+sampled outputs that the oracle evaluates one by one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import bspline as ob
+from oracle import quant
+from oracle import render as orr
+from tests.gpu_common import announce, assert_values_close, composite_band
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mfa():
+    import paper_2312_15073_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.model_c1()
+
+
+def to_dev(x, dev, dtype=None):
+    import torch
+    t = torch.as_tensor(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev)
+
+
+def adversarial_points(model, rng, n_rand):
+    """Random points plus points exactly on knots, on the box faces and
+    outside the box (clamped by the map)."""
+    pts = [rng.random((n_rand, 3)).astype(np.float32)]
+    T = model.blocks[0].knots[0]
+    knots = np.unique(T).astype(np.float32)
+    k = rng.choice(knots, size=(400, 3))
+    pts.append(k)
+    pts.append(np.array([[0, 0, 0], [1, 1, 1], [1, 0, 1], [-0.25, 0.5, 1.5], [2, -1, 0.5],
+                         [np.nextafter(np.float32(1), np.float32(0))] * 3], dtype=np.float32))
+    return np.concatenate(pts).astype(np.float32)
+
+
+def oracle_points(model, pts32):
+    return ob.evaluate(model, pts32.astype(np.float64))
+
+
+# ------------------------------------------------------------------ points
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_decode_points_single_block_fp32(mfa, dev, p):
+    model = synth.model_c1(p=p)
+    rng = np.random.default_rng(100 + p)
+    pts = adversarial_points(model, rng, 20000)
+    announce(f"decode_points c1 p={p} n={len(pts)}")
+    with mfa.Model(model, "f32") as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts.T, dev), dbg=True)
+        out, dbg = out.cpu().numpy(), dbg.cpu().numpy()
+    ref = oracle_points(model, pts)
+    np.testing.assert_array_equal(dbg[:, :3], ref["spans"])
+    assert np.all(dbg[:, 3] == 0)
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(model.blocks[0].ctrl)))
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000])
+def test_decode_points_ragged_sizes(mfa, dev, c1, n):
+    pts = synth.random_points(n, seed=n)
+    announce(f"decode_points ragged n={n}")
+    with mfa.Model(c1, "f32") as M:
+        out = mfa.decode_points(M, to_dev(pts, dev)).cpu().numpy()
+    ref = oracle_points(c1, pts.T)
+    assert out.shape == (n, 4)
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(c1.blocks[0].ctrl)))
+
+
+def test_decode_points_empty_is_noop(mfa, dev, c1):
+    import torch
+    announce("decode_points n=0")
+    with mfa.Model(c1, "f32") as M:
+        out = mfa.decode_points(M, torch.zeros((3, 0), dtype=torch.float32, device=dev))
+    assert out.shape == (0, 4)
+
+
+def test_decode_points_nonunit_box_and_nonuniform_knots(mfa, dev):
+    rng = np.random.default_rng(7)
+    p = 3
+    ns = (11, 14, 9)
+    knots = []
+    for a, n in enumerate(ns):
+        inner = np.sort(rng.uniform(0, 1, n - p - 1))
+        inner[2] = inner[3]
+        knots.append(np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)]))
+    P = rng.standard_normal(ns)
+    model = synth.single_block_model(P, [p] * 3, knots, lo=(-2.0, 0.5, 1.0), hi=(3.0, 0.75, 9.0))
+    pts = (model.lo + rng.random((30000, 3)) * (model.hi - model.lo)).astype(np.float32)
+    announce("decode_points non-uniform knots, non-unit box")
+    with mfa.Model(model, "f32") as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts.T, dev), dbg=True)
+        out, dbg = out.cpu().numpy(), dbg.cpu().numpy()
+    ref = oracle_points(model, pts)
+    np.testing.assert_array_equal(dbg[:, :3], ref["spans"])
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)))
+
+
+# ------------------------------------------------------------------ grid
+def test_decode_grid_c1_full(mfa, dev, c1):
+    ax = [synth.grid_axis(64)] * 3
+    announce("decode_grid c1 64^3")
+    with mfa.Model(c1, "f32") as M:
+        out, spans = mfa.decode_grid(M, [to_dev(a, dev) for a in ax], spans=True)
+        out, spans = out.cpu().numpy(), spans.cpu().numpy()
+    ref = ob.decode_grid(c1, ax)
+    rs = ob.grid_spans(c1, ax)
+    np.testing.assert_array_equal(spans, np.concatenate(rs))
+    assert_values_close(out.reshape(-1, 4), ref[..., 0].reshape(-1), ref[..., 1:].reshape(-1, 3),
+                        np.max(np.abs(c1.blocks[0].ctrl)))
+
+
+def test_decode_grid_ragged_unsorted_tables(mfa, dev, c1):
+    rng = np.random.default_rng(3)
+    ax = [rng.permutation(np.concatenate([synth.grid_axis(30), [-0.2, 1.3]])),
+          np.sort(rng.random(5)),
+          np.concatenate([synth.grid_axis(70)[::-1], [0.5]])]
+    announce("decode_grid ragged 32x5x71 unsorted")
+    with mfa.Model(c1, "f32") as M:
+        out, spans = mfa.decode_grid(M, [to_dev(a, dev) for a in ax], spans=True)
+        out, spans = out.cpu().numpy(), spans.cpu().numpy()
+    ref = ob.decode_grid(c1, ax)
+    np.testing.assert_array_equal(spans, np.concatenate(ob.grid_spans(c1, ax)))
+    assert_values_close(out.reshape(-1, 4), ref[..., 0].reshape(-1), ref[..., 1:].reshape(-1, 3),
+                        np.max(np.abs(c1.blocks[0].ctrl)))
+
+
+# ------------------------------------------------------------------ render
+def check_render(mfa, dev, model, cam, params, W, H, storage="f32", ref_model=None):
+    ref_model = ref_model or model
+    with mfa.Model(model, storage) as M:
+        rgba, ns, al = mfa.render_frame(M, cam, params, W, H, nsamp=True, alpha=True, device=dev)
+        rgba, ns, al = rgba.cpu().numpy(), ns.cpu().numpy(), al.cpu().numpy()
+    ref = orr.render(orr.model_field(ref_model), model.lo, model.hi, cam, params, W, H,
+                     record_alpha=True)
+    K = ns[..., 0].reshape(-1)
+    used = ns[..., 1].reshape(-1)
+    np.testing.assert_array_equal(K, ref["K"])                      # schedule: exact
+    # exact FP32 replay of the kernel's own opacities: identical decisions
+    alpha = al.reshape(W * H, -1)
+    rep = orr.ert_replay_f32(alpha, K, params["ert_alpha"])
+    np.testing.assert_array_equal(used, rep)
+    # against the FP64 oracle: equal outside the threshold band
+    band = composite_band(ref["alpha"], ref["used"], float(params["ert_alpha"]))
+    out = ~band
+    np.testing.assert_array_equal(used[out], ref["used"][out])
+    assert np.all(np.abs(used[band] - ref["used"][band]) <= 1)
+    img = rgba.reshape(-1, 4)
+    diff = np.abs(img[out] - ref["rgba"][out])
+    rmse = float(np.sqrt(np.mean(diff ** 2))) if diff.size else 0.0
+    assert rmse <= 1e-5, f"image RMSE {rmse:.3e}"
+    assert diff.max(initial=0.0) <= 1e-3, f"image max-abs {diff.max():.3e}"
+    return dict(band=int(band.sum()), rmse=rmse, samples=int(used.sum()),
+                terminated=int((used < K).sum()))
+
+
+def test_render_c1_ortho_128(mfa, dev, c1):
+    W = H = 128
+    cam = synth.ortho_camera(W, H)
+    params = synth.render_params(c1)
+    announce("render c1 128x128 ortho")
+    r = check_render(mfa, dev, c1, cam, params, W, H)
+    assert r["samples"] > 100000 and r["terminated"] > 100
+
+
+def test_render_c1_perspective_ragged(mfa, dev, c1):
+    W, H = 100, 37
+    cam = synth.perspective_camera(W, H, az_deg=-70, el_deg=40, dist=1.6)
+    params = synth.render_params(c1, max_samples=90)
+    announce("render c1 100x37 perspective, max_samples 90")
+    check_render(mfa, dev, c1, cam, params, W, H)
+
+
+def test_render_closed_form_constant_opacity(mfa, dev):
+    T = synth.clamped_uniform_knots(8, 3)
+    P = synth.linear_precision_ctrl([T] * 3, [3] * 3, (0.0, 1.0, 0.0, 0.0))
+    model = synth.single_block_model(P, [3] * 3, [T] * 3, voxel=1.0 / 64)
+    cam = synth.axis_camera(20, 20, axis=0, half_extent=0.45)
+    params = synth.render_params(model, tf=synth.tf_table_constant([0.2, 0.5, 0.9, 0.1]),
+                                 step=1.0 / 128, vmin=0.0, vmax=1.0)
+    announce("render closed form")
+    with mfa.Model(model, "f32") as M:
+        rgba, ns = mfa.render_frame(M, cam, params, 20, 20, nsamp=True, device=dev)
+        rgba, ns = rgba.cpu().numpy(), ns.cpu().numpy()
+    assert np.all(ns[..., 0] == 128) and np.all(ns[..., 1] == 44)
+    A = 1 - (1 - float(np.float32(0.1))) ** 44
+    np.testing.assert_allclose(rgba[..., 3], A, atol=1e-6)
+
+
+# ------------------------------------------------------------------ precision forms
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_reduced_precision_storage(mfa, dev, dtype, p):
+    model = synth.model_c1(p=p)
+    P = model.blocks[0].ctrl
+    qP = quant.stored_values(P, dtype)
+    qmodel = synth.single_block_model(qP, [p] * 3, model.blocks[0].knots, voxel=model.voxel)
+    pts = synth.random_points(20011, seed=40 + p)
+    announce(f"decode_points {dtype} p={p}")
+    with mfa.Model(model, dtype) as M:
+        bits = M.export_ctrl(0)
+        out = mfa.decode_points(M, to_dev(pts, dev)).cpu().numpy()
+        info = M.info()
+    np.testing.assert_array_equal(bits, quant.stored_bits(P, dtype))
+    assert info["vmin"] == np.float32(qP.min()) and info["vmax"] == np.float32(qP.max())
+    ref_q = oracle_points(qmodel, pts.T)
+    assert_values_close(out, ref_q["f"], ref_q["grad"], np.max(np.abs(P)))
+    # against the FP64 model: within the storage bound plus arithmetic error
+    ref = oracle_points(model, pts.T)
+    dP = np.max(np.abs(qP - P))
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)), extra_f=dP,
+                        extra_g=2 * p * (16 - p) * dP)
+
+
+def test_render_bf16_matches_oracle_on_stored_points(mfa, dev, c1):
+    qP = quant.stored_values(c1.blocks[0].ctrl, "bf16")
+    qmodel = synth.single_block_model(qP, [3] * 3, c1.blocks[0].knots, voxel=c1.voxel)
+    W = H = 64
+    cam = synth.ortho_camera(W, H, az_deg=120)
+    params = synth.render_params(c1)
+    announce("render c1 bf16 64x64")
+    check_render(mfa, dev, c1, cam, params, W, H, storage="bf16", ref_model=qmodel)
+
+
+# ------------------------------------------------------------------ full-size workloads (sampled)
+@pytest.fixture(scope="module")
+def c2():
+    return synth.model_c2()
+
+
+def test_c2_grid_512_sampled(mfa, dev, c2):
+    import torch
+    ax = [synth.grid_axis(512)] * 3
+    announce("decode_grid c2 512^3 (sampled)")
+    with mfa.Model(c2, "f32") as M:
+        out, spans = mfa.decode_grid(M, [to_dev(a, dev) for a in ax], spans=True)
+        rng = np.random.default_rng(5)
+        idx = rng.integers(0, 512, size=(3000, 3))
+        idx = np.concatenate([idx, [[0, 0, 0], [511, 511, 511], [0, 511, 255]]])
+        sel = out[torch.as_tensor(idx[:, 0]), torch.as_tensor(idx[:, 1]), torch.as_tensor(idx[:, 2])]
+        got = sel.cpu().numpy()
+        spans = spans.cpu().numpy()
+        del out
+    np.testing.assert_array_equal(spans, np.concatenate(ob.grid_spans(c2, ax)))
+    ref = ob.decode_grid(c2, ax, out_index=idx)
+    assert_values_close(got, ref[:, 0], ref[:, 1:], np.max(np.abs(c2.blocks[0].ctrl)))
+
+
+def test_c2_points_1e7_sampled(mfa, dev, c2):
+    pts = synth.random_points(10_000_000, seed=12)
+    announce("decode_points c2 1e7 (sampled)")
+    with mfa.Model(c2, "f32") as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts, dev), dbg=True)
+        rng = np.random.default_rng(6)
+        k = np.concatenate([rng.integers(0, pts.shape[1], size=20000), [0, pts.shape[1] - 1]])
+        import torch
+        kt = torch.as_tensor(k, device=dev)
+        got = out[kt].cpu().numpy()
+        gs = dbg[kt].cpu().numpy()
+    ref = oracle_points(c2, pts[:, k].T)
+    np.testing.assert_array_equal(gs[:, :3], ref["spans"])
+    assert_values_close(got, ref["f"], ref["grad"], np.max(np.abs(c2.blocks[0].ctrl)))
+
+
+def test_c2_render_1024_sampled(mfa, dev, c2):
+    W = H = 1024
+    cam = synth.perspective_camera(W, H)
+    params = synth.render_params(c2)
+    announce("render c2 1024x1024 perspective (sampled)")
+    with mfa.Model(c2, "f32") as M:
+        rgba, ns = mfa.render_frame(M, cam, params, W, H, nsamp=True, device=dev)
+        rgba, ns = rgba.cpu().numpy().reshape(-1, 4), ns.cpu().numpy().reshape(-1, 2)
+    rng = np.random.default_rng(8)
+    pix = np.stack([rng.integers(0, H, 240), rng.integers(0, W, 240)], axis=1)
+    pix = np.concatenate([pix, [[0, 0], [H - 1, W - 1], [H // 2, W // 2]]])
+    ref = orr.render(orr.model_field(c2), c2.lo, c2.hi, cam, params, W, H, pixels=pix,
+                     record_alpha=True)
+    flat = pix[:, 0] * W + pix[:, 1]
+    np.testing.assert_array_equal(ns[flat, 0], ref["K"])
+    band = composite_band(ref["alpha"], ref["used"], float(params["ert_alpha"]))
+    np.testing.assert_array_equal(ns[flat, 1][~band], ref["used"][~band])
+    diff = np.abs(rgba[flat][~band] - ref["rgba"][~band])
+    assert diff.max(initial=0) <= 1e-3 and np.sqrt(np.mean(diff ** 2)) <= 1e-5
+    assert ns[:, 1].sum() > 1e7          # a real frame: many samples
