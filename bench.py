@@ -150,10 +150,12 @@ def main(argv=None):
     rgba = torch.empty((FRAME, FRAME, 4), dtype=torch.float32, device=dev)
 
     # samples the frame composites (exact, from the kernel's own counters)
-    _, ns = mfa.render_frame(model, cam, params, FRAME, FRAME, tf_dev=tf, nsamp=True, device=dev)
+    _, ns, ne = mfa.render_frame(model, cam, params, FRAME, FRAME, tf_dev=tf, nsamp=True,
+                                 neval=True, device=dev)
     torch.cuda.synchronize()
     s_frame = int(ns[..., 1].sum().item())
-    del ns
+    s_eval = int(ne.sum().item())
+    del ns, ne
     n_grid = GRID_N ** 3
     samples_step = n_grid + N_POINTS + s_frame
 
@@ -199,9 +201,11 @@ def main(argv=None):
                               achieved=pts_bytes / kern_ms["decode_points"] / 1e6, unit="GB/s",
                               peak=PEAK_HBM_GBS, bytes_per_launch=pts_bytes,
                               tflops=N_POINTS * fl / kern_ms["decode_points"] / 1e9),
-        "render": dict(ms=kern_ms["render"], samples=s_frame, bound="alu",
-                       achieved=s_frame * fl_r / kern_ms["render"] / 1e9, unit="TFLOP/s",
-                       peak=PEAK_FP32_TFLOPS, flop_per_launch=s_frame * fl_r),
+        # algorithmic work of a frame: full value+gradient+shading work for the
+        # samples evaluated; samples skipped as transparent count no flops
+        "render": dict(ms=kern_ms["render"], samples=s_frame, evaluated_samples=s_eval,
+                       bound="alu", achieved=s_eval * fl_r / kern_ms["render"] / 1e9,
+                       unit="TFLOP/s", peak=PEAK_FP32_TFLOPS, flop_per_launch=s_eval * fl_r),
     }
     for k in kernels.values():
         k["frac"] = k["achieved"] / k["peak"]
@@ -231,6 +235,7 @@ def main(argv=None):
                                 f"{N_POINTS} random points + {FRAME}x{FRAME} perspective frame "
                                 f"(max 1024 samples/ray)"),
                    "samples_per_step": samples_step, "frame_samples": s_frame,
+                   "frame_samples_evaluated": s_eval,
                    "parallelism": "single GPU"},
         "ms_per_frame": kern_ms["render"],
         "kernels": kernels,

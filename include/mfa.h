@@ -212,11 +212,17 @@ typedef struct {
 
 /* Optional debug outputs of a render (device memory, NULL = not wanted).
  *  nsamp        : int32 [h][w][2] = (K scheduled samples, samples used).
+ *  neval        : int32 [h][w]: samples whose value and gradient were
+ *                 evaluated; the others lie where the transfer function is
+ *                 zero over the value bounds of the enclosing control points
+ *                 (the spline's convex hull), so their opacity is exactly 0
+ *                 and they leave the pixel unchanged.
  *  alpha        : FP32 [h][w][alpha_stride]: per-sample opacity after the
  *                 transfer function, for samples 0..used-1 (rest untouched).
  *  alpha_stride : >= max_samples when alpha is given.                      */
 typedef struct {
   int32_t* nsamp;
+  int32_t* neval;
   float* alpha;
   int32_t alpha_stride;
 } mfa_render_debug;

@@ -213,11 +213,13 @@ def make_params(params: dict, tf_dev) -> L.RenderParams:
 
 
 def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=None, out=None,
-                 nsamp: bool = False, alpha: bool = False, stream=None, device=None):
+                 nsamp: bool = False, alpha: bool = False, neval: bool = False, stream=None,
+                 device=None):
     """Ray-casts a w x h image.  params as produced by synth.render_params
     (tf may be given as a CUDA (256,4) float32 tensor in tf_dev).  Returns
     rgba (h, w, 4) float32 and optional int32 (h, w, 2) sample counts and
-    float32 (h, w, max_samples) per-sample opacities."""
+    float32 (h, w, max_samples) per-sample opacities and int32 (h, w)
+    evaluated-sample counts, in that order, for the ones asked for."""
     torch = _torch()
     dev = device or torch.device("cuda", torch.cuda.current_device())
     if tf_dev is None:
@@ -229,7 +231,7 @@ def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=N
     po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
     dbg = None
     extra = []
-    if nsamp or alpha:
+    if nsamp or alpha or neval:
         dbg = L.RenderDebug()
         if nsamp:
             ns = torch.zeros((h, w, 2), dtype=torch.int32, device=dev)
@@ -241,6 +243,10 @@ def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=N
             dbg.alpha = al.data_ptr()
             dbg.alpha_stride = ms
             extra.append(al)
+        if neval:
+            ne = torch.zeros((h, w), dtype=torch.int32, device=dev)
+            dbg.neval = ne.data_ptr()
+            extra.append(ne)
     L.check(L.lib().mfa_render_frame(model.handle, C.byref(cobj), C.byref(pobj), int(w), int(h), po,
                                      C.byref(dbg) if dbg is not None else None,
                                      _stream_ptr(stream)))

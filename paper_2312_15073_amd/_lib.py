@@ -51,7 +51,8 @@ class RenderParams(C.Structure):
 
 
 class RenderDebug(C.Structure):
-    _fields_ = [("nsamp", C.c_void_p), ("alpha", C.c_void_p), ("alpha_stride", C.c_int32)]
+    _fields_ = [("nsamp", C.c_void_p), ("neval", C.c_void_p), ("alpha", C.c_void_p),
+                ("alpha_stride", C.c_int32)]
 
 
 # name -> (restype, argtypes); every function declared in include/mfa.h

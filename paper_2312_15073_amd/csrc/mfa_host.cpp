@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -165,13 +166,14 @@ struct mfa_model_s {
   float* d_mats = nullptr;
   DevBlock* d_blocks = nullptr;
   double* d_edges = nullptr;
+  float2* d_mcb = nullptr;
   int64_t device_bytes = 0;
   DevModel dm{};
 };
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -200,6 +202,59 @@ static void default_knots(int n, int p, double* T) {
   }
   const double nsp = (double)(n - p);
   for (int j = 1; j < n - p; ++j) T[p + j] = (double)j / nsp;
+}
+
+// Value bounds per macro cell (kMacro^3 spans) of one block: min and max of
+// the stored control points that act on any span of the cell (the spline is
+// a convex combination of them), by windowed min/max one axis at a time.
+static void macro_bounds(const std::vector<float>& V, const int n[3], int p, const int mc[3],
+                         std::vector<float2>& out) {
+  auto win = [&](int a, int c, int& lo, int& hi) {
+    lo = c * kMacro;
+    hi = std::min(c * kMacro + kMacro - 1, n[a] - p - 1) + p;
+  };
+  const int n0 = n[0], n1 = n[1], n2 = n[2];
+  std::vector<float> lo2((size_t)n0 * n1 * mc[2]), hi2(lo2.size());
+  for (int64_t r = 0; r < (int64_t)n0 * n1; ++r)
+    for (int c = 0; c < mc[2]; ++c) {
+      int a0, a1;
+      win(2, c, a0, a1);
+      float mn = INFINITY, mx = -INFINITY;
+      for (int k = a0; k <= a1; ++k) {
+        mn = std::fmin(mn, V[r * n2 + k]);
+        mx = std::fmax(mx, V[r * n2 + k]);
+      }
+      lo2[r * mc[2] + c] = mn;
+      hi2[r * mc[2] + c] = mx;
+    }
+  std::vector<float> lo1((size_t)n0 * mc[1] * mc[2]), hi1(lo1.size());
+  for (int i = 0; i < n0; ++i)
+    for (int c1 = 0; c1 < mc[1]; ++c1) {
+      int a0, a1;
+      win(1, c1, a0, a1);
+      for (int c2 = 0; c2 < mc[2]; ++c2) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int jj = a0; jj <= a1; ++jj) {
+          const size_t q = ((size_t)i * n1 + jj) * mc[2] + c2;
+          mn = std::fmin(mn, lo2[q]);
+          mx = std::fmax(mx, hi2[q]);
+        }
+        lo1[((size_t)i * mc[1] + c1) * mc[2] + c2] = mn;
+        hi1[((size_t)i * mc[1] + c1) * mc[2] + c2] = mx;
+      }
+    }
+  for (int c0 = 0; c0 < mc[0]; ++c0) {
+    int a0, a1;
+    win(0, c0, a0, a1);
+    for (int c12 = 0; c12 < mc[1] * mc[2]; ++c12) {
+      float mn = INFINITY, mx = -INFINITY;
+      for (int i = a0; i <= a1; ++i) {
+        mn = std::fmin(mn, lo1[(size_t)i * mc[1] * mc[2] + c12]);
+        mx = std::fmax(mx, hi1[(size_t)i * mc[1] * mc[2] + c12]);
+      }
+      out.push_back(make_float2(mn, mx));
+    }
+  }
 }
 
 template <class Tp>
@@ -305,6 +360,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       m->n[3 * b + a] = B.n_ctrl[a];
     }
     D.rs1 = (es == 2) ? (B.n_ctrl[2] + (B.n_ctrl[2] & 1)) : B.n_ctrl[2];
+    for (int a = 0; a < 3; ++a) D.mc[a] = (D.nsp[a] + kMacro - 1) / kMacro;
     D.ctrl_off = off;
     m->coff[b] = off;
     m->rs1[b] = D.rs1;
@@ -353,9 +409,11 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   // storage rounding
   std::vector<uint8_t> pool((size_t)pool_bytes, 0);
   float vmin = INFINITY, vmax = -INFINITY;
+  std::vector<float2> mcb;
   for (int64_t b = 0; b < nb; ++b) {
     const mfa_block_desc& B = blocks[b];
     const int n0 = B.n_ctrl[0], n1 = B.n_ctrl[1], n2 = B.n_ctrl[2];
+    std::vector<float> V((size_t)n0 * n1 * n2);
     for (int64_t i = 0; i < (int64_t)n0 * n1; ++i) {
       for (int k = 0; k < n2; ++k) {
         const int64_t src = i * n2 + k;
@@ -386,11 +444,29 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
         }
         vmin = std::fmin(vmin, stored);
         vmax = std::fmax(vmax, stored);
+        V[(size_t)src] = stored;
       }
     }
+    dblk[b].mc_off = (int32_t)mcb.size();
+    macro_bounds(V, B.n_ctrl, p, dblk[b].mc, mcb);
   }
   m->vmin = vmin;
   m->vmax = vmax;
+  // Widen the bounds by a margin above the FP32 evaluation error (basis
+  // tables and sums in FP32 stay within ~1e-6 of the exact convex
+  // combination relative to max |P|).
+  const float margin = 1e-4f * std::fmax(std::fabs(vmin), std::fabs(vmax));
+  for (float2& c : mcb) {
+    c.x -= margin;
+    c.y += margin;
+  }
+  // most frequent basis table (interior spans)
+  std::vector<int64_t> mat_count(mat_ids.size(), 0);
+  for (const SpanRec& r : recs) ++mat_count[r.mat];
+  int imat = -1;
+  int64_t best = 0;
+  for (size_t q = 0; q < mat_count.size(); ++q)
+    if (mat_count[q] > best) { best = mat_count[q]; imat = (int)q; }
 
   std::vector<double> edge_pool;
   int edge_off[3];
@@ -404,7 +480,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_rec, recs.data(), recs.size() * sizeof(SpanRec), m, "span upload")) != MFA_OK ||
       (st = upload(&m->d_mats, mats.data(), mats.size() * sizeof(float), m, "basis upload")) != MFA_OK ||
       (st = upload(&m->d_blocks, dblk.data(), dblk.size() * sizeof(DevBlock), m, "block upload")) != MFA_OK ||
-      (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK) {
+      (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK ||
+      (st = upload(&m->d_mcb, mcb.data(), mcb.size() * sizeof(float2), m, "bounds upload")) != MFA_OK) {
     free_model(m);
     return st;
   }
@@ -426,6 +503,10 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   }
   dm.nblocks = (int)nb;
   dm.mat_stride = mat_stride(p);
+  dm.n_mats = (int)mat_ids.size();
+  dm.n_rec = (int)recs.size();
+  dm.imat = imat;
+  dm.mcb = m->d_mcb;
   dm.b0 = dblk[0];
   *out = m;
   return MFA_OK;
@@ -556,6 +637,7 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
   r.tf = rp->tf_rgba;
   r.rgba = rgba;
   r.nsamp = dbg ? dbg->nsamp : nullptr;
+  r.neval = dbg ? dbg->neval : nullptr;
   r.alpha = dbg ? dbg->alpha : nullptr;
   r.alpha_stride = dbg ? dbg->alpha_stride : 0;
   r.w = w;

@@ -38,8 +38,15 @@ struct DevBlock {
   int32_t rec_off[3];   // index of the block's span 0 record per axis
   int32_t rs1;          // row stride along axis 1 in elements (n2, padded to
                         // even for 16-bit storage so rows pair into dwords)
+  int32_t mc[3];        // macro cells per axis = ceil(nsp / kMacro)
+  int32_t mc_off;       // index of the block's first macro cell in the bounds pool
 };
-static_assert(sizeof(DevBlock) == 96, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 112, "DevBlock layout");
+
+// Spans per axis grouped into one macro cell for the value bounds used to
+// skip samples that the transfer function makes fully transparent.
+constexpr int kMacroShift = 2;
+constexpr int kMacro = 1 << kMacroShift;
 
 struct DevModel {
   const void* ctrl;
@@ -52,6 +59,11 @@ struct DevModel {
   int32_t grid[3];
   int32_t nblocks;
   int32_t mat_stride;    // floats per basis table
+  int32_t n_mats;        // basis tables in the pool
+  int32_t n_rec;         // span records in the pool
+  int32_t imat;          // most frequent basis table (interior spans), or -1
+  const float2* mcb;     // per macro cell (lo, hi) bounds of the stored values,
+                         // widened by a margin covering FP32 evaluation error
   double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
   double box_lo[3];
   double box_hi[3];
@@ -80,6 +92,7 @@ struct RenderArgs {
   const float* tf;
   float* rgba;
   int32_t* nsamp;
+  int32_t* neval;
   float* alpha;
   int32_t alpha_stride;
   int32_t w, h;

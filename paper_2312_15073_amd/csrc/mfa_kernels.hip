@@ -144,32 +144,59 @@ __device__ __forceinline__ double param_of(double xc, double lo, double inv_ext)
 
 // ------------------------------------------------------------------ basis
 // Values N[r] and d/dtau D[r] (r = 0..P) of the basis functions active on a
-// span, by Horner on the span's polynomial table M (see mat_stride()).
+// span, by Horner on the span's polynomial table (see mat_stride()).
 template <int P>
-__device__ __forceinline__ void basis(const float* __restrict__ M, float tau, float (&N)[P + 1],
-                                      float (&D)[P + 1]) {
-  constexpr int kWords = mat_stride(P);
-  float c[kWords];
+using Table = float[mat_stride(P)];
+
+template <int P>
+__device__ __forceinline__ void load_table(const float* __restrict__ M, Table<P>& c) {
 #pragma unroll
-  for (int q = 0; q < kWords / 4; ++q) {
+  for (int q = 0; q < mat_stride(P) / 4; ++q) {
     const float4 v = reinterpret_cast<const float4*>(M)[q];
     c[4 * q + 0] = v.x;
     c[4 * q + 1] = v.y;
     c[4 * q + 2] = v.z;
     c[4 * q + 3] = v.w;
   }
+}
+
+template <int P>
+__device__ __forceinline__ void horner(const Table<P>& c, float tau, float (&N)[P + 1],
+                                       float (&D)[P + 1]) {
 #pragma unroll
   for (int r = 0; r <= P; ++r) {
     float v = c[r * (P + 1) + P];
 #pragma unroll
     for (int m = P - 1; m >= 0; --m) v = fmaf(v, tau, c[r * (P + 1) + m]);
     N[r] = v;
-    const float* e = c + (P + 1) * (P + 1) + r * P;
-    float d = e[P - 1];
+    const int e = (P + 1) * (P + 1) + r * P;
+    float d = c[e + P - 1];
 #pragma unroll
-    for (int m = P - 2; m >= 0; --m) d = fmaf(d, tau, e[m]);
+    for (int m = P - 2; m >= 0; --m) d = fmaf(d, tau, c[e + m]);
     D[r] = d;
   }
+}
+
+// The most frequent table of the model (the interior spans of uniform knots)
+// is held in scalar registers (ci); per-lane tables are loaded only when a
+// lane of the wave sits on another span type.
+template <int P>
+__device__ __forceinline__ void basis(const float* __restrict__ mats, int stride, int mat, int imat,
+                                      const Table<P>& ci, float tau, float (&N)[P + 1],
+                                      float (&D)[P + 1]) {
+  if (__all(mat == imat)) {
+    horner<P>(ci, tau, N, D);
+  } else {
+    Table<P> c;
+    load_table<P>(mats + mat * stride, c);
+    horner<P>(c, tau, N, D);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void load_interior(const DevModel& m, Table<P>& ci) {
+  const int im = m.imat < 0 ? 0 : m.imat;
+  load_table<P>(m.mats + im * m.mat_stride, ci);
 }
 
 // ------------------------------------------------------------------ contraction
@@ -212,13 +239,7 @@ __device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0,
   }
 }
 
-// ------------------------------------------------------------------ point evaluation
-struct Eval {
-  float f, gx, gy, gz;
-  int s[3];     // span index s = p + j per axis
-  int block;    // flat block id
-};
-
+// ------------------------------------------------------------------ point location
 // Owning block along one axis: b = max{ i in [0, G-1] : E[i] <= xc }.  The
 // guess from the mean block width is corrected by exact edge comparisons.
 __device__ __forceinline__ int owner(const double* __restrict__ E, int G, double scale, double xc) {
@@ -229,12 +250,23 @@ __device__ __forceinline__ int owner(const double* __restrict__ E, int G, double
   return b;
 }
 
-template <int P, Storage S, bool MULTI>
-__device__ __forceinline__ Eval eval_world(const DevModel& m, __amdgpu_buffer_rsrc_t rs,
-                                           const double (&x)[3]) {
-  Eval r;
-  const DevBlock* B = &m.b0;
-  DevBlock blk;
+// Everything the evaluation needs about one world point after the exact
+// FP64 steps: per axis the span, local coordinate, chain-rule scale and
+// basis table; the first control row and the row strides; the macro cell.
+struct Loc {
+  float tau[3], ds[3];
+  int mat[3], j[3];
+  int block;
+  uint32_t e0, s0, s1;
+  int mc;
+};
+
+// R: span records (global pool or its LDS copy).
+template <int P, bool MULTI>
+__device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
+                                      const double (&x)[3]) {
+  Loc L;
+  const DevBlock* __restrict__ B = &m.b0;
   double u[3];
   if constexpr (MULTI) {
     int b[3];
@@ -245,37 +277,45 @@ __device__ __forceinline__ Eval eval_world(const DevModel& m, __amdgpu_buffer_rs
       xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
       b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
     }
-    r.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
-    blk = m.blocks[r.block];
-    B = &blk;
+    L.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
+    B = m.blocks + L.block;
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
   } else {
-    r.block = 0;
+    L.block = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
   }
-  float N[3][P + 1], D[3][P + 1], ds[3];
-  int j[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     SpanRec rec;
-    j[a] = locate_span(m.rec + B->rec_off[a], B->nsp[a], u[a], rec);
-    r.s[a] = j[a] + P;
-    basis<P>(m.mats + (int64_t)rec.mat * m.mat_stride, local_tau(rec, u[a]), N[a], D[a]);
-    ds[a] = rec.dscale;
+    L.j[a] = locate_span(R + B->rec_off[a], B->nsp[a], u[a], rec);
+    L.tau[a] = local_tau(rec, u[a]);
+    L.ds[a] = rec.dscale;
+    L.mat[a] = rec.mat;
   }
   const uint32_t n1 = (uint32_t)B->n[1], s1 = (uint32_t)B->rs1;
-  const uint32_t e0 =
-      (uint32_t)B->ctrl_off + ((uint32_t)j[0] * n1 + (uint32_t)j[1]) * s1 + (uint32_t)j[2];
+  L.s1 = s1;
+  L.s0 = n1 * s1;
+  L.e0 = (uint32_t)B->ctrl_off + ((uint32_t)L.j[0] * n1 + (uint32_t)L.j[1]) * s1 + (uint32_t)L.j[2];
+  L.mc = B->mc_off + (((L.j[0] >> kMacroShift) * B->mc[1] + (L.j[1] >> kMacroShift)) * B->mc[2] +
+                      (L.j[2] >> kMacroShift));
+  return L;
+}
+
+// Value and world gradient at a located point.
+template <int P, Storage S, bool UNIFORM_STRIDES>
+__device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t rs,
+                                           const float* __restrict__ mats, int stride, int imat,
+                                           const Table<P>& ci) {
+  float N[3][P + 1], D[3][P + 1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) basis<P>(mats, stride, L.mat[a], imat, ci, L.tau[a], N[a], D[a]);
   float f, fx, fy, fz;
-  contract<P, S, !MULTI>(rs, e0, n1 * s1, s1, N[0], D[0], N[1], D[1], N[2], D[2], f, fx, fy, fz);
-  r.f = f;
-  r.gx = fx * ds[0];
-  r.gy = fy * ds[1];
-  r.gz = fz * ds[2];
-  return r;
+  contract<P, S, UNIFORM_STRIDES>(rs, L.e0, L.s0, L.s1, N[0], D[0], N[1], D[1], N[2], D[2], f, fx,
+                                  fy, fz);
+  return make_float4(f, fx * L.ds[0], fy * L.ds[1], fz * L.ds[2]);
 }
 
 // ------------------------------------------------------------------ K1: points
@@ -283,13 +323,15 @@ template <int P, Storage S, bool MULTI>
 __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
                                                           int64_t n, float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
+  Table<P> ci;
+  load_interior<P>(m, ci);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const double x[3] = {(double)xyz[i], (double)xyz[n + i], (double)xyz[2 * n + i]};
-  const Eval e = eval_world<P, S, MULTI>(m, rs, x);
-  reinterpret_cast<float4*>(out)[i] = make_float4(e.f, e.gx, e.gy, e.gz);
-  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(e.s[0], e.s[1], e.s[2], e.block);
+  const Loc L = locate<P, MULTI>(m, m.rec, x);
+  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat, ci);
+  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
 
 // ------------------------------------------------------------------ K3: grid
@@ -314,7 +356,9 @@ __device__ __forceinline__ void axis_basis(const DevModel& m, int a, double uraw
   const double u = clampd(uraw, 0.0, 1.0);
   SpanRec rec;
   j = locate_span(m.rec + m.b0.rec_off[a], m.b0.nsp[a], u, rec);
-  basis<P>(m.mats + (int64_t)rec.mat * m.mat_stride, local_tau(rec, u), N, D);
+  Table<P> c;
+  load_table<P>(m.mats + rec.mat * m.mat_stride, c);
+  horner<P>(c, local_tau(rec, u), N, D);
   ds = rec.dscale;
 }
 
@@ -467,21 +511,59 @@ __device__ __forceinline__ void sample_point(const Ray& ray, double step, int k,
   for (int a = 0; a < 3; ++a) x[a] = ray.o[a] + t * ray.d[a];
 }
 
-template <int P, Storage S, bool MULTI>
+// Transfer-function coordinate s in [0, 255] of a value (shared by the
+// lookup and by the transparency test so both round identically).
+__device__ __forceinline__ float tf_coord(float f, float vmin, float inv_range) {
+  const float s = (f - vmin) * inv_range;
+  return fminf(fmaxf(s, 0.f), 1.f) * 255.f;
+}
+
+__device__ __forceinline__ int tf_entry(float s) { return min((int)floorf(s), 254); }
+
+// LDSREC: single-block model whose span records and basis tables are copied
+// into LDS once per workgroup.
+template <int P, Storage S, bool MULTI, bool LDSREC>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
+  extern __shared__ float4 dyn[];
   __shared__ float4 tf[256];
-  tf[threadIdx.x] = reinterpret_cast<const float4*>(r.tf)[threadIdx.x];
+  __shared__ int zpre[257];      // zpre[i] = number of entries < i with alpha != 0
+  __shared__ int wtot[kBlock / kWave];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const float4 te = reinterpret_cast<const float4*>(r.tf)[tid];
+  tf[tid] = te;
+  const unsigned long long nzm = __ballot(te.w != 0.f);
+  if (lane == 0) wtot[wave] = __popcll(nzm);
+  const SpanRec* R = m.rec;
+  const float* MT = m.mats;
+  if constexpr (LDSREC) {
+    SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
+    float* lm = reinterpret_cast<float*>(lr + m.n_rec);
+    for (int q = tid; q < m.n_rec * 2; q += kBlock)
+      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
+    for (int q = tid; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    R = lr;
+    MT = lm;
+  }
+  Table<P> ci;
+  load_interior<P>(m, ci);
   __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += wtot[w];
+  zpre[tid] = base + __popcll(nzm & ((1ull << lane) - 1ull));
+  if (tid == kBlock - 1) zpre[256] = base + __popcll(nzm);
+  __syncthreads();
+
   const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
   const int tile = xcd_tile(blockIdx.x, tx * ty);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
   const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
   const bool pix = i < r.w && j < r.h;
   Ray ray;
   ray.K = 0;
   if (pix) ray = make_ray(m, r, i, j);
-  float L[3];
+  float L[3] = {0.f, 0.f, 0.f};
   if (pix) {
     const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
 #pragma unroll
@@ -490,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const int64_t pid = (int64_t)j * r.w + i;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
-  int used = 0;
+  int used = 0, nev = 0;
   bool done = false;
   for (int k = 0;; ++k) {
     const bool act = pix && !done && k < ray.K;
@@ -498,35 +580,45 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, k, x);
-    const Eval e = eval_world<P, S, MULTI>(m, rs, x);
-    // transfer function
-    float s = (e.f - r.vmin) * r.inv_range;
-    s = fminf(fmaxf(s, 0.f), 1.f) * 255.f;
-    const int i0 = min((int)floorf(s), 254);
-    const float w = s - (float)i0;
-    const float4 c0 = tf[i0], c1 = tf[i0 + 1];
-    const float cr = fmaf(w, c1.x - c0.x, c0.x);
-    const float cg = fmaf(w, c1.y - c0.y, c0.y);
-    const float cb = fmaf(w, c1.z - c0.z, c0.z);
-    const float alpha = fmaf(w, c1.w - c0.w, c0.w);
-    // headlight Phong, two-sided
-    const float gn = sqrtf(e.gx * e.gx + e.gy * e.gy + e.gz * e.gz);
-    const float inv = 1.f / fmaxf(gn, r.g0);
-    const float diff = fabsf((e.gx * L[0] + e.gy * L[1] + e.gz * L[2]) * inv);
-    float spec = 1.f, bse = diff;
-    for (int ex = r.shininess; ex; ex >>= 1) {
-      if (ex & 1) spec *= bse;
-      bse *= bse;
+    const Loc Lc = locate<P, MULTI>(m, R, x);
+    // Skip the evaluation where the transfer function is zero over the
+    // value bounds of the macro cell: such a sample has alpha = 0 exactly
+    // and leaves C and A unchanged.
+    const float2 bnd = m.mcb[Lc.mc];
+    const bool empty =
+        zpre[tf_entry(tf_coord(bnd.y, r.vmin, r.inv_range)) + 2] ==
+        zpre[tf_entry(tf_coord(bnd.x, r.vmin, r.inv_range))];
+    float alpha = 0.f;
+    if (!empty) {
+      const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat, ci);
+      ++nev;
+      const float s = tf_coord(e.x, r.vmin, r.inv_range);
+      const int i0 = tf_entry(s);
+      const float w = s - (float)i0;
+      const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+      const float cr = fmaf(w, c1.x - c0.x, c0.x);
+      const float cg = fmaf(w, c1.y - c0.y, c0.y);
+      const float cb = fmaf(w, c1.z - c0.z, c0.z);
+      alpha = fmaf(w, c1.w - c0.w, c0.w);
+      // headlight Phong, two-sided
+      const float gn = sqrtf(e.y * e.y + e.z * e.z + e.w * e.w);
+      const float inv = 1.f / fmaxf(gn, r.g0);
+      const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
+      float spec = 1.f, bse = diff;
+      for (int ex = r.shininess; ex; ex >>= 1) {
+        if (ex & 1) spec *= bse;
+        bse *= bse;
+      }
+      const float shade = fmaf(r.kd, diff, r.ka);
+      const float ks = r.ks * spec;
+      // front-to-back over; the opacity update rounds each operation
+      const float om = __fsub_rn(1.f, A);
+      const float ta = __fmul_rn(om, alpha);
+      C0 = fmaf(ta, fmaf(cr, shade, ks), C0);
+      C1 = fmaf(ta, fmaf(cg, shade, ks), C1);
+      C2 = fmaf(ta, fmaf(cb, shade, ks), C2);
+      A = __fadd_rn(A, ta);
     }
-    const float shade = fmaf(r.kd, diff, r.ka);
-    const float ks = r.ks * spec;
-    // front-to-back over; the opacity update rounds each operation
-    const float om = __fsub_rn(1.f, A);
-    const float ta = __fmul_rn(om, alpha);
-    C0 = fmaf(ta, fmaf(cr, shade, ks), C0);
-    C1 = fmaf(ta, fmaf(cg, shade, ks), C1);
-    C2 = fmaf(ta, fmaf(cb, shade, ks), C2);
-    A = __fadd_rn(A, ta);
     used = k + 1;
     if (r.alpha) r.alpha[pid * r.alpha_stride + k] = alpha;
     done = A >= r.ert_alpha;
@@ -534,6 +626,7 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   if (pix) {
     reinterpret_cast<float4*>(r.rgba)[pid] = make_float4(C0, C1, C2, A);
     if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, used);
+    if (r.neval) r.neval[pid] = nev;
   }
 }
 
@@ -559,13 +652,19 @@ static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Span records and tables go to LDS when they fit this budget.
+constexpr int kLdsRecBytes = 40 * 1024;
+
 template <int P, Storage S>
 static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   if (multi)
-    hipLaunchKernelGGL((render_k<P, S, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+    hipLaunchKernelGGL((render_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else if (lds <= (size_t)kLdsRecBytes)
+    hipLaunchKernelGGL((render_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else
-    hipLaunchKernelGGL((render_k<P, S, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+    hipLaunchKernelGGL((render_k<P, S, false, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   return hipGetLastError();
 }
 

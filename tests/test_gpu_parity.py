@@ -141,12 +141,15 @@ def test_decode_grid_ragged_unsorted_tables(mfa, dev, c1):
 def check_render(mfa, dev, model, cam, params, W, H, storage="f32", ref_model=None):
     ref_model = ref_model or model
     with mfa.Model(model, storage) as M:
-        rgba, ns, al = mfa.render_frame(M, cam, params, W, H, nsamp=True, alpha=True, device=dev)
-        rgba, ns, al = rgba.cpu().numpy(), ns.cpu().numpy(), al.cpu().numpy()
+        rgba, ns, al, ne = mfa.render_frame(M, cam, params, W, H, nsamp=True, alpha=True,
+                                            neval=True, device=dev)
+        rgba, ns, al, ne = rgba.cpu().numpy(), ns.cpu().numpy(), al.cpu().numpy(), ne.cpu().numpy()
     ref = orr.render(orr.model_field(ref_model), model.lo, model.hi, cam, params, W, H,
                      record_alpha=True)
     K = ns[..., 0].reshape(-1)
     used = ns[..., 1].reshape(-1)
+    ne = ne.reshape(-1)
+    assert np.all(ne <= used) and np.all(ne >= 0)
     np.testing.assert_array_equal(K, ref["K"])                      # schedule: exact
     # exact FP32 replay of the kernel's own opacities: identical decisions
     alpha = al.reshape(W * H, -1)
@@ -163,7 +166,7 @@ def check_render(mfa, dev, model, cam, params, W, H, storage="f32", ref_model=No
     assert rmse <= 1e-5, f"image RMSE {rmse:.3e}"
     assert diff.max(initial=0.0) <= 1e-3, f"image max-abs {diff.max():.3e}"
     return dict(band=int(band.sum()), rmse=rmse, samples=int(used.sum()),
-                terminated=int((used < K).sum()))
+                terminated=int((used < K).sum()), evaluated=int(ne.sum()))
 
 
 def test_render_c1_ortho_128(mfa, dev, c1):
@@ -173,6 +176,7 @@ def test_render_c1_ortho_128(mfa, dev, c1):
     announce("render c1 128x128 ortho")
     r = check_render(mfa, dev, c1, cam, params, W, H)
     assert r["samples"] > 100000 and r["terminated"] > 100
+    assert r["evaluated"] < r["samples"]         # transparent cells were skipped
 
 
 def test_render_c1_perspective_ragged(mfa, dev, c1):
@@ -280,8 +284,10 @@ def test_c2_render_1024_sampled(mfa, dev, c2):
     params = synth.render_params(c2)
     announce("render c2 1024x1024 perspective (sampled)")
     with mfa.Model(c2, "f32") as M:
-        rgba, ns = mfa.render_frame(M, cam, params, W, H, nsamp=True, device=dev)
+        rgba, ns, ne = mfa.render_frame(M, cam, params, W, H, nsamp=True, neval=True, device=dev)
         rgba, ns = rgba.cpu().numpy().reshape(-1, 4), ns.cpu().numpy().reshape(-1, 2)
+        ne = ne.cpu().numpy().reshape(-1)
+    assert np.all(ne <= ns[:, 1]) and ne.sum() < 0.6 * ns[:, 1].sum()
     rng = np.random.default_rng(8)
     pix = np.stack([rng.integers(0, H, 240), rng.integers(0, W, 240)], axis=1)
     pix = np.concatenate([pix, [[0, 0], [H - 1, W - 1], [H // 2, W // 2]]])
