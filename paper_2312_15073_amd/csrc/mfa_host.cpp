@@ -103,6 +103,19 @@ static float f16_value(uint16_t h) {
 
 static int elem_size(mfa_dtype d) { return d == MFA_F32 ? 4 : 2; }
 
+// FP16 pattern of the largest half <= v (down) or smallest half >= v (up);
+// beyond the half range the result is the corresponding infinity.
+static uint16_t f16_directed(float v, bool up) {
+  uint16_t h = to_f16(v);
+  const float hv = f16_value(h);
+  if (up ? hv >= v : hv <= v) return h;
+  // step one ulp in the needed direction (sign-magnitude encoding)
+  const bool neg = (h & 0x8000u) != 0;
+  if ((h & 0x7FFFu) == 0) return up ? 0x0001u : 0x8001u;     // +-0 -> +-smallest subnormal
+  const bool away = up != neg;            // moving away from zero?
+  return (uint16_t)(away ? h + 1 : h - 1);
+}
+
 // ------------------------------------------------------------------ basis polynomials
 // Pieces of the degree-p basis functions active on span s as polynomials in
 // tau = (u - T[s]) / h: the Cox-de Boor recursion applied to polynomials,
@@ -147,6 +160,36 @@ static std::vector<float> span_table(const double* T, int p, int s) {
   return out;
 }
 
+// The uniform interior table of degree p as a vector (see UniformTable).
+template <int P>
+static std::vector<float> uniform_table_p() {
+  constexpr UniformTable<P> U{};
+  return std::vector<float>(U.c, U.c + mat_stride(P));
+}
+
+static std::vector<float> uniform_table(int p) {
+  switch (p) {
+    case 1: return uniform_table_p<1>();
+    case 2: return uniform_table_p<2>();
+    case 3: return uniform_table_p<3>();
+    case 4: return uniform_table_p<4>();
+    case 5: return uniform_table_p<5>();
+    default: return {};
+  }
+}
+
+// Equal to the canonical table up to FP64 rounding of the knots: within
+// 1e-6 of its largest coefficient, entry by entry (tables of other span
+// shapes differ by O(0.1)).
+static bool near_table(const std::vector<float>& a, const std::vector<float>& b) {
+  if (a.size() != b.size()) return false;
+  float scale = 0.f;
+  for (float v : b) scale = std::max(scale, std::fabs(v));
+  for (size_t q = 0; q < a.size(); ++q)
+    if (!(std::fabs(a[q] - b[q]) <= 1e-6f * scale)) return false;
+  return true;
+}
+
 // ------------------------------------------------------------------ model
 struct mfa_model_s {
   int device = 0;
@@ -166,7 +209,7 @@ struct mfa_model_s {
   float* d_mats = nullptr;
   DevBlock* d_blocks = nullptr;
   double* d_edges = nullptr;
-  float2* d_mcb = nullptr;
+  uint32_t* d_mcb = nullptr;
   int64_t device_bytes = 0;
   DevModel dm{};
 };
@@ -204,14 +247,15 @@ static void default_knots(int n, int p, double* T) {
   for (int j = 1; j < n - p; ++j) T[p + j] = (double)j / nsp;
 }
 
-// Value bounds per macro cell (kMacro^3 spans) of one block: min and max of
+// Value bounds per macro cell (2^shift spans per axis) of one block: min and max of
 // the stored control points that act on any span of the cell (the spline is
 // a convex combination of them), by windowed min/max one axis at a time.
-static void macro_bounds(const std::vector<float>& V, const int n[3], int p, const int mc[3],
-                         std::vector<float2>& out) {
+static void macro_bounds(const std::vector<float>& V, const int n[3], int p, int shift,
+                         const int mc[3], std::vector<float2>& out) {
+  const int mk = 1 << shift;
   auto win = [&](int a, int c, int& lo, int& hi) {
-    lo = c * kMacro;
-    hi = std::min(c * kMacro + kMacro - 1, n[a] - p - 1) + p;
+    lo = c * mk;
+    hi = std::min(c * mk + mk - 1, n[a] - p - 1) + p;
   };
   const int n0 = n[0], n1 = n[1], n2 = n[2];
   std::vector<float> lo2((size_t)n0 * n1 * mc[2]), hi2(lo2.size());
@@ -341,6 +385,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   std::vector<SpanRec> recs;
   std::vector<float> mats;
   std::map<std::vector<float>, int> mat_ids;
+  const std::vector<float> canon = uniform_table(p);
   int64_t off = 0;
   m->n.resize(3 * nb);
   m->coff.resize(nb);
@@ -354,13 +399,14 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     DevBlock& D = dblk[b];
     for (int a = 0; a < 3; ++a) {
       D.lo[a] = edges[a][bi[a]];
-      D.inv_ext[a] = 1.0 / (edges[a][bi[a] + 1] - edges[a][bi[a]]);
+      D.ext[a] = edges[a][bi[a] + 1] - edges[a][bi[a]];
+      D.inv_ext[a] = 1.0 / D.ext[a];
       D.n[a] = B.n_ctrl[a];
       D.nsp[a] = B.n_ctrl[a] - p;
       m->n[3 * b + a] = B.n_ctrl[a];
     }
     D.rs1 = (es == 2) ? (B.n_ctrl[2] + (B.n_ctrl[2] & 1)) : B.n_ctrl[2];
-    for (int a = 0; a < 3; ++a) D.mc[a] = (D.nsp[a] + kMacro - 1) / kMacro;
+
     D.ctrl_off = off;
     m->coff[b] = off;
     m->rs1[b] = D.rs1;
@@ -386,6 +432,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
         r.dscale = (float)(r.inv_h * D.inv_ext[a]);
         std::vector<float> tab = (r.t_next > r.t) ? span_table(T.data(), p, s)
                                                   : std::vector<float>(mat_stride(p), 0.f);
+        if (near_table(tab, canon)) tab = canon;
         auto it = mat_ids.find(tab);
         if (it == mat_ids.end()) {
           const int id = (int)mat_ids.size();
@@ -400,6 +447,23 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     }
   }
   if (recs.size() > (size_t)INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "too many spans"); }
+  // Finest macro cells whose bounds (4 bytes each) take no more memory than
+  // the larger of the stored control points and 16 MiB.
+  int mc_shift = kMaxMacroShift;
+  for (int sh = 0; sh <= kMaxMacroShift; ++sh) {
+    int64_t cells = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t c = 1;
+      for (int a = 0; a < 3; ++a) c *= (dblk[b].nsp[a] + (1 << sh) - 1) >> sh;
+      cells += c;
+    }
+    if (cells * 4 <= std::max<int64_t>(off * es, 16ll << 20)) {
+      mc_shift = sh;
+      break;
+    }
+  }
+  for (int64_t b = 0; b < nb; ++b)
+    for (int a = 0; a < 3; ++a) dblk[b].mc[a] = (dblk[b].nsp[a] + (1 << mc_shift) - 1) >> mc_shift;
   const int64_t pool_bytes = off * es + 64;       // tail pad: 16-bit rows read one word ahead
   if (pool_bytes > 0xFFFFFFFFll) {
     free_model(m);
@@ -448,7 +512,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       }
     }
     dblk[b].mc_off = (int32_t)mcb.size();
-    macro_bounds(V, B.n_ctrl, p, dblk[b].mc, mcb);
+    macro_bounds(V, B.n_ctrl, p, mc_shift, dblk[b].mc, mcb);
   }
   m->vmin = vmin;
   m->vmax = vmax;
@@ -456,17 +520,13 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   // tables and sums in FP32 stay within ~1e-6 of the exact convex
   // combination relative to max |P|).
   const float margin = 1e-4f * std::fmax(std::fabs(vmin), std::fabs(vmax));
-  for (float2& c : mcb) {
-    c.x -= margin;
-    c.y += margin;
-  }
-  // most frequent basis table (interior spans)
-  std::vector<int64_t> mat_count(mat_ids.size(), 0);
-  for (const SpanRec& r : recs) ++mat_count[r.mat];
-  int imat = -1;
-  int64_t best = 0;
-  for (size_t q = 0; q < mat_count.size(); ++q)
-    if (mat_count[q] > best) { best = mat_count[q]; imat = (int)q; }
+  std::vector<uint32_t> mcb16(mcb.size());
+  for (size_t q = 0; q < mcb.size(); ++q)
+    mcb16[q] = (uint32_t)f16_directed(mcb[q].x - margin, false) |
+               ((uint32_t)f16_directed(mcb[q].y + margin, true) << 16);
+  // the uniform interior table, evaluated from literals by the kernels
+  const auto ic = mat_ids.find(canon);
+  const int imat = ic == mat_ids.end() ? -1 : ic->second;
 
   std::vector<double> edge_pool;
   int edge_off[3];
@@ -481,7 +541,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_mats, mats.data(), mats.size() * sizeof(float), m, "basis upload")) != MFA_OK ||
       (st = upload(&m->d_blocks, dblk.data(), dblk.size() * sizeof(DevBlock), m, "block upload")) != MFA_OK ||
       (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK ||
-      (st = upload(&m->d_mcb, mcb.data(), mcb.size() * sizeof(float2), m, "bounds upload")) != MFA_OK) {
+      (st = upload(&m->d_mcb, mcb16.data(), mcb16.size() * sizeof(uint32_t), m, "bounds upload")) != MFA_OK) {
     free_model(m);
     return st;
   }
@@ -506,6 +566,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   dm.n_mats = (int)mat_ids.size();
   dm.n_rec = (int)recs.size();
   dm.imat = imat;
+  dm.mc_shift = mc_shift;
   dm.mcb = m->d_mcb;
   dm.b0 = dblk[0];
   *out = m;
@@ -661,6 +722,7 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
   r.sx = cam->sx;
   r.sy = cam->sy;
   r.step = step;
+  r.inv_step = 1.0 / step;
   hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   return MFA_OK;

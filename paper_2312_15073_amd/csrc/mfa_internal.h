@@ -38,15 +38,16 @@ struct DevBlock {
   int32_t rec_off[3];   // index of the block's span 0 record per axis
   int32_t rs1;          // row stride along axis 1 in elements (n2, padded to
                         // even for 16-bit storage so rows pair into dwords)
-  int32_t mc[3];        // macro cells per axis = ceil(nsp / kMacro)
+  int32_t mc[3];        // macro cells per axis = ceil(nsp / 2^mc_shift)
   int32_t mc_off;       // index of the block's first macro cell in the bounds pool
+  double ext[3];        // hi - lo (estimates of cell exits only)
 };
-static_assert(sizeof(DevBlock) == 112, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 136, "DevBlock layout");
 
 // Spans per axis grouped into one macro cell for the value bounds used to
-// skip samples that the transfer function makes fully transparent.
-constexpr int kMacroShift = 2;
-constexpr int kMacro = 1 << kMacroShift;
+// skip samples that the transfer function makes fully transparent: 2^shift,
+// shift in [0, kMaxMacroShift], chosen per model (DevModel::mc_shift).
+constexpr int kMaxMacroShift = 2;
 
 struct DevModel {
   const void* ctrl;
@@ -61,9 +62,11 @@ struct DevModel {
   int32_t mat_stride;    // floats per basis table
   int32_t n_mats;        // basis tables in the pool
   int32_t n_rec;         // span records in the pool
-  int32_t imat;          // most frequent basis table (interior spans), or -1
-  const float2* mcb;     // per macro cell (lo, hi) bounds of the stored values,
-                         // widened by a margin covering FP32 evaluation error
+  int32_t imat;          // id of the uniform interior table (UniformTable), or -1
+  int32_t mc_shift;      // log2 of the spans per macro cell and axis
+  const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
+                         // two FP16 halves rounded outward, widened by a margin
+                         // covering FP32 evaluation error
   double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
   double box_lo[3];
   double box_hi[3];
@@ -79,6 +82,49 @@ enum class Storage : int { F32 = 1, BF16 = 2, F16 = 3 };
 inline constexpr int mat_stride(int p) {
   return (((p + 1) * (p + 1) + (p + 1) * p) + 3) / 4 * 4;
 }
+
+// The basis table of an interior span of uniform knots (the uniform
+// B-spline pieces of degree p), computed at compile time by the Cox-de Boor
+// recursion on polynomials in tau over the integer knots -p..p+1, in FP64,
+// then rounded to FP32.  Host and kernels use this one routine, so a span
+// whose table equals it can be evaluated from literals.
+template <int P>
+struct UniformTable {
+  float c[mat_stride(P)];
+  constexpr UniformTable() : c() {
+    double N[P + 1][P + 1] = {};   // N[r][m]: function r, power m of tau
+    double M[P + 1][P + 1] = {};
+    N[0][0] = 1.0;
+    for (int q = 1; q <= P; ++q) {
+      for (int r = 0; r <= P; ++r)
+        for (int m = 0; m <= P; ++m) M[r][m] = 0.0;
+      for (int r = 0; r <= q; ++r) {
+        // knots t_i = i relative to the span start; function i = r - q
+        const int i = r - q;
+        if (r >= 1) {            // (u - t_i) / q * N_{i,q-1}, u = tau
+          const double a0 = (0.0 - i) / q, a1 = 1.0 / q;
+          for (int m = 0; m <= P; ++m) {
+            M[r][m] += a0 * N[r - 1][m];
+            if (m + 1 <= P) M[r][m + 1] += a1 * N[r - 1][m];
+          }
+        }
+        if (r <= q - 1) {        // (t_{i+q+1} - u) / q * N_{i+1,q-1}
+          const double b0 = (double)(i + q + 1) / q, b1 = -1.0 / q;
+          for (int m = 0; m <= P; ++m) {
+            M[r][m] += b0 * N[r][m];
+            if (m + 1 <= P) M[r][m + 1] += b1 * N[r][m];
+          }
+        }
+      }
+      for (int r = 0; r <= P; ++r)
+        for (int m = 0; m <= P; ++m) N[r][m] = M[r][m];
+    }
+    for (int r = 0; r <= P; ++r)
+      for (int m = 0; m <= P; ++m) c[r * (P + 1) + m] = (float)N[r][m];
+    for (int r = 0; r <= P; ++r)
+      for (int m = 0; m < P; ++m) c[(P + 1) * (P + 1) + r * P + m] = (float)((m + 1) * N[r][m + 1]);
+  }
+};
 
 struct GridArgs {
   const double* axis[3];
@@ -104,6 +150,7 @@ struct RenderArgs {
   float ka, kd, ks, g0;
   double eye[3], fwd[3], right[3], up[3];
   double sx, sy, step;
+  double inv_step;        // 1 / step (estimates only)
 };
 
 }  // namespace mfa

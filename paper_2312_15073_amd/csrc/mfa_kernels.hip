@@ -177,26 +177,19 @@ __device__ __forceinline__ void horner(const Table<P>& c, float tau, float (&N)[
   }
 }
 
-// The most frequent table of the model (the interior spans of uniform knots)
-// is held in scalar registers (ci); per-lane tables are loaded only when a
-// lane of the wave sits on another span type.
+// Spans with the uniform interior table (imat) use it as literals; per-lane
+// tables are loaded only when a lane of the wave sits on another span type.
 template <int P>
 __device__ __forceinline__ void basis(const float* __restrict__ mats, int stride, int mat, int imat,
-                                      const Table<P>& ci, float tau, float (&N)[P + 1],
-                                      float (&D)[P + 1]) {
+                                      float tau, float (&N)[P + 1], float (&D)[P + 1]) {
   if (__all(mat == imat)) {
-    horner<P>(ci, tau, N, D);
+    constexpr UniformTable<P> U{};
+    horner<P>(U.c, tau, N, D);
   } else {
     Table<P> c;
     load_table<P>(mats + mat * stride, c);
     horner<P>(c, tau, N, D);
   }
-}
-
-template <int P>
-__device__ __forceinline__ void load_interior(const DevModel& m, Table<P>& ci) {
-  const int im = m.imat < 0 ? 0 : m.imat;
-  load_table<P>(m.mats + im * m.mat_stride, ci);
 }
 
 // ------------------------------------------------------------------ contraction
@@ -299,19 +292,18 @@ __device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restri
   L.s1 = s1;
   L.s0 = n1 * s1;
   L.e0 = (uint32_t)B->ctrl_off + ((uint32_t)L.j[0] * n1 + (uint32_t)L.j[1]) * s1 + (uint32_t)L.j[2];
-  L.mc = B->mc_off + (((L.j[0] >> kMacroShift) * B->mc[1] + (L.j[1] >> kMacroShift)) * B->mc[2] +
-                      (L.j[2] >> kMacroShift));
+  const int sh = m.mc_shift;
+  L.mc = B->mc_off + (((L.j[0] >> sh) * B->mc[1] + (L.j[1] >> sh)) * B->mc[2] + (L.j[2] >> sh));
   return L;
 }
 
 // Value and world gradient at a located point.
 template <int P, Storage S, bool UNIFORM_STRIDES>
 __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t rs,
-                                           const float* __restrict__ mats, int stride, int imat,
-                                           const Table<P>& ci) {
+                                           const float* __restrict__ mats, int stride, int imat) {
   float N[3][P + 1], D[3][P + 1];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) basis<P>(mats, stride, L.mat[a], imat, ci, L.tau[a], N[a], D[a]);
+  for (int a = 0; a < 3; ++a) basis<P>(mats, stride, L.mat[a], imat, L.tau[a], N[a], D[a]);
   float f, fx, fy, fz;
   contract<P, S, UNIFORM_STRIDES>(rs, L.e0, L.s0, L.s1, N[0], D[0], N[1], D[1], N[2], D[2], f, fx,
                                   fy, fz);
@@ -323,14 +315,12 @@ template <int P, Storage S, bool MULTI>
 __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
                                                           int64_t n, float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
-  Table<P> ci;
-  load_interior<P>(m, ci);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const double x[3] = {(double)xyz[i], (double)xyz[n + i], (double)xyz[2 * n + i]};
   const Loc L = locate<P, MULTI>(m, m.rec, x);
-  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat, ci);
+  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
 
@@ -546,8 +536,6 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
     R = lr;
     MT = lm;
   }
-  Table<P> ci;
-  load_interior<P>(m, ci);
   __syncthreads();
   int base = 0;
   for (int w = 0; w < wave; ++w) base += wtot[w];
@@ -574,6 +562,8 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
   int used = 0, nev = 0;
   bool done = false;
+  int last_mc = -1;
+  bool last_empty = false;
   for (int k = 0;; ++k) {
     const bool act = pix && !done && k < ray.K;
     if (__ballot(act) == 0) break;                 // whole wave finished
@@ -584,13 +574,19 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
     // Skip the evaluation where the transfer function is zero over the
     // value bounds of the macro cell: such a sample has alpha = 0 exactly
     // and leaves C and A unchanged.
-    const float2 bnd = m.mcb[Lc.mc];
-    const bool empty =
-        zpre[tf_entry(tf_coord(bnd.y, r.vmin, r.inv_range)) + 2] ==
-        zpre[tf_entry(tf_coord(bnd.x, r.vmin, r.inv_range))];
+    // The verdict is kept while the ray stays in the same cell.
+    if (Lc.mc != last_mc) {
+      const uint32_t bh = m.mcb[Lc.mc];
+      const float blo = __half2float(__ushort_as_half((unsigned short)(bh & 0xFFFFu)));
+      const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
+      last_empty = zpre[tf_entry(tf_coord(bhi, r.vmin, r.inv_range)) + 2] ==
+                   zpre[tf_entry(tf_coord(blo, r.vmin, r.inv_range))];
+      last_mc = Lc.mc;
+    }
+    const bool empty = last_empty;
     float alpha = 0.f;
     if (!empty) {
-      const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat, ci);
+      const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat);
       ++nev;
       const float s = tf_coord(e.x, r.vmin, r.inv_range);
       const int i0 = tf_entry(s);

@@ -187,6 +187,15 @@ def test_render_c1_perspective_ragged(mfa, dev, c1):
     check_render(mfa, dev, c1, cam, params, W, H)
 
 
+def test_render_c1_axis_aligned_rays(mfa, dev, c1):
+    W, H = 80, 72
+    cam = synth.axis_camera(W, H, axis=2, half_extent=0.55)     # two direction components are 0
+    params = synth.render_params(c1)
+    announce("render c1 80x72 axis-aligned ortho")
+    r = check_render(mfa, dev, c1, cam, params, W, H)
+    assert r["evaluated"] < r["samples"]
+
+
 def test_render_closed_form_constant_opacity(mfa, dev):
     T = synth.clamped_uniform_knots(8, 3)
     P = synth.linear_precision_ctrl([T] * 3, [3] * 3, (0.0, 1.0, 0.0, 0.0))
