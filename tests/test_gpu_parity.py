@@ -309,3 +309,104 @@ def test_c2_render_1024_sampled(mfa, dev, c2):
     diff = np.abs(rgba[flat][~band] - ref["rgba"][~band])
     assert diff.max(initial=0) <= 1e-3 and np.sqrt(np.mean(diff ** 2)) <= 1e-5
     assert ns[:, 1].sum() > 1e7          # a real frame: many samples
+
+
+# ------------------------------------------------------------------ multi-block models
+def small_multiblock(seed=21, p=3):
+    """3x2x2 blocks with uneven edges and uneven control-point counts, each
+    block fitted to one Gaussian-sum field at its Greville abscissae."""
+    rng = np.random.default_rng(seed)
+    field = synth.field_c1(seed)
+    edges = [np.array([0.0, 0.3, 0.55, 1.0]), np.array([0.0, 0.6, 1.0]), np.array([0.0, 0.45, 1.0])]
+    blocks = []
+    for b0 in range(3):
+        for b1 in range(2):
+            for b2 in range(2):
+                n = [int(v) for v in rng.integers(p + 2, 14, size=3)]
+                knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
+                lo = np.array([edges[0][b0], edges[1][b1], edges[2][b2]])
+                hi = np.array([edges[0][b0 + 1], edges[1][b1 + 1], edges[2][b2 + 1]])
+                xs = [lo[a] + synth.greville(knots[a], p, n[a]) * (hi[a] - lo[a]) for a in range(3)]
+                blocks.append(synth.BlockSpec([p] * 3, knots, field.value_separable(*xs)))
+    return synth.ModelSpec([3, 2, 2], np.zeros(3), np.ones(3), edges, blocks, voxel=1.0 / 63)
+
+
+def test_decode_points_multiblock(mfa, dev):
+    model = small_multiblock()
+    rng = np.random.default_rng(4)
+    pts = [rng.random((30000, 3)).astype(np.float32)]
+    for a in range(3):                      # points exactly on block faces
+        for e in model.edges[a]:
+            v = rng.random((50, 3)).astype(np.float32)
+            v[:, a] = np.float32(e)
+            pts.append(v)
+    pts.append(np.array([[-0.5, 0.5, 0.5], [1.5, 2.0, -3.0]], dtype=np.float32))
+    pts = np.concatenate(pts)
+    announce(f"decode_points multi-block 3x2x2 n={len(pts)}")
+    with mfa.Model(model, "f32") as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts.T, dev), dbg=True)
+        out, dbg = out.cpu().numpy(), dbg.cpu().numpy()
+    ref = oracle_points(model, pts)
+    flat = (ref["blocks"][:, 0] * 2 + ref["blocks"][:, 1]) * 2 + ref["blocks"][:, 2]
+    np.testing.assert_array_equal(dbg[:, 3], flat)
+    np.testing.assert_array_equal(dbg[:, :3], ref["spans"])
+    pmax = max(np.abs(b.ctrl).max() for b in model.blocks)
+    assert_values_close(out, ref["f"], ref["grad"], pmax)
+
+
+@pytest.mark.parametrize("kind", ["ortho", "persp"])
+def test_render_multiblock_rays_cross_blocks(mfa, dev, kind):
+    model = small_multiblock()
+    W, H = 72, 56
+    cam = (synth.ortho_camera(W, H, az_deg=50, el_deg=25) if kind == "ortho"
+           else synth.perspective_camera(W, H, az_deg=-40, el_deg=30))
+    params = synth.render_params(model)
+    announce(f"render multi-block {kind} {W}x{H}")
+    r = check_render(mfa, dev, model, cam, params, W, H)
+    assert r["samples"] > 20000
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return synth.model_c4()
+
+
+def test_c4_points_sampled(mfa, dev, c4):
+    import torch
+    n = 20_000_000
+    pts = synth.random_points(n, seed=14)
+    announce(f"decode_points 8x8x8-block model n={n} (sampled)")
+    with mfa.Model(c4, "f32") as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts, dev), dbg=True)
+        rng = np.random.default_rng(9)
+        k = np.concatenate([rng.integers(0, n, size=20000), [0, n - 1]])
+        kt = torch.as_tensor(k, device=dev)
+        got, gd = out[kt].cpu().numpy(), dbg[kt].cpu().numpy()
+    ref = oracle_points(c4, pts[:, k].T)
+    flat = (ref["blocks"][:, 0] * 8 + ref["blocks"][:, 1]) * 8 + ref["blocks"][:, 2]
+    np.testing.assert_array_equal(gd[:, 3], flat)
+    np.testing.assert_array_equal(gd[:, :3], ref["spans"])
+    assert_values_close(got, ref["f"], ref["grad"], max(np.abs(b.ctrl).max() for b in c4.blocks))
+
+
+def test_c4_render_2048_sampled(mfa, dev, c4):
+    W = H = 2048
+    cam = synth.perspective_camera(W, H, az_deg=35, el_deg=25)
+    params = synth.render_params(c4, max_samples=2048)
+    announce("render 8x8x8-block model 2048x2048 (sampled)")
+    with mfa.Model(c4, "f32") as M:
+        rgba, ns, ne = mfa.render_frame(M, cam, params, W, H, nsamp=True, neval=True, device=dev)
+        rgba, ns = rgba.cpu().numpy().reshape(-1, 4), ns.cpu().numpy().reshape(-1, 2)
+        ne = ne.cpu().numpy().reshape(-1)
+    rng = np.random.default_rng(10)
+    pix = np.stack([rng.integers(0, H, 120), rng.integers(0, W, 120)], axis=1)
+    pix = np.concatenate([pix, [[H // 2, W // 2], [H // 3, W // 2]]])
+    ref = orr.render(orr.model_field(c4), c4.lo, c4.hi, cam, params, W, H, pixels=pix,
+                     record_alpha=True)
+    flat = pix[:, 0] * W + pix[:, 1]
+    np.testing.assert_array_equal(ns[flat, 0], ref["K"])
+    band = composite_band(ref["alpha"], ref["used"], float(params["ert_alpha"]))
+    np.testing.assert_array_equal(ns[flat, 1][~band], ref["used"][~band])
+    diff = np.abs(rgba[flat][~band] - ref["rgba"][~band])
+    assert diff.max(initial=0) <= 1e-3 and np.sqrt(np.mean(diff ** 2)) <= 1e-5
+    assert np.all(ne <= ns[:, 1]) and ns[:, 1].sum() > 1e8
