@@ -20,6 +20,8 @@ hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi,
                                 int64_t n, float* out, int32_t* dbg, hipStream_t st);
 hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
                               hipStream_t st);
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
+                                const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st);
 hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
                          hipStream_t st);
 }  // namespace mfa
@@ -211,12 +213,15 @@ struct mfa_model_s {
   double* d_edges = nullptr;
   uint32_t* d_mcb = nullptr;
   int64_t device_bytes = 0;
+  int64_t n_buckets = 0;        // sort buckets (block, tile)
+  void* d_ws = nullptr;         // scratch of sorted decodes, grown on demand
+  size_t ws_bytes = 0;
   DevModel dm{};
 };
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -464,6 +469,15 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   }
   for (int64_t b = 0; b < nb; ++b)
     for (int a = 0; a < 3; ++a) dblk[b].mc[a] = (dblk[b].nsp[a] + (1 << mc_shift) - 1) >> mc_shift;
+  int64_t buckets = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    dblk[b].tile_off = (int32_t)buckets;
+    int64_t t = 1;
+    for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << kTileShift) - 1) >> kTileShift;
+    buckets += t;
+  }
+  if (buckets > INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "too many sort buckets"); }
+  m->n_buckets = buckets;
   const int64_t pool_bytes = off * es + 64;       // tail pad: 16-bit rows read one word ahead
   if (pool_bytes > 0xFFFFFFFFll) {
     free_model(m);
@@ -631,11 +645,50 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
   if (!m) return fail(MFA_E_ARG, "null model");
   if (n < 0 || n >= (1ll << 31)) return fail(MFA_E_ARG, "n = %lld out of range", (long long)n);
   if (flags & ~MFA_DECODE_SORTED) return fail(MFA_E_ARG, "unknown flags 0x%x", flags);
-  if (flags & MFA_DECODE_SORTED) return fail(MFA_E_UNSUPPORTED, "sorted decode not built yet");
   if (n == 0) return MFA_OK;
   if (!xyz || !out) return fail(MFA_E_ARG, "null xyz/out");
   mfa_status st = check_device(m);
   if (st != MFA_OK) return st;
+  if (flags & MFA_DECODE_SORTED) {
+    // scratch: key, rank, perm (4 B each), sorted xyz (12 B) per point;
+    // histogram, offsets and scan partials per bucket
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t nbk = (size_t)m->n_buckets;
+    const size_t nparts = (nbk + 2047) / 2048;
+    const size_t o_key = 0, o_rank = o_key + al(4 * (size_t)n), o_perm = o_rank + al(4 * (size_t)n);
+    const size_t o_xyz = o_perm + al(4 * (size_t)n), o_hist = o_xyz + al(12 * (size_t)n);
+    const size_t o_offs = o_hist + al(4 * nbk), o_part = o_offs + al(4 * nbk);
+    const size_t need = o_part + al(4 * nparts);
+    if (need > m->ws_bytes) {
+      if (m->d_ws) {
+        hipError_t fe = hipFree(m->d_ws);   // waits for work still using it
+        m->d_ws = nullptr;
+        m->device_bytes -= (int64_t)m->ws_bytes;
+        m->ws_bytes = 0;
+        if (fe != hipSuccess) return hip_fail(fe, "scratch free");
+      }
+      hipError_t ae = hipMalloc(&m->d_ws, need);
+      if (ae != hipSuccess) return hip_fail(ae, "scratch for sorted decode");
+      m->ws_bytes = need;
+      m->device_bytes += (int64_t)need;
+    }
+    uint8_t* w = (uint8_t*)m->d_ws;
+    SortArgs sa{};
+    sa.xyz = xyz;
+    sa.n = n;
+    sa.key = (uint32_t*)(w + o_key);
+    sa.rank = (uint32_t*)(w + o_rank);
+    sa.perm = (uint32_t*)(w + o_perm);
+    sa.xyz_s = (float*)(w + o_xyz);
+    sa.hist = (uint32_t*)(w + o_hist);
+    sa.offs = (uint32_t*)(w + o_offs);
+    sa.part = (uint32_t*)(w + o_part);
+    sa.nb = (int32_t)nbk;
+    hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), m->nblocks > 1, sa, out, dbg,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sorted decode launch");
+    return MFA_OK;
+  }
   hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), m->nblocks > 1, xyz, n, out,
                                       dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_points launch");

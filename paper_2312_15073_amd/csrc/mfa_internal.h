@@ -41,8 +41,14 @@ struct DevBlock {
   int32_t mc[3];        // macro cells per axis = ceil(nsp / 2^mc_shift)
   int32_t mc_off;       // index of the block's first macro cell in the bounds pool
   double ext[3];        // hi - lo (estimates of cell exits only)
+  int32_t tile_off;     // first sort bucket of the block
+  int32_t pad;
 };
-static_assert(sizeof(DevBlock) == 136, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 144, "DevBlock layout");
+
+// Points sorted for decode are grouped by (block, tile); a tile spans
+// 2^kTileShift knot spans per axis.
+constexpr int kTileShift = 2;
 
 // Spans per axis grouped into one macro cell for the value bounds used to
 // skip samples that the transfer function makes fully transparent: 2^shift,
@@ -124,6 +130,19 @@ struct UniformTable {
     for (int r = 0; r <= P; ++r)
       for (int m = 0; m < P; ++m) c[(P + 1) * (P + 1) + r * P + m] = (float)((m + 1) * N[r][m + 1]);
   }
+};
+
+struct SortArgs {
+  const float* xyz;      // input SoA [3][n]
+  int64_t n;
+  uint32_t* key;         // [n] bucket of each point
+  uint32_t* rank;        // [n] position among the points of its bucket
+  uint32_t* perm;        // [n] sorted position -> input index
+  float* xyz_s;          // [3][n] coordinates in sorted order
+  uint32_t* hist;        // [nb] points per bucket
+  uint32_t* offs;        // [nb] exclusive prefix of hist
+  uint32_t* part;        // [ceil(nb / chunk)] chunk sums of the scan
+  int32_t nb;            // buckets
 };
 
 struct GridArgs {

@@ -324,6 +324,161 @@ __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const floa
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
 
+// Workgroup i runs on XCD i % 8: deal contiguous bands of work items to
+// XCDs so each XCD's L2 holds what its workgroups touch.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+// ------------------------------------------------------------------ K5: sort by (block, tile)
+// Counting sort of points by bucket = (owning block, tile of 2^kTileShift
+// spans per axis).  The bucket only orders the work; every point is then
+// evaluated by the same exact rules, so the results do not depend on it.
+template <int P, bool MULTI>
+__device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double (&x)[3]) {
+  const DevBlock* __restrict__ B = &m.b0;
+  double u[3];
+  if constexpr (MULTI) {
+    int b[3];
+    double xc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double* E = m.edges + m.edge_off[a];
+      xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
+      b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+    }
+    B = m.blocks + ((b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+  }
+  int t[3], td[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int nsp = B->nsp[a];
+    const int j = min((int)(u[a] * (double)nsp), nsp - 1);
+    t[a] = j >> kTileShift;
+    td[a] = (nsp + (1 << kTileShift) - 1) >> kTileShift;
+  }
+  return (uint32_t)(B->tile_off + (t[0] * td[1] + t[1]) * td[2] + t[2]);
+}
+
+__global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <int P, bool MULTI>
+__global__ __launch_bounds__(kBlock) void sort_keys_k(DevModel m, SortArgs sa) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= sa.n) return;
+  const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
+  const uint32_t k = sort_bucket<P, MULTI>(m, x);
+  sa.key[i] = k;
+  sa.rank[i] = atomicAdd(sa.hist + k, 1u);
+}
+
+// Exclusive scan of hist into offs: chunk sums, a one-workgroup scan of
+// the chunk sums, then each chunk's local scan plus its base.
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = kBlock * kScanPer;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t o = __shfl_up(inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  total = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) total += wsum[w];
+  __syncthreads();
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_part_k(SortArgs sa) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q)
+    if (c0 + q < sa.nb) s += sa.hist[c0 + q];
+  uint32_t total;
+  block_exclusive_scan(s, wsum, total);
+  if (threadIdx.x == 0) sa.part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_spine_k(SortArgs sa, int nparts) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  uint32_t carry = 0;
+  for (int c = 0; c < nparts; c += kBlock) {
+    const int q = c + threadIdx.x;
+    const uint32_t v = q < nparts ? sa.part[q] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, wsum, total);
+    if (q < nparts) sa.part[q] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_final_k(SortArgs sa) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = (c0 + q < sa.nb) ? sa.hist[c0 + q] : 0u;
+    s += v[q];
+  }
+  uint32_t total;
+  uint32_t run = sa.part[blockIdx.x] + block_exclusive_scan(s, wsum, total);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (c0 + q < sa.nb) sa.offs[c0 + q] = run;
+    run += v[q];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void sort_scatter_k(SortArgs sa) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= sa.n) return;
+  const uint32_t pos = sa.offs[sa.key[i]] + sa.rank[i];
+  if ((int64_t)pos >= sa.n) return;       // cannot happen when the counts are consistent
+  sa.perm[pos] = (uint32_t)i;
+  sa.xyz_s[pos] = sa.xyz[i];
+  sa.xyz_s[sa.n + pos] = sa.xyz[sa.n + i];
+  sa.xyz_s[2 * sa.n + pos] = sa.xyz[2 * sa.n + i];
+}
+
+// Decode in sorted order (workgroup ranges dealt to XCDs in contiguous
+// bands); results go to the input positions.
+template <int P, Storage S, bool MULTI>
+__global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
+                                                          float* __restrict__ out,
+                                                          int32_t* __restrict__ dbg) {
+  const int nchunks = (int)((sa.n + kBlock - 1) / kBlock);
+  const int64_t t = (int64_t)xcd_tile(blockIdx.x, nchunks) * kBlock + threadIdx.x;
+  if (t >= sa.n) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const double x[3] = {(double)sa.xyz_s[t], (double)sa.xyz_s[sa.n + t], (double)sa.xyz_s[2 * sa.n + t]};
+  const Loc L = locate<P, MULTI>(m, m.rec, x);
+  const uint32_t i = sa.perm[t];
+  if ((int64_t)i >= sa.n) return;
+  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
+  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
+}
+
 // ------------------------------------------------------------------ K3: grid
 // One wave = 64 consecutive entries c of axis 2 for one entry b of axis 1
 // and a run of up to ga.ta entries a of axis 0.  The axis-0 bases of the
@@ -443,11 +598,6 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
 // bands: each XCD's L2 then holds the part of the model its rays touch.
 constexpr int kTile = 16;
 
-__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
-  const int x = bid & 7, q = bid >> 3;
-  const int per = ntiles >> 3, rem = ntiles & 7;
-  return x * per + (x < rem ? x : rem) + q;
-}
 
 struct Ray {
   double o[3], d[3];
@@ -641,6 +791,28 @@ static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int6
 }
 
 template <int P, Storage S>
+static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, float* out,
+                           int32_t* dbg, hipStream_t st) {
+  const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
+  const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
+  const int nparts = (sa.nb + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
+  if (multi)
+    hipLaunchKernelGGL((sort_keys_k<P, true>), dim3(g), dim3(kBlock), 0, st, m, sa);
+  else
+    hipLaunchKernelGGL((sort_keys_k<P, false>), dim3(g), dim3(kBlock), 0, st, m, sa);
+  hipLaunchKernelGGL(scan_part_k, dim3(nparts), dim3(kBlock), 0, st, sa);
+  hipLaunchKernelGGL(scan_spine_k, dim3(1), dim3(kBlock), 0, st, sa, nparts);
+  hipLaunchKernelGGL(scan_final_k, dim3(nparts), dim3(kBlock), 0, st, sa);
+  hipLaunchKernelGGL(sort_scatter_k, dim3(g), dim3(kBlock), 0, st, sa);
+  if (multi)
+    hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+  else
+    hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+  return hipGetLastError();
+}
+
+template <int P, Storage S>
 static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
   ga.ta = kGridTA;
   dim3 grid((ga.res[2] + kWave - 1) / kWave, (ga.res[1] + 3) / 4, (ga.res[0] + kGridTA - 1) / kGridTA);
@@ -687,6 +859,11 @@ static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, h
 hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
                                 int64_t n, float* out, int32_t* dbg, hipStream_t st) {
   MFA_DISPATCH(points_p, m, multi, xyz, n, out, dbg, st)
+}
+
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
+                                const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st) {
+  MFA_DISPATCH(sorted_p, m, multi, sa, out, dbg, st)
 }
 
 hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,

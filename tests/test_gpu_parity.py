@@ -410,3 +410,52 @@ def test_c4_render_2048_sampled(mfa, dev, c4):
     diff = np.abs(rgba[flat][~band] - ref["rgba"][~band])
     assert diff.max(initial=0) <= 1e-3 and np.sqrt(np.mean(diff ** 2)) <= 1e-5
     assert np.all(ne <= ns[:, 1]) and ns[:, 1].sum() > 1e8
+
+
+# ------------------------------------------------------------------ sorted decode
+def _sorted_matches_unsorted(mfa, dev, model, pts, storage="f32"):
+    with mfa.Model(model, storage) as M:
+        x = to_dev(pts, dev)
+        a, da = mfa.decode_points(M, x, dbg=True)
+        b, db = mfa.decode_points(M, x, dbg=True, sorted_order=True)
+        a, da, b, db = a.cpu().numpy(), da.cpu().numpy(), b.cpu().numpy(), db.cpu().numpy()
+    np.testing.assert_array_equal(b.view(np.uint32), a.view(np.uint32))   # bit for bit
+    np.testing.assert_array_equal(db, da)
+    return a
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_sorted_decode_single_block(mfa, dev, c1, storage):
+    rng = np.random.default_rng(30)
+    pts = adversarial_points(c1, rng, 50000).T.copy()
+    announce(f"sorted decode c1 {storage} n={pts.shape[1]}")
+    out = _sorted_matches_unsorted(mfa, dev, c1, pts, storage)
+    if storage == "f32":
+        ref = oracle_points(c1, pts.T)
+        assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(c1.blocks[0].ctrl)))
+
+
+def test_sorted_decode_multiblock_and_scratch_regrowth(mfa, dev):
+    model = small_multiblock()
+    announce("sorted decode multi-block, growing n")
+    with mfa.Model(model, "f32") as M:
+        for n in (1000, 257, 120001, 5):           # grow, shrink, grow, tiny
+            pts = synth.random_points(n, seed=n, lo=(-0.1, -0.1, -0.1), hi=(1.1, 1.1, 1.1))
+            x = to_dev(pts, dev)
+            a = mfa.decode_points(M, x).cpu().numpy()
+            b = mfa.decode_points(M, x, sorted_order=True).cpu().numpy()
+            np.testing.assert_array_equal(b.view(np.uint32), a.view(np.uint32))
+    ref = oracle_points(model, pts.T)
+    assert_values_close(b, ref["f"], ref["grad"], max(np.abs(bl.ctrl).max() for bl in model.blocks))
+
+
+def test_sorted_decode_c2_1e7(mfa, dev, c2):
+    pts = synth.random_points(10_000_000, seed=12)
+    announce("sorted decode c2 1e7")
+    _sorted_matches_unsorted(mfa, dev, c2, pts)
+
+
+def test_sorted_decode_c4_2e7(mfa, dev, c4):
+    pts = synth.random_points(20_000_000, seed=15)
+    announce("sorted decode 8x8x8-block model 2e7")
+    _sorted_matches_unsorted(mfa, dev, c4, pts)
