@@ -136,15 +136,16 @@ mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst,
  *  xyz   : device FP32, structure of arrays [3][n] (x then y then z); each
  *          coordinate is promoted exactly to FP64.
  *  n     : 0 <= n < 2^31 (n == 0 is a no-op).
- *  flags : 0, or MFA_DECODE_SORTED: points are first ordered by a counting
- *          sort on (owning block, tile of 4^3 spans) and evaluated in that
- *          order, so neighbouring threads share control points; results
- *          are still written in input order and are identical bit for bit
- *          to the unsorted call.  Uses scratch memory held by the model
- *          (28 bytes per point plus 8 per bucket, allocated on first use
- *          and grown when a larger n arrives; MFA_E_NOMEM if that fails).
- *          Sorted calls on one model must not overlap in time (they share
- *          the scratch).
+ *  flags : 0, or MFA_DECODE_SORTED: points are first grouped by bucket =
+ *          (owning block, tile of 2^k spans per axis, k chosen per model for
+ *          at most 4096 buckets; models of more than 4096 blocks return
+ *          MFA_E_UNSUPPORTED) and evaluated in that order, so neighbouring
+ *          threads share control points; results are still written in
+ *          input order and are identical bit for bit to the unsorted call.
+ *          Uses scratch memory held by the model (16 bytes per point plus
+ *          12 per bucket, allocated on first use and grown when a larger n
+ *          arrives; MFA_E_NOMEM if that fails).  Sorted calls on one model
+ *          must not overlap in time (they share the scratch).
  *  out   : device FP32 [n][4] = (f, df/dx, df/dy, df/dz) in world units.
  *  dbg   : NULL, or device int32 [n][4] = (span0, span1, span2, block)
  *          with block = (b0*grid1 + b1)*grid2 + b2.

@@ -469,14 +469,26 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   }
   for (int64_t b = 0; b < nb; ++b)
     for (int a = 0; a < 3; ++a) dblk[b].mc[a] = (dblk[b].nsp[a] + (1 << mc_shift) - 1) >> mc_shift;
+  // sort tiles: the finest power-of-two span groups giving at most
+  // kMaxBuckets buckets (blocks count at least one bucket each)
+  int sort_shift = -1;
   int64_t buckets = 0;
-  for (int64_t b = 0; b < nb; ++b) {
-    dblk[b].tile_off = (int32_t)buckets;
-    int64_t t = 1;
-    for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << kTileShift) - 1) >> kTileShift;
-    buckets += t;
+  for (int sh = 0; sh <= 16 && sort_shift < 0; ++sh) {
+    buckets = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t t = 1;
+      for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << sh) - 1) >> sh;
+      buckets += t;
+    }
+    if (buckets <= kMaxBuckets) sort_shift = sh;
   }
-  if (buckets > INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "too many sort buckets"); }
+  if (sort_shift < 0) sort_shift = 16;    // more blocks than buckets: sorted decode rejected
+  for (int64_t b = 0, acc = 0; b < nb; ++b) {
+    dblk[b].tile_off = (int32_t)acc;
+    int64_t t = 1;
+    for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << sort_shift) - 1) >> sort_shift;
+    acc += t;
+  }
   m->n_buckets = buckets;
   const int64_t pool_bytes = off * es + 64;       // tail pad: 16-bit rows read one word ahead
   if (pool_bytes > 0xFFFFFFFFll) {
@@ -581,6 +593,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   dm.n_rec = (int)recs.size();
   dm.imat = imat;
   dm.mc_shift = mc_shift;
+  dm.sort_shift = sort_shift;
   dm.mcb = m->d_mcb;
   dm.b0 = dblk[0];
   *out = m;
@@ -650,15 +663,16 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
   mfa_status st = check_device(m);
   if (st != MFA_OK) return st;
   if (flags & MFA_DECODE_SORTED) {
-    // scratch: key, rank, perm (4 B each), sorted xyz (12 B) per point;
-    // histogram, offsets and scan partials per bucket
+    // scratch: one 16-byte sorted record per point; counts, starts and
+    // cursors per bucket
+    if (m->n_buckets > kMaxBuckets)
+      return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t nbk = (size_t)m->n_buckets;
-    const size_t nparts = (nbk + 2047) / 2048;
-    const size_t o_key = 0, o_rank = o_key + al(4 * (size_t)n), o_perm = o_rank + al(4 * (size_t)n);
-    const size_t o_xyz = o_perm + al(4 * (size_t)n), o_hist = o_xyz + al(12 * (size_t)n);
-    const size_t o_offs = o_hist + al(4 * nbk), o_part = o_offs + al(4 * nbk);
-    const size_t need = o_part + al(4 * nparts);
+    const size_t o_rec = 0;
+    const size_t o_hist = o_rec + al(16 * (size_t)n), o_start = o_hist + al(4 * nbk);
+    const size_t o_cur = o_start + al(4 * nbk);
+    const size_t need = o_cur + al(4 * nbk);
     if (need > m->ws_bytes) {
       if (m->d_ws) {
         hipError_t fe = hipFree(m->d_ws);   // waits for work still using it
@@ -676,13 +690,10 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     SortArgs sa{};
     sa.xyz = xyz;
     sa.n = n;
-    sa.key = (uint32_t*)(w + o_key);
-    sa.rank = (uint32_t*)(w + o_rank);
-    sa.perm = (uint32_t*)(w + o_perm);
-    sa.xyz_s = (float*)(w + o_xyz);
+    sa.rec = (float4*)(w + o_rec);
     sa.hist = (uint32_t*)(w + o_hist);
-    sa.offs = (uint32_t*)(w + o_offs);
-    sa.part = (uint32_t*)(w + o_part);
+    sa.start = (uint32_t*)(w + o_start);
+    sa.cursor = (uint32_t*)(w + o_cur);
     sa.nb = (int32_t)nbk;
     hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), m->nblocks > 1, sa, out, dbg,
                                         (hipStream_t)stream);

@@ -47,8 +47,9 @@ struct DevBlock {
 static_assert(sizeof(DevBlock) == 144, "DevBlock layout");
 
 // Points sorted for decode are grouped by (block, tile); a tile spans
-// 2^kTileShift knot spans per axis.
-constexpr int kTileShift = 2;
+// 2^sort_shift knot spans per axis, the shift chosen per model so that there
+// are at most kMaxBuckets buckets.
+constexpr int kMaxBuckets = 4096;
 
 // Spans per axis grouped into one macro cell for the value bounds used to
 // skip samples that the transfer function makes fully transparent: 2^shift,
@@ -70,6 +71,7 @@ struct DevModel {
   int32_t n_rec;         // span records in the pool
   int32_t imat;          // id of the uniform interior table (UniformTable), or -1
   int32_t mc_shift;      // log2 of the spans per macro cell and axis
+  int32_t sort_shift;    // log2 of the spans per sort tile and axis
   const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
@@ -135,14 +137,11 @@ struct UniformTable {
 struct SortArgs {
   const float* xyz;      // input SoA [3][n]
   int64_t n;
-  uint32_t* key;         // [n] bucket of each point
-  uint32_t* rank;        // [n] position among the points of its bucket
-  uint32_t* perm;        // [n] sorted position -> input index
-  float* xyz_s;          // [3][n] coordinates in sorted order
+  float4* rec;           // [n] sorted records (x, y, z, input index as bits)
   uint32_t* hist;        // [nb] points per bucket
-  uint32_t* offs;        // [nb] exclusive prefix of hist
-  uint32_t* part;        // [ceil(nb / chunk)] chunk sums of the scan
-  int32_t nb;            // buckets
+  uint32_t* start;       // [nb] first sorted position of each bucket
+  uint32_t* cursor;      // [nb] positions handed out so far per bucket
+  int32_t nb;            // buckets (<= kMaxBuckets)
 };
 
 struct GridArgs {

@@ -333,10 +333,17 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 }
 
 // ------------------------------------------------------------------ K5: sort by (block, tile)
-// Counting sort of points by bucket = (owning block, tile of 2^kTileShift
+// Multisplit of the points by bucket = (owning block, tile of 2^sort_shift
 // spans per axis).  The bucket only orders the work; every point is then
 // evaluated by the same exact rules, so the results do not depend on it.
-template <int P, bool MULTI>
+// Pass 1 counts the buckets of each 8192-point chunk in LDS and adds the
+// counts to the global histogram; a one-workgroup scan gives each bucket's
+// start; pass 2 recounts each chunk, claims a run per bucket with one
+// global atomic, and writes its points into those runs.
+constexpr int kSortPer = 32;                   // points per thread
+constexpr int kSortChunk = kBlock * kSortPer;  // points per workgroup
+
+template <bool MULTI>
 __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double (&x)[3]) {
   const DevBlock* __restrict__ B = &m.b0;
   double u[3];
@@ -357,13 +364,14 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
     for (int a = 0; a < 3; ++a)
       u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
   }
+  const int sh = m.sort_shift;
   int t[3], td[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int nsp = B->nsp[a];
     const int j = min((int)(u[a] * (double)nsp), nsp - 1);
-    t[a] = j >> kTileShift;
-    td[a] = (nsp + (1 << kTileShift) - 1) >> kTileShift;
+    t[a] = j >> sh;
+    td[a] = (nsp + (1 << sh) - 1) >> sh;
   }
   return (uint32_t)(B->tile_off + (t[0] * td[1] + t[1]) * td[2] + t[2]);
 }
@@ -373,24 +381,37 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
   if (i < n) p[i] = 0u;
 }
 
-template <int P, bool MULTI>
-__global__ __launch_bounds__(kBlock) void sort_keys_k(DevModel m, SortArgs sa) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= sa.n) return;
-  const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
-  const uint32_t k = sort_bucket<P, MULTI>(m, x);
-  sa.key[i] = k;
-  sa.rank[i] = atomicAdd(sa.hist + k, 1u);
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void sort_hist_k(DevModel m, SortArgs sa) {
+  __shared__ uint32_t h[kMaxBuckets];
+  for (int b = threadIdx.x; b < sa.nb; b += kBlock) h[b] = 0u;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
+    if (i < sa.n) {
+      const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
+      atomicAdd(h + sort_bucket<MULTI>(m, x), 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < sa.nb; b += kBlock)
+    if (h[b]) atomicAdd(sa.hist + b, h[b]);
 }
 
-// Exclusive scan of hist into offs: chunk sums, a one-workgroup scan of
-// the chunk sums, then each chunk's local scan plus its base.
-constexpr int kScanPer = 8;
-constexpr int kScanChunk = kBlock * kScanPer;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+// Exclusive scan of the bucket counts (one workgroup) and reset of cursors.
+__global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  constexpr int kPer = kMaxBuckets / kBlock;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  uint32_t inc = v;
+  uint32_t v[kPer], s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int b = threadIdx.x * kPer + q;
+    v[q] = b < sa.nb ? sa.hist[b] : 0u;
+    s += v[q];
+  }
+  uint32_t inc = s;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t o = __shfl_up(inc, off);
@@ -398,67 +419,50 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
   }
   if (lane == kWave - 1) wsum[wave] = inc;
   __syncthreads();
-  uint32_t base = 0;
-  for (int w = 0; w < wave; ++w) base += wsum[w];
-  total = 0;
-  for (int w = 0; w < kBlock / kWave; ++w) total += wsum[w];
-  __syncthreads();
-  return base + inc - v;
-}
-
-__global__ __launch_bounds__(kBlock) void scan_part_k(SortArgs sa) {
-  __shared__ uint32_t wsum[kBlock / kWave];
-  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-  uint32_t s = 0;
+  uint32_t run = inc - s;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
 #pragma unroll
-  for (int q = 0; q < kScanPer; ++q)
-    if (c0 + q < sa.nb) s += sa.hist[c0 + q];
-  uint32_t total;
-  block_exclusive_scan(s, wsum, total);
-  if (threadIdx.x == 0) sa.part[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kBlock) void scan_spine_k(SortArgs sa, int nparts) {
-  __shared__ uint32_t wsum[kBlock / kWave];
-  uint32_t carry = 0;
-  for (int c = 0; c < nparts; c += kBlock) {
-    const int q = c + threadIdx.x;
-    const uint32_t v = q < nparts ? sa.part[q] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, wsum, total);
-    if (q < nparts) sa.part[q] = carry + ex;
-    carry += total;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void scan_final_k(SortArgs sa) {
-  __shared__ uint32_t wsum[kBlock / kWave];
-  const int64_t c0 = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
-  uint32_t v[kScanPer];
-  uint32_t s = 0;
-#pragma unroll
-  for (int q = 0; q < kScanPer; ++q) {
-    v[q] = (c0 + q < sa.nb) ? sa.hist[c0 + q] : 0u;
-    s += v[q];
-  }
-  uint32_t total;
-  uint32_t run = sa.part[blockIdx.x] + block_exclusive_scan(s, wsum, total);
-#pragma unroll
-  for (int q = 0; q < kScanPer; ++q) {
-    if (c0 + q < sa.nb) sa.offs[c0 + q] = run;
+  for (int q = 0; q < kPer; ++q) {
+    const int b = threadIdx.x * kPer + q;
+    if (b < sa.nb) {
+      sa.start[b] = run;
+      sa.cursor[b] = 0u;
+    }
     run += v[q];
   }
 }
 
-__global__ __launch_bounds__(kBlock) void sort_scatter_k(SortArgs sa) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= sa.n) return;
-  const uint32_t pos = sa.offs[sa.key[i]] + sa.rank[i];
-  if ((int64_t)pos >= sa.n) return;       // cannot happen when the counts are consistent
-  sa.perm[pos] = (uint32_t)i;
-  sa.xyz_s[pos] = sa.xyz[i];
-  sa.xyz_s[sa.n + pos] = sa.xyz[sa.n + i];
-  sa.xyz_s[2 * sa.n + pos] = sa.xyz[2 * sa.n + i];
+template <bool MULTI>
+__global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
+  __shared__ uint32_t h[kMaxBuckets];
+  __shared__ uint32_t base[kMaxBuckets];
+  for (int b = threadIdx.x; b < sa.nb; b += kBlock) h[b] = 0u;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
+  uint32_t key[kSortPer], rank[kSortPer];
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
+    key[q] = 0xFFFFFFFFu;
+    if (i < sa.n) {
+      const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
+      key[q] = sort_bucket<MULTI>(m, x);
+      rank[q] = atomicAdd(h + key[q], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < sa.nb; b += kBlock)
+    if (h[b]) base[b] = sa.start[b] + atomicAdd(sa.cursor + b, h[b]);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSortPer; ++q) {
+    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
+    if (key[q] == 0xFFFFFFFFu) continue;
+    const uint32_t pos = base[key[q]] + rank[q];
+    if ((int64_t)pos >= sa.n) continue;        // cannot happen when the counts are consistent
+    sa.rec[pos] = make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i],
+                              __uint_as_float((uint32_t)i));
+  }
 }
 
 // Decode in sorted order (workgroup ranges dealt to XCDs in contiguous
@@ -471,9 +475,10 @@ __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs s
   const int64_t t = (int64_t)xcd_tile(blockIdx.x, nchunks) * kBlock + threadIdx.x;
   if (t >= sa.n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
-  const double x[3] = {(double)sa.xyz_s[t], (double)sa.xyz_s[sa.n + t], (double)sa.xyz_s[2 * sa.n + t]};
+  const float4 q = sa.rec[t];
+  const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
   const Loc L = locate<P, MULTI>(m, m.rec, x);
-  const uint32_t i = sa.perm[t];
+  const uint32_t i = __float_as_uint(q.w);
   if ((int64_t)i >= sa.n) return;
   reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
@@ -794,17 +799,18 @@ template <int P, Storage S>
 static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
   const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
+  const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
   const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
-  const int nparts = (sa.nb + kScanChunk - 1) / kScanChunk;
   hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
   if (multi)
-    hipLaunchKernelGGL((sort_keys_k<P, true>), dim3(g), dim3(kBlock), 0, st, m, sa);
+    hipLaunchKernelGGL(sort_hist_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
   else
-    hipLaunchKernelGGL((sort_keys_k<P, false>), dim3(g), dim3(kBlock), 0, st, m, sa);
-  hipLaunchKernelGGL(scan_part_k, dim3(nparts), dim3(kBlock), 0, st, sa);
-  hipLaunchKernelGGL(scan_spine_k, dim3(1), dim3(kBlock), 0, st, sa, nparts);
-  hipLaunchKernelGGL(scan_final_k, dim3(nparts), dim3(kBlock), 0, st, sa);
-  hipLaunchKernelGGL(sort_scatter_k, dim3(g), dim3(kBlock), 0, st, sa);
+    hipLaunchKernelGGL(sort_hist_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+  hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kBlock), 0, st, sa);
+  if (multi)
+    hipLaunchKernelGGL(sort_scatter_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+  else
+    hipLaunchKernelGGL(sort_scatter_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
   if (multi)
     hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
   else
