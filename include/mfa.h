@@ -243,6 +243,84 @@ mfa_status mfa_render_frame(mfa_model model, const mfa_camera* camera, const mfa
                             int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
                             void* stream);
 
+/* ------------------------------------------------------------------ serving */
+
+/* A request loop for many clients sharing one GPU: the visualisation
+ * pipeline re-runs on every change of transfer function, shading or view
+ * (Sec. IV-B), here as render and point-query requests against resident
+ * models.  A scheduler thread admits requests first come first served
+ * while the bytes of their buffers fit the memory budget, splits them into
+ * work items (16x16 pixel tiles, 256-point chunks), packs at most
+ * max_batch_items items per batch (a large request spans batches) and runs
+ * each batch as persistent launches on the server's own stream; at most two
+ * batches are in flight.  Results equal those of mfa_render_frame and
+ * mfa_decode_points (unsorted) bit for bit.                                */
+typedef struct mfa_server_s* mfa_server;   /* opaque */
+
+#define MFA_SERVER_FAKE_EXECUTOR 1u   /* no device work: each batch "runs" for
+                                         fake_item_us per item (host tests)  */
+typedef struct {
+  int64_t hbm_budget_bytes;   /* bytes of request buffers admitted at once (> 0)  */
+  int32_t queue_cap;          /* requests waiting for a batch (> 0)               */
+  int32_t max_batch_items;    /* work items per batch (0 = 8192)                  */
+  uint32_t flags;             /* 0 or MFA_SERVER_FAKE_EXECUTOR                    */
+  double fake_item_us;        /* modelled time per item with the fake executor    */
+} mfa_server_config;
+
+enum { MFA_REQ_RENDER = 0, MFA_REQ_POINTS = 1 };
+
+/* One request.  Render: camera, params, w, h and the device RGBA buffer
+ * rgba [h][w][4] as for mfa_render_frame (footprint w*h*16 + 4096 bytes).
+ * Points: device SoA xyz [3][n] and device out [n][4] as for
+ * mfa_decode_points (footprint 28*n bytes).  The caller keeps the buffers
+ * (and the TF table) alive and untouched until the request is done.       */
+typedef struct {
+  int32_t kind;
+  int32_t model_id;
+  mfa_camera camera;
+  mfa_render_params params;
+  int32_t w, h;
+  float* rgba;
+  const float* xyz;
+  int64_t n;
+  float* out;
+} mfa_request;
+
+/* Host times in seconds since the server was created: submit, admission
+ * (memory granted), launch of its first batch, completion noticed by the
+ * scheduler.  status is MFA_OK or MFA_E_DEVICE; done is 0 or 1.           */
+typedef struct {
+  double t_submit, t_admit, t_start, t_done;
+  int32_t status;
+  int32_t done;
+} mfa_request_stats;
+
+/* Creates a server on the current device (its models must live there).
+ * With MFA_SERVER_FAKE_EXECUTOR no device is touched and models may be
+ * NULL.                                                                     */
+mfa_status mfa_server_create(const mfa_server_config* config, mfa_server* out);
+
+/* Makes a model servable; model_id receives its index.  The model must
+ * outlive the server.                                                      */
+mfa_status mfa_server_add_model(mfa_server server, mfa_model model, int32_t* model_id);
+
+/* Queues a request without waiting for the GPU.  Errors: MFA_E_ARG (bad
+ * request or model id), MFA_E_BUDGET (footprint above the whole budget),
+ * MFA_E_BUSY (queue_cap requests waiting).                                 */
+mfa_status mfa_server_submit(mfa_server server, const mfa_request* request, uint64_t* ticket);
+
+/* Host-only status read; MFA_E_NOTFOUND for an unknown ticket.            */
+mfa_status mfa_server_poll(mfa_server server, uint64_t ticket, mfa_request_stats* stats);
+
+/* Blocks until the request is done; returns its status.                   */
+mfa_status mfa_server_wait(mfa_server server, uint64_t ticket, mfa_request_stats* stats);
+
+/* Forgets a finished request (its stats are no longer available).         */
+mfa_status mfa_server_release(mfa_server server, uint64_t ticket);
+
+/* Finishes every queued request, then frees the server.  NULL is a no-op. */
+mfa_status mfa_server_destroy(mfa_server server);
+
 /* ------------------------------------------------------------------ host utilities */
 
 /* Host-only helpers (no device work): the storage rounding and the default

@@ -16,7 +16,7 @@ import numpy as np
 from . import _lib as L
 from ._lib import MFAError  # noqa: F401
 
-__all__ = ["Model", "decode_points", "decode_grid", "render_frame", "MFAError",
+__all__ = ["Model", "Server", "decode_points", "decode_grid", "render_frame", "MFAError",
            "quantize", "default_knots", "version"]
 
 _DTYPES = {"f32": L.MFA_F32, "bf16": L.MFA_BF16, "f16": L.MFA_F16}
@@ -251,6 +251,107 @@ def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=N
                                      C.byref(dbg) if dbg is not None else None,
                                      _stream_ptr(stream)))
     return (out, *extra) if extra else out
+
+
+class Server:
+    """Request loop over resident models (mfa_server_*).
+
+    fake_item_us switches to the host-only fake executor (no device work;
+    each batch takes fake_item_us per work item)."""
+
+    def __init__(self, hbm_budget_bytes: int, queue_cap: int = 1024, max_batch_items: int = 0,
+                 fake_item_us: Optional[float] = None):
+        cfg = L.ServerConfig()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.queue_cap = int(queue_cap)
+        cfg.max_batch_items = int(max_batch_items)
+        cfg.flags = L.MFA_SERVER_FAKE_EXECUTOR if fake_item_us is not None else 0
+        cfg.fake_item_us = float(fake_item_us or 0.0)
+        h = C.c_void_p()
+        L.check(L.lib().mfa_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = {}          # ticket -> objects kept alive until done
+
+    def add_model(self, model: Optional[Model]) -> int:
+        mid = C.c_int32()
+        L.check(L.lib().mfa_server_add_model(self._h, model.handle if model is not None else None,
+                                             C.byref(mid)))
+        return mid.value
+
+    def _submit(self, req, keep) -> int:
+        t = C.c_uint64()
+        L.check(L.lib().mfa_server_submit(self._h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_render(self, model_id: int, cam: dict, params: dict, w: int, h: int, rgba,
+                      tf_dev=None) -> int:
+        torch = _torch()
+        req = L.Request()
+        req.kind = L.MFA_REQ_RENDER
+        req.model_id = model_id
+        keep = [rgba]
+        if tf_dev is not None or isinstance(rgba, torch.Tensor):
+            if tf_dev is None:
+                tf_dev = torch.as_tensor(np.ascontiguousarray(params["tf"], dtype=np.float32),
+                                         device=rgba.device)
+            req.params = make_params(params, tf_dev)
+            req.rgba = _dev_ptr(rgba, torch.float32, (h, w, 4), "rgba").value
+            keep.append(tf_dev)
+        else:                    # fake executor: any non-null address
+            req.params = L.RenderParams()
+            req.rgba = int(rgba)
+        if cam is not None:
+            req.camera = make_camera(cam)
+        req.w, req.h = int(w), int(h)
+        return self._submit(req, keep)
+
+    def submit_points(self, model_id: int, xyz, out, n: Optional[int] = None) -> int:
+        torch = _torch()
+        req = L.Request()
+        req.kind = L.MFA_REQ_POINTS
+        req.model_id = model_id
+        if isinstance(xyz, torch.Tensor):
+            n = int(xyz.shape[1])
+            req.xyz = _dev_ptr(xyz, torch.float32, (3, n), "xyz").value
+            req.out = _dev_ptr(out, torch.float32, (n, 4), "out").value
+        else:                    # fake executor: any non-null addresses
+            req.xyz, req.out = int(xyz), int(out)
+        req.n = int(n)
+        return self._submit(req, [xyz, out])
+
+    def poll(self, ticket: int) -> dict:
+        st = L.RequestStats()
+        L.check(L.lib().mfa_server_poll(self._h, ticket, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in L.RequestStats._fields_}
+
+    def wait(self, ticket: int) -> dict:
+        st = L.RequestStats()
+        L.check(L.lib().mfa_server_wait(self._h, ticket, C.byref(st)))
+        self._keep.pop(ticket, None)
+        return {f: getattr(st, f) for f, _ in L.RequestStats._fields_}
+
+    def release(self, ticket: int) -> None:
+        L.check(L.lib().mfa_server_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.lib().mfa_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def quantize(x: np.ndarray, dtype: str) -> np.ndarray:

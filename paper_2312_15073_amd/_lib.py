@@ -55,6 +55,25 @@ class RenderDebug(C.Structure):
                 ("alpha_stride", C.c_int32)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("queue_cap", C.c_int32),
+                ("max_batch_items", C.c_int32), ("flags", C.c_uint32), ("fake_item_us", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("model_id", C.c_int32), ("camera", Camera),
+                ("params", RenderParams), ("w", C.c_int32), ("h", C.c_int32),
+                ("rgba", C.c_void_p), ("xyz", C.c_void_p), ("n", C.c_int64), ("out", C.c_void_p)]
+
+
+class RequestStats(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("status", C.c_int32), ("done", C.c_int32)]
+
+
+MFA_SERVER_FAKE_EXECUTOR = 1
+MFA_REQ_RENDER, MFA_REQ_POINTS = 0, 1
+
 # name -> (restype, argtypes); every function declared in include/mfa.h
 SIGNATURES = {
     "mfa_model_create": (C.c_int, [C.POINTER(DomainDesc), C.POINTER(BlockDesc), C.c_int32, C.c_int,
@@ -69,6 +88,13 @@ SIGNATURES = {
     "mfa_render_frame": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(RenderDebug),
                                    C.c_void_p]),
+    "mfa_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    "mfa_server_add_model": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "mfa_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "mfa_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(RequestStats)]),
+    "mfa_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(RequestStats)]),
+    "mfa_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "mfa_server_destroy": (C.c_int, [C.c_void_p]),
     "mfa_quantize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     "mfa_default_knots": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
     "mfa_last_error": (C.c_char_p, []),

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmfa.so")
-SOURCES = ["mfa_host.cpp", "mfa_kernels.hip"]
+SOURCES = ["mfa_host.cpp", "mfa_server.cpp", "mfa_kernels.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for all device code.
@@ -30,7 +30,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
+def build(verbose: bool = False, jobs: int = 3) -> str:
     """Compiles every source and links libmfa.so; returns its path."""
     cc = hipcc()
     obj_dir = os.path.join(HERE, "_build")

@@ -14,6 +14,7 @@
 
 #include "mfa.h"
 #include "mfa_internal.h"
+#include "mfa_model.h"
 
 namespace mfa {
 hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
@@ -31,7 +32,7 @@ using namespace mfa;
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
-static mfa_status fail(mfa_status st, const char* fmt, ...) {
+mfa_status fail(mfa_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -41,7 +42,7 @@ static mfa_status fail(mfa_status st, const char* fmt, ...) {
   return st;
 }
 
-static mfa_status hip_fail(hipError_t e, const char* what) {
+mfa_status hip_fail(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? MFA_E_NOMEM : MFA_E_DEVICE, "%s: %s", what,
               hipGetErrorString(e));
 }
@@ -193,31 +194,6 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 }
 
 // ------------------------------------------------------------------ model
-struct mfa_model_s {
-  int device = 0;
-  int degree = 0;
-  mfa_dtype storage = MFA_F32;
-  int grid[3] = {1, 1, 1};
-  int nblocks = 1;
-  double voxel = 0.0;
-  std::vector<int32_t> n;       // 3 per block
-  std::vector<int64_t> coff;    // element offset per block
-  std::vector<int32_t> rs1;     // row stride per block
-  int64_t n_ctrl_total = 0;
-  float vmin = 0.f, vmax = 0.f;
-  void* d_ctrl = nullptr;
-  int64_t ctrl_bytes = 0;
-  SpanRec* d_rec = nullptr;
-  float* d_mats = nullptr;
-  DevBlock* d_blocks = nullptr;
-  double* d_edges = nullptr;
-  uint32_t* d_mcb = nullptr;
-  int64_t device_bytes = 0;
-  int64_t n_buckets = 0;        // sort buckets (block, tile)
-  void* d_ws = nullptr;         // scratch of sorted decodes, grown on demand
-  size_t ws_bytes = 0;
-  DevModel dm{};
-};
 
 static void free_model(mfa_model m) {
   if (!m) return;
@@ -620,7 +596,7 @@ extern "C" mfa_status mfa_model_info(mfa_model m, mfa_model_info_t* info) {
   return MFA_OK;
 }
 
-static mfa_status check_device(mfa_model m) {
+mfa_status check_device(mfa_model m) {
   int cur = -1;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -649,7 +625,7 @@ extern "C" mfa_status mfa_model_export_ctrl(mfa_model m, int32_t block, void* ds
 }
 
 // ------------------------------------------------------------------ decode
-static Storage storage_of(mfa_model m) {
+Storage storage_of(mfa_model m) {
   return m->storage == MFA_F32 ? Storage::F32 : m->storage == MFA_BF16 ? Storage::BF16 : Storage::F16;
 }
 
@@ -733,9 +709,9 @@ extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3]
 }
 
 // ------------------------------------------------------------------ render
-extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
-                                       int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
-                                       void* stream) {
+mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
+                            int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                            RenderArgs* out) {
   if (!m || !cam || !rp || !rgba) return fail(MFA_E_ARG, "null argument");
   if (w < 1 || h < 1 || w > 16384 || h > 16384) return fail(MFA_E_ARG, "image %dx%d out of range", w, h);
   if (cam->kind != MFA_ORTHO && cam->kind != MFA_PERSPECTIVE) return fail(MFA_E_ARG, "camera kind");
@@ -756,8 +732,6 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
     return fail(MFA_E_ARG, "shading parameters must be finite");
   if (dbg && dbg->alpha && dbg->alpha_stride < rp->max_samples)
     return fail(MFA_E_ARG, "alpha_stride %d < max_samples %d", dbg->alpha_stride, rp->max_samples);
-  mfa_status st = check_device(m);
-  if (st != MFA_OK) return st;
   RenderArgs r{};
   r.tf = rp->tf_rgba;
   r.rgba = rgba;
@@ -787,6 +761,18 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
   r.sy = cam->sy;
   r.step = step;
   r.inv_step = 1.0 / step;
+  *out = r;
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
+                                       int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                                       void* stream) {
+  RenderArgs r;
+  mfa_status st = make_render_args(m, cam, rp, w, h, rgba, dbg, &r);
+  if (st != MFA_OK) return st;
+  st = check_device(m);
+  if (st != MFA_OK) return st;
   hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   return MFA_OK;

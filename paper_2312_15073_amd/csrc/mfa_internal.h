@@ -172,3 +172,26 @@ struct RenderArgs {
 };
 
 }  // namespace mfa
+
+namespace mfa {
+
+// Serving: a batch is a list of equal work items over admitted requests.
+// A render item is one 16x16 pixel tile of a frame; a points item is 256
+// consecutive points of a query set.
+enum { kServeRender = 0, kServePoints = 1 };
+
+struct ServeReq {
+  int32_t kind;          // kServeRender / kServePoints
+  int32_t model;         // index in the device model table
+  RenderArgs ra;         // render requests
+  const float* xyz;      // points requests: device SoA [3][n]
+  float* out;            //                  device [n][4]
+  int64_t n;
+};
+
+struct ServeItem {
+  int32_t req;           // index in the batch's request array
+  int32_t index;         // tile or 256-point chunk of the request
+};
+
+}  // namespace mfa

@@ -665,41 +665,33 @@ __device__ __forceinline__ float tf_coord(float f, float vmin, float inv_range) 
 
 __device__ __forceinline__ int tf_entry(float s) { return min((int)floorf(s), 254); }
 
-// LDSREC: single-block model whose span records and basis tables are copied
-// into LDS once per workgroup.
-template <int P, Storage S, bool MULTI, bool LDSREC>
-__global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
-  extern __shared__ float4 dyn[];
-  __shared__ float4 tf[256];
-  __shared__ int zpre[257];      // zpre[i] = number of entries < i with alpha != 0
-  __shared__ int wtot[kBlock / kWave];
+// Transfer function into LDS plus zpre[i] = number of entries below i with
+// non-zero opacity (for the transparency test).  All threads take part.
+__device__ __forceinline__ void stage_tf(const float* __restrict__ tfp, float4* tf, int* zpre,
+                                         int* wtot) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wave = tid / kWave;
-  const float4 te = reinterpret_cast<const float4*>(r.tf)[tid];
+  const float4 te = reinterpret_cast<const float4*>(tfp)[tid];
   tf[tid] = te;
   const unsigned long long nzm = __ballot(te.w != 0.f);
   if (lane == 0) wtot[wave] = __popcll(nzm);
-  const SpanRec* R = m.rec;
-  const float* MT = m.mats;
-  if constexpr (LDSREC) {
-    SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
-    float* lm = reinterpret_cast<float*>(lr + m.n_rec);
-    for (int q = tid; q < m.n_rec * 2; q += kBlock)
-      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
-    for (int q = tid; q < m.n_mats * m.mat_stride / 4; q += kBlock)
-      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
-    R = lr;
-    MT = lm;
-  }
   __syncthreads();
   int base = 0;
   for (int w = 0; w < wave; ++w) base += wtot[w];
   zpre[tid] = base + __popcll(nzm & ((1ull << lane) - 1ull));
   if (tid == kBlock - 1) zpre[256] = base + __popcll(nzm);
   __syncthreads();
+}
 
-  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-  const int tile = xcd_tile(blockIdx.x, tx * ty);
+// One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
+// and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
+template <int P, Storage S, bool MULTI>
+__device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs& r, int tile,
+                                            const SpanRec* __restrict__ R,
+                                            const float* __restrict__ MT, const float4* tf,
+                                            const int* zpre) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int tx = (r.w + kTile - 1) / kTile;
   const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
   const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
   const bool pix = i < r.w && j < r.h;
@@ -781,6 +773,74 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   }
 }
 
+// LDSREC: single-block model whose span records and basis tables are copied
+// into LDS once per workgroup.
+template <int P, Storage S, bool MULTI, bool LDSREC>
+__global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
+  extern __shared__ float4 dyn[];
+  __shared__ float4 tf[256];
+  __shared__ int zpre[257];
+  __shared__ int wtot[kBlock / kWave];
+  const SpanRec* R = m.rec;
+  const float* MT = m.mats;
+  if constexpr (LDSREC) {
+    SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
+    float* lm = reinterpret_cast<float*>(lr + m.n_rec);
+    for (int q = threadIdx.x; q < m.n_rec * 2; q += kBlock)
+      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
+    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    R = lr;
+    MT = lm;
+  }
+  stage_tf(r.tf, tf, zpre, wtot);
+  const int ntiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  render_tile<P, S, MULTI>(m, r, xcd_tile(blockIdx.x, ntiles), R, MT, tf, zpre);
+}
+
+// ------------------------------------------------------------------ K6: persistent serving
+// Each workgroup takes work items from an atomic cursor until the batch is
+// exhausted (every wave reaches the exit once the cursor passes n_items).
+// The kernel instance fixes (degree, storage, multi-block); requests of one
+// batch may use any model of that kind and any mix of frames and query sets.
+template <int P, Storage S, bool MULTI>
+__global__ __launch_bounds__(kBlock) void serve_k(const DevModel* __restrict__ models,
+                                                  const ServeReq* __restrict__ reqs,
+                                                  const ServeItem* __restrict__ items, int n_items,
+                                                  int* __restrict__ cursor) {
+  __shared__ float4 tf[256];
+  __shared__ int zpre[257];
+  __shared__ int wtot[kBlock / kWave];
+  __shared__ int s_item;
+  int staged = -1;                                 // request whose TF is in LDS
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(cursor, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) return;
+    const ServeItem I = items[it];
+    const ServeReq* Q = reqs + I.req;
+    const DevModel& m = models[Q->model];
+    if (Q->kind == kServeRender) {
+      if (staged != I.req) {
+        stage_tf(Q->ra.tf, tf, zpre, wtot);
+        staged = I.req;
+      }
+      render_tile<P, S, MULTI>(m, Q->ra, I.index, m.rec, m.mats, tf, zpre);
+      __syncthreads();                             // tf may be restaged by the next item
+    } else {
+      const int64_t i = (int64_t)I.index * kBlock + threadIdx.x;
+      if (i < Q->n) {
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+        const double x[3] = {(double)Q->xyz[i], (double)Q->xyz[Q->n + i], (double)Q->xyz[2 * Q->n + i]};
+        const Loc L = locate<P, MULTI>(m, m.rec, x);
+        reinterpret_cast<float4*>(Q->out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 template <int P, Storage S>
 static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int64_t n, float* out,
@@ -815,6 +875,18 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
     hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
   else
     hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+  return hipGetLastError();
+}
+
+template <int P, Storage S>
+static hipError_t serve_p(bool multi, const DevModel* models, const ServeReq* reqs,
+                          const ServeItem* items, int n_items, int* cursor, int grid, hipStream_t st) {
+  if (multi)
+    hipLaunchKernelGGL((serve_k<P, S, true>), dim3(grid), dim3(kBlock), 0, st, models, reqs, items,
+                       n_items, cursor);
+  else
+    hipLaunchKernelGGL((serve_k<P, S, false>), dim3(grid), dim3(kBlock), 0, st, models, reqs, items,
+                       n_items, cursor);
   return hipGetLastError();
 }
 
@@ -870,6 +942,11 @@ hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi,
 hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st) {
   MFA_DISPATCH(sorted_p, m, multi, sa, out, dbg, st)
+}
+
+hipError_t launch_serve(int p, Storage s, bool multi, const DevModel* models, const ServeReq* reqs,
+                        const ServeItem* items, int n_items, int* cursor, int grid, hipStream_t st) {
+  MFA_DISPATCH(serve_p, multi, models, reqs, items, n_items, cursor, grid, st)
 }
 
 hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,

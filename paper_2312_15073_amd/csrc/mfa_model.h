@@ -1,0 +1,47 @@
+// Host-side model record shared by the library's host sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mfa.h"
+#include "mfa_internal.h"
+
+struct mfa_model_s {
+  int device = 0;
+  int degree = 0;
+  mfa_dtype storage = MFA_F32;
+  int grid[3] = {1, 1, 1};
+  int nblocks = 1;
+  double voxel = 0.0;
+  std::vector<int32_t> n;       // 3 per block
+  std::vector<int64_t> coff;    // element offset per block
+  std::vector<int32_t> rs1;     // row stride per block
+  int64_t n_ctrl_total = 0;
+  float vmin = 0.f, vmax = 0.f;
+  void* d_ctrl = nullptr;
+  int64_t ctrl_bytes = 0;
+  mfa::SpanRec* d_rec = nullptr;
+  float* d_mats = nullptr;
+  mfa::DevBlock* d_blocks = nullptr;
+  double* d_edges = nullptr;
+  uint32_t* d_mcb = nullptr;
+  int64_t device_bytes = 0;
+  int64_t n_buckets = 0;        // sort buckets (block, tile)
+  void* d_ws = nullptr;         // scratch of sorted decodes, grown on demand
+  size_t ws_bytes = 0;
+  mfa::DevModel dm{};
+};
+
+// Error helpers: set the calling thread's last-error message and return st.
+mfa_status fail(mfa_status st, const char* fmt, ...);
+mfa_status hip_fail(hipError_t e, const char* what);
+mfa::Storage storage_of(mfa_model m);
+mfa_status check_device(mfa_model m);
+// Validated kernel arguments of a render of model m (shared by the direct
+// entry point and the server).
+mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
+                            int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                            mfa::RenderArgs* out);

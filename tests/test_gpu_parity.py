@@ -459,3 +459,45 @@ def test_sorted_decode_c4_2e7(mfa, dev, c4):
     pts = synth.random_points(20_000_000, seed=15)
     announce("sorted decode 8x8x8-block model 2e7")
     _sorted_matches_unsorted(mfa, dev, c4, pts)
+
+
+# ------------------------------------------------------------------ serving
+def test_server_results_equal_direct_calls(mfa, dev, c1):
+    import torch
+    multi = small_multiblock()
+    models = [mfa.Model(c1, "f32"), mfa.Model(c1, "bf16"), mfa.Model(multi, "f32")]
+    specs = [c1, c1, multi]
+    rng = np.random.default_rng(50)
+    announce("server: mixed renders and point queries on 3 models")
+    with mfa.Server(hbm_budget_bytes=1 << 34, queue_cap=256, max_batch_items=64) as S:
+        ids = [S.add_model(M) for M in models]
+        jobs = []
+        for q in range(24):
+            k = q % 3
+            if q % 2 == 0:
+                W, H = int(rng.integers(20, 90)), int(rng.integers(20, 70))
+                cam = synth.perspective_camera(W, H, az_deg=float(rng.uniform(0, 360)),
+                                               el_deg=float(rng.uniform(-50, 50)))
+                params = synth.render_params(specs[k], max_samples=int(rng.integers(50, 400)))
+                tf = to_dev(params["tf"], dev)
+                out = torch.full((H, W, 4), -1.0, device=dev)
+                t = S.submit_render(ids[k], cam, params, W, H, out, tf_dev=tf)
+                jobs.append(("r", k, t, out, (cam, params, W, H, tf)))
+            else:
+                n = int(rng.integers(1, 5000))
+                x = to_dev(synth.random_points(n, seed=q), dev)
+                out = torch.full((n, 4), -1.0, device=dev)
+                t = S.submit_points(ids[k], x, out)
+                jobs.append(("p", k, t, out, x))
+        stats = [S.wait(j[2]) for j in jobs]
+    for (kind, k, t, out, arg), st in zip(jobs, stats):
+        assert st["status"] == 0 and st["done"] == 1
+        if kind == "r":
+            cam, params, W, H, tf = arg
+            ref = mfa.render_frame(models[k], cam, params, W, H, tf_dev=tf, device=dev)
+        else:
+            ref = mfa.decode_points(models[k], arg)
+        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32),
+                                      ref.cpu().numpy().view(np.uint32))
+    for M in models:
+        M.close()
