@@ -119,17 +119,33 @@ def _cpu_model() -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="single128",
+                    choices=["single128", "multiblock", "serving"],
+                    help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
+                         "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
+                         "serving: open-loop request trace over three resident models")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests")
+    ap.add_argument("--load", type=float, default=0.6, help="serving: offered load / capacity")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the multi-GPU path is a design, not part of this build", file=sys.stderr)
         return 2
+    if args.workload == "multiblock":
+        return run_multiblock(args)
+    if args.workload == "serving":
+        return run_serving(args)
+    if args.steps is None:
+        args.steps = 20
+    return run_single128(args)
 
+
+def run_single128(args):
     spec = synth.model_c2()
     p = spec.blocks[0].degree[0]
     pts = synth.random_points(N_POINTS, seed=12)
@@ -246,6 +262,239 @@ def main(argv=None):
     }
     print(json.dumps(line), flush=True)
     model.close()
+    return 0
+
+
+# ------------------------------------------------------------------ 8x8x8-block workload
+MB_POINTS = 100_000_000
+MB_FRAME = 2048
+
+
+def _cpu_job_mb(job):
+    from oracle import bspline as ob
+    from oracle import render as orr
+    kind, arg = job
+    spec = _CPU_STATE["spec"]
+    if kind == "points":
+        ob.evaluate(spec, arg.T.astype(np.float64))
+        return arg.shape[1]
+    cam, params, pix = arg
+    r = orr.render(orr.model_field(spec), spec.lo, spec.hi, cam, params, MB_FRAME, MB_FRAME, pixels=pix)
+    return int(r["used"].sum())
+
+
+def cpu_baseline_mb(spec, cam, params, pts):
+    """The FP64 oracle on 2e5 of the points and the central 96x96 pixels."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    _CPU_STATE["spec"] = spec
+    sub = pts[:, :200_000]
+    jobs = [("points", np.ascontiguousarray(sub[:, c]))
+            for c in np.array_split(np.arange(sub.shape[1]), cores)]
+    crop = 96
+    r0 = MB_FRAME // 2 - crop // 2
+    for rr in np.array_split(np.arange(r0, r0 + crop), 4 * cores):
+        pix = np.stack(np.meshgrid(rr, np.arange(r0, r0 + crop), indexing="ij"), -1).reshape(-1, 2)
+        jobs.append(("render", (cam, params, pix)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        n = int(sum(pool.map(_cpu_job_mb, jobs, chunksize=1)))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle: {sub.shape[1]} of {MB_POINTS} points and the central "
+                       f"{crop}x{crop} pixels of the {MB_FRAME}^2 frame; {n} samples in {dt:.1f} s"),
+            "cpu_model": _cpu_model()}
+
+
+def run_multiblock(args):
+    """Step = block/tile-sorted decode of 1e8 points + one 2048^2 frame of the
+    8x8x8-block model (~57M control points, degree 3)."""
+    steps = 5 if args.steps is None else args.steps
+    spec = synth.model_c4()
+    pts = synth.random_points(MB_POINTS, seed=14)
+    cam = synth.perspective_camera(MB_FRAME, MB_FRAME)
+    params = synth.render_params(spec, max_samples=2048)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_mb(spec, cam, params, pts)
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    model = mfa.Model(spec, args.storage)
+    xyz = torch.as_tensor(pts, device=dev)
+    del pts
+    tf = torch.as_tensor(params["tf"], device=dev)
+    pts_out = torch.empty((MB_POINTS, 4), dtype=torch.float32, device=dev)
+    rgba = torch.empty((MB_FRAME, MB_FRAME, 4), dtype=torch.float32, device=dev)
+    _, ns, ne = mfa.render_frame(model, cam, params, MB_FRAME, MB_FRAME, tf_dev=tf, nsamp=True,
+                                 neval=True, device=dev)
+    torch.cuda.synchronize()
+    s_frame, s_eval = int(ns[..., 1].sum().item()), int(ne.sum().item())
+    del ns, ne
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        mfa.decode_points(model, xyz, out=pts_out, sorted_order=True)
+        if ev:
+            ev[1].record(stream)
+        mfa.render_frame(model, cam, params, MB_FRAME, MB_FRAME, tf_dev=tf, out=rgba, device=dev)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / steps
+    kms = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(steps)]))
+           for i, n in enumerate(["decode_points", "render"])}
+    info = model.info()
+    fl_r = flop_per_sample(3) + 54
+    kernels = {
+        "decode_points": dict(ms=kms["decode_points"], samples=MB_POINTS, bound="hbm",
+                              achieved=(MB_POINTS * 28 + info["ctrl_bytes"]) / kms["decode_points"] / 1e6,
+                              unit="GB/s", peak=PEAK_HBM_GBS),
+        "render": dict(ms=kms["render"], samples=s_frame, evaluated_samples=s_eval, bound="alu",
+                       achieved=s_eval * fl_r / kms["render"] / 1e9, unit="TFLOP/s",
+                       peak=PEAK_FP32_TFLOPS),
+    }
+    for k in kernels.values():
+        k["frac"] = k["achieved"] / k["peak"]
+        k["samples_per_s"] = k["samples"] / (k["ms"] * 1e-3)
+    dom = max(kernels, key=lambda n: kernels[n]["ms"])
+    dk = kernels[dom]
+    roofline = {"bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
+                "unit": dk["unit"], "frac": dk["frac"], "traffic": None, "kernel": dom}
+    samples_step = MB_POINTS + s_frame
+    print(json.dumps({
+        "metric": METRIC, "value": samples_step / (ms_step * 1e-3), "unit": "samples/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"f32 ({args.storage} storage)",
+        "data": "synthetic",
+        "config": {"workload": (f"8x8x8 blocks, {info['n_ctrl_total']} control points (24..72 per "
+                                f"axis and block), degree 3, {args.storage} storage; block/tile-"
+                                f"sorted decode of {MB_POINTS} random points + {MB_FRAME}^2 "
+                                f"perspective frame (max 2048 samples/ray)"),
+                   "samples_per_step": samples_step, "frame_samples": s_frame,
+                   "frame_samples_evaluated": s_eval, "parallelism": "single GPU"},
+        "ms_per_frame": kms["render"], "kernels": kernels, "roofline": roofline,
+        "cpu_baseline": cpu}), flush=True)
+    model.close()
+    return 0
+
+
+# ------------------------------------------------------------------ serving workload
+def _serving_trace(n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        if rng.random() < 0.5:
+            side = int(rng.choice([256, 512, 1024, 2048]))
+            reqs.append(("render", int(rng.integers(0, 3)), side,
+                         float(rng.uniform(0, 360)), float(rng.uniform(-60, 60))))
+        else:
+            reqs.append(("points", int(rng.integers(0, 3)), int(10 ** rng.uniform(3, 7)), 0.0, 0.0))
+    return reqs
+
+
+def _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params):
+    """Submits the trace open-loop (exponential gaps at `rate`; rate 0 = all
+    at once) and returns per-request (latency, kind, size) and the wall time."""
+    models = [mfa.Model(sp, st) for sp, st in zip(specs, storages)]
+    S = mfa.Server(hbm_budget_bytes=200 * 10 ** 9, queue_cap=8192, max_batch_items=4096)
+    ids = [S.add_model(M) for M in models]
+    rng = np.random.default_rng(99)
+    gaps = rng.exponential(1.0 / rate, size=len(trace)) if rate > 0 else np.zeros(len(trace))
+    sched = np.cumsum(gaps)
+    slot_ticket = {}
+    tickets = []
+    t0 = time.perf_counter()
+    for k, (kind, mid, size, az, el) in enumerate(trace):
+        delay = t0 + sched[k] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        key = (kind, size if kind == "render" else 0, k % len(pools[kind, size if kind == "render" else 0]))
+        if key in slot_ticket:                          # buffer reuse waits for its last user
+            S.wait(slot_ticket[key])
+        buf = pools[key[0], key[1]][key[2]]
+        lag = time.perf_counter() - (t0 + sched[k])
+        if kind == "render":
+            cam = synth.perspective_camera(size, size, az_deg=az, el_deg=el)
+            t = S.submit_render(ids[mid], cam, params[mid], size, size, buf, tf_dev=tfs[mid])
+        else:
+            t = S.submit_points(ids[mid], xyz, buf, n=size)     # first 3*size floats of xyz
+        slot_ticket[key] = t
+        tickets.append((t, lag, kind, size))
+    out = []
+    for t, lag, kind, size in tickets:
+        st = S.wait(t)
+        out.append((st["t_done"] - st["t_submit"] + lag, kind, size))
+    wall = time.perf_counter() - t0
+    S.close()
+    for M in models:
+        M.close()
+    return out, wall
+
+
+def run_serving(args):
+    """Open-loop Poisson trace over three resident models: the 16^3 model in
+    FP32, the same in BF16 and the 48^3 least-squares model in BF16 (and a
+    plain run with all three in FP32).  Half the requests are renders of
+    256^2..2048^2 from random orbit cameras, half are point batches of
+    10^3..10^7 points."""
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c1 = synth.model_c1()
+    c48 = synth.model_c3_fit48()
+    specs = [c1, c1, c48]
+    params = [synth.render_params(sp) for sp in specs]
+    tfs = [torch.as_tensor(p["tf"], device=dev) for p in params]
+    nmax = 10 ** 7
+    xyz = torch.as_tensor(synth.random_points(nmax, seed=5), device=dev)
+    nslot = 24
+    pools = {("render", s): [torch.empty((s, s, 4), device=dev) for _ in range(nslot)]
+             for s in (256, 512, 1024, 2048)}
+    pools["points", 0] = [torch.empty((nmax, 4), device=dev) for _ in range(nslot)]
+    warm = max(50, args.requests // 10)
+    trace = _serving_trace(warm + args.requests, seed=5)
+    # capacity: the whole trace at once (closed burst)
+    burst = trace[:min(400, len(trace))]
+    _, wall = _serve_run(mfa, torch, dev, specs, ["f32", "bf16", "bf16"], burst, 0.0, pools, xyz,
+                         tfs, params)
+    capacity = len(burst) / wall
+    rate = args.load * capacity
+    res = {}
+    for label, storages in (("bf16_mix", ["f32", "bf16", "bf16"]), ("fp32", ["f32", "f32", "f32"])):
+        lat, wall = _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params)
+        lat = lat[warm:]
+        ms = np.array([x[0] for x in lat]) * 1e3
+        kinds = np.array([x[1] for x in lat])
+        res[label] = {"p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+                      "p50_render_ms": float(np.percentile(ms[kinds == "render"], 50)),
+                      "p99_render_ms": float(np.percentile(ms[kinds == "render"], 99)),
+                      "p50_points_ms": float(np.percentile(ms[kinds == "points"], 50)),
+                      "p99_points_ms": float(np.percentile(ms[kinds == "points"], 99)),
+                      "throughput_rps": len(trace) / wall}
+    print(json.dumps({
+        "metric": METRIC, "value": res["bf16_mix"]["p99_ms"], "unit": "ms (p99 latency)",
+        "n_gpus": 1, "steps": args.requests, "warmup": warm, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (bf16 storage for 2 of 3 models)",
+        "data": "synthetic",
+        "config": {"workload": ("serving: 16^3 FP32, 16^3 BF16 and 48^3 BF16 models resident, "
+                                "open-loop Poisson arrivals, 50 % renders 256^2..2048^2, 50 % point "
+                                "batches 1e3..1e7, 200 GB budget"),
+                   "capacity_rps": capacity, "offered_rps": rate, "load": args.load,
+                   "parallelism": "single GPU"},
+        "serving": res,
+        "p99_bf16_over_fp32": res["bf16_mix"]["p99_ms"] / res["fp32"]["p99_ms"]}), flush=True)
     return 0
 
 

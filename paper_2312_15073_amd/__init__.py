@@ -312,9 +312,13 @@ class Server:
         req.kind = L.MFA_REQ_POINTS
         req.model_id = model_id
         if isinstance(xyz, torch.Tensor):
-            n = int(xyz.shape[1])
-            req.xyz = _dev_ptr(xyz, torch.float32, (3, n), "xyz").value
-            req.out = _dev_ptr(out, torch.float32, (n, 4), "out").value
+            # xyz is read as [3][n] from its start; a larger buffer may carry
+            # a smaller n (its first 3n floats are the coordinates)
+            n = int(xyz.shape[1]) if n is None else int(n)
+            req.xyz = _dev_ptr(xyz, torch.float32, None, "xyz").value
+            req.out = _dev_ptr(out, torch.float32, None, "out").value
+            if xyz.numel() < 3 * n or out.numel() < 4 * n:
+                raise ValueError("xyz / out smaller than 3n / 4n floats")
         else:                    # fake executor: any non-null addresses
             req.xyz, req.out = int(xyz), int(out)
         req.n = int(n)
