@@ -128,7 +128,8 @@ def main(argv=None):
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
                          "serving: open-loop request trace over three resident models")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: measured requests")
+    ap.add_argument("--batch-items", type=int, default=4096, help="serving: work items per batch")
     ap.add_argument("--load", type=float, default=0.6, help="serving: offered load / capacity")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -403,11 +404,11 @@ def _serving_trace(n, seed):
     return reqs
 
 
-def _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params):
+def _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params, batch_items):
     """Submits the trace open-loop (exponential gaps at `rate`; rate 0 = all
     at once) and returns per-request (latency, kind, size) and the wall time."""
     models = [mfa.Model(sp, st) for sp, st in zip(specs, storages)]
-    S = mfa.Server(hbm_budget_bytes=200 * 10 ** 9, queue_cap=8192, max_batch_items=4096)
+    S = mfa.Server(hbm_budget_bytes=200 * 10 ** 9, queue_cap=16384, max_batch_items=batch_items)
     ids = [S.add_model(M) for M in models]
     rng = np.random.default_rng(99)
     gaps = rng.exponential(1.0 / rate, size=len(trace)) if rate > 0 else np.zeros(len(trace))
@@ -463,17 +464,18 @@ def run_serving(args):
     pools = {("render", s): [torch.empty((s, s, 4), device=dev) for _ in range(nslot)]
              for s in (256, 512, 1024, 2048)}
     pools["points", 0] = [torch.empty((nmax, 4), device=dev) for _ in range(nslot)]
-    warm = max(50, args.requests // 10)
+    warm = max(50, args.requests // 20)
     trace = _serving_trace(warm + args.requests, seed=5)
     # capacity: the whole trace at once (closed burst)
     burst = trace[:min(400, len(trace))]
     _, wall = _serve_run(mfa, torch, dev, specs, ["f32", "bf16", "bf16"], burst, 0.0, pools, xyz,
-                         tfs, params)
+                         tfs, params, args.batch_items)
     capacity = len(burst) / wall
     rate = args.load * capacity
     res = {}
     for label, storages in (("bf16_mix", ["f32", "bf16", "bf16"]), ("fp32", ["f32", "f32", "f32"])):
-        lat, wall = _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params)
+        lat, wall = _serve_run(mfa, torch, dev, specs, storages, trace, rate, pools, xyz, tfs, params,
+                               args.batch_items)
         lat = lat[warm:]
         ms = np.array([x[0] for x in lat]) * 1e3
         kinds = np.array([x[1] for x in lat])
@@ -492,6 +494,7 @@ def run_serving(args):
                                 "open-loop Poisson arrivals, 50 % renders 256^2..2048^2, 50 % point "
                                 "batches 1e3..1e7, 200 GB budget"),
                    "capacity_rps": capacity, "offered_rps": rate, "load": args.load,
+                   "batch_items": args.batch_items, "measured_requests": args.requests,
                    "parallelism": "single GPU"},
         "serving": res,
         "p99_bf16_over_fp32": res["bf16_mix"]["p99_ms"] / res["fp32"]["p99_ms"]}), flush=True)

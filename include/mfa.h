@@ -252,8 +252,8 @@ mfa_status mfa_render_frame(mfa_model model, const mfa_camera* camera, const mfa
  * while the bytes of their buffers fit the memory budget, splits them into
  * work items (16x16 pixel tiles, 256-point chunks), packs at most
  * max_batch_items items per batch (a large request spans batches) and runs
- * each batch as persistent launches on the server's own stream; at most two
- * batches are in flight.  Results equal those of mfa_render_frame and
+ * each batch as persistent launches on one of three server-owned streams
+ * (up to three batches overlap).  Results equal those of mfa_render_frame and
  * mfa_decode_points (unsorted) bit for bit.                                */
 typedef struct mfa_server_s* mfa_server;   /* opaque */
 

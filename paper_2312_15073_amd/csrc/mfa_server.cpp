@@ -8,8 +8,8 @@
 // served while the bytes of their buffers fit the budget, split into work
 // items (16x16 pixel tiles, 256-point chunks) and packed into batches of at
 // most max_batch_items items, so a large frame spans several batches and
-// small requests behind it still start soon.  At most two batches are in
-// flight; each is one persistent launch per model kind present.
+// small requests behind it still start soon.  Up to three batches run at
+// once, each on its own stream as one persistent launch per model kind.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,7 +39,7 @@ namespace {
 
 constexpr int kTileEdge = 16;
 constexpr int kChunk = 256;
-constexpr int kMaxInFlight = 2;
+constexpr int kMaxInFlight = 3;
 
 struct Req {
   uint64_t ticket = 0;
@@ -73,10 +73,9 @@ struct Batch {
 
 // Device and pinned host buffers of one batch slot.
 struct Slot {
-  ServeReq* d_reqs = nullptr;
-  ServeItem* d_items = nullptr;
-  int* d_cursors = nullptr;
-  uint8_t* h_stage = nullptr;
+  uint8_t* d_buf = nullptr;     // cursors | requests | items of one batch
+  uint8_t* h_stage = nullptr;   // pinned staging of d_buf
+  hipStream_t stream = nullptr; // batches of different slots overlap
 };
 
 }  // namespace
@@ -85,14 +84,13 @@ struct mfa_server_s {
   mfa_server_config cfg{};
   bool fake = false;
   int device = -1;
-  hipStream_t stream = nullptr;
   int cus = 0;
   std::vector<mfa_model> models;
   DevModel* d_models = nullptr;
   int d_models_cap = 0;
   int max_reqs = 0;
   Slot slots[kMaxInFlight];
-  bool slot_busy[kMaxInFlight] = {false, false};
+  bool slot_busy[kMaxInFlight] = {false, false, false};
 
   std::mutex mu;
   std::condition_variable cv;       // scheduler wake-up
@@ -175,31 +173,25 @@ mfa_status mfa_server_s::launch(Batch& b, const std::vector<ServeItem>& items,
     return MFA_OK;
   }
   Slot& S = slots[b.slot];
-  const size_t rq_bytes = descs.size() * sizeof(ServeReq);
-  const size_t it_bytes = items.size() * sizeof(ServeItem);
-  const size_t cu_bytes = ranges.size() * sizeof(int);
-  // one staging area: requests | items | cursors (zeroed)
-  std::memcpy(S.h_stage, descs.data(), rq_bytes);
-  std::memcpy(S.h_stage + (size_t)max_reqs * sizeof(ServeReq), items.data(), it_bytes);
-  std::memset(S.h_stage + (size_t)max_reqs * sizeof(ServeReq) +
-                  (size_t)cfg.max_batch_items * sizeof(ServeItem), 0, cu_bytes);
-  hipError_t e = hipMemcpyAsync(S.d_reqs, S.h_stage, rq_bytes, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(S.d_items, S.h_stage + (size_t)max_reqs * sizeof(ServeReq), it_bytes,
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(S.d_cursors,
-                       S.h_stage + (size_t)max_reqs * sizeof(ServeReq) +
-                           (size_t)cfg.max_batch_items * sizeof(ServeItem),
-                       cu_bytes, hipMemcpyHostToDevice, stream);
+  // one packed copy per batch: cursors (zeroed) | requests | items
+  const size_t o_req = 64 * sizeof(int);
+  const size_t o_item = (o_req + descs.size() * sizeof(ServeReq) + 15) & ~(size_t)15;
+  const size_t total = o_item + items.size() * sizeof(ServeItem);
+  std::memset(S.h_stage, 0, o_req);
+  std::memcpy(S.h_stage + o_req, descs.data(), descs.size() * sizeof(ServeReq));
+  std::memcpy(S.h_stage + o_item, items.data(), items.size() * sizeof(ServeItem));
+  hipError_t e = hipMemcpyAsync(S.d_buf, S.h_stage, total, hipMemcpyHostToDevice, S.stream);
+  int* d_cursors = (int*)S.d_buf;
+  const ServeReq* d_reqs = (const ServeReq*)(S.d_buf + o_req);
+  const ServeItem* d_items = (const ServeItem*)(S.d_buf + o_item);
   for (size_t k = 0; k < ranges.size() && e == hipSuccess; ++k) {
     const Variant& v = ranges[k].first;
     const int a = ranges[k].second.first, n = ranges[k].second.second - a;
     const int grid = std::min(n, 4 * cus);
-    e = launch_serve(v.p, v.s, v.multi, d_models, S.d_reqs, S.d_items + a, n, S.d_cursors + k, grid,
-                     stream);
+    e = launch_serve(v.p, v.s, v.multi, d_models, d_reqs, d_items + a, n, d_cursors + k, grid,
+                     S.stream);
   }
-  if (e == hipSuccess) e = hipEventRecord(b.ev, stream);
+  if (e == hipSuccess) e = hipEventRecord(b.ev, S.stream);
   if (e != hipSuccess) return hip_fail(e, "server batch launch");
   return MFA_OK;
 }
@@ -225,25 +217,28 @@ void mfa_server_s::run() {
   if (!fake) (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // retire finished batches in order
-    while (!inflight.empty()) {
-      Batch& f = inflight.front();
+    // retire finished batches (slots run on separate streams, so in any order)
+    for (auto it = inflight.begin(); it != inflight.end();) {
       bool fin;
       if (fake) {
-        fin = now() >= f.t_end_fake;
+        fin = now() >= it->t_end_fake;
       } else {
-        const hipError_t q = hipEventQuery(f.ev);
+        const hipError_t q = hipEventQuery(it->ev);
         if (q != hipSuccess && q != hipErrorNotReady) fault = MFA_E_DEVICE;
         fin = q != hipErrorNotReady;
       }
-      if (!fin) break;
-      retire(f, now());
-      inflight.pop_front();
+      if (fin) {
+        retire(*it, now());
+        it = inflight.erase(it);
+      } else {
+        ++it;
+      }
     }
     if (stop && queue.empty() && inflight.empty()) return;
     // start a batch when a slot is free
     if ((int)inflight.size() < kMaxInFlight && !queue.empty()) {
-      int slot = slot_busy[0] ? 1 : 0;
+      int slot = 0;
+      while (slot_busy[slot]) ++slot;
       Batch b;
       b.slot = slot;
       std::vector<ServeItem> items;
@@ -279,13 +274,11 @@ static mfa_status server_free(mfa_server s) {
     for (auto& b : s->inflight)
       if (b.ev) (void)hipEventDestroy(b.ev);
     for (auto& S : s->slots) {
-      if (S.d_reqs) (void)hipFree(S.d_reqs);
-      if (S.d_items) (void)hipFree(S.d_items);
-      if (S.d_cursors) (void)hipFree(S.d_cursors);
+      if (S.d_buf) (void)hipFree(S.d_buf);
       if (S.h_stage) (void)hipHostFree(S.h_stage);
+      if (S.stream) (void)hipStreamDestroy(S.stream);
     }
     if (s->d_models) (void)hipFree(s->d_models);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
   }
   delete s;
   return MFA_OK;
@@ -311,14 +304,12 @@ extern "C" mfa_status mfa_server_create(const mfa_server_config* cfg, mfa_server
     hipDeviceProp_t prop;
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, s->device);
     if (e == hipSuccess) s->cus = prop.multiProcessorCount;
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     for (auto& S : s->slots) {
-      const size_t stage = (size_t)s->max_reqs * sizeof(ServeReq) +
-                           (size_t)s->cfg.max_batch_items * sizeof(ServeItem) + 64 * sizeof(int);
-      if (e == hipSuccess) e = hipMalloc((void**)&S.d_reqs, (size_t)s->max_reqs * sizeof(ServeReq));
-      if (e == hipSuccess) e = hipMalloc((void**)&S.d_items, (size_t)s->cfg.max_batch_items * sizeof(ServeItem));
-      if (e == hipSuccess) e = hipMalloc((void**)&S.d_cursors, 64 * sizeof(int));
-      if (e == hipSuccess) e = hipHostMalloc((void**)&S.h_stage, stage, hipHostMallocDefault);
+      const size_t bytes = 64 * sizeof(int) + (size_t)s->max_reqs * sizeof(ServeReq) + 16 +
+                           (size_t)s->cfg.max_batch_items * sizeof(ServeItem);
+      if (e == hipSuccess) e = hipMalloc((void**)&S.d_buf, bytes);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&S.h_stage, bytes, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking);
     }
     if (e != hipSuccess) {
       server_free(s);
@@ -343,7 +334,9 @@ extern "C" mfa_status mfa_server_add_model(mfa_server s, mfa_model m, int32_t* m
     if (n > s->d_models_cap) {
       const int cap = std::max(8, 2 * n);
       DevModel* nd = nullptr;
-      hipError_t e = hipStreamSynchronize(s->stream);
+      hipError_t e = hipSuccess;
+      for (auto& S : s->slots)
+        if (e == hipSuccess && S.stream) e = hipStreamSynchronize(S.stream);
       if (e == hipSuccess) e = hipMalloc((void**)&nd, (size_t)cap * sizeof(DevModel));
       if (e == hipSuccess && s->d_models)
         e = hipMemcpy(nd, s->d_models, (size_t)(n - 1) * sizeof(DevModel), hipMemcpyDeviceToDevice);
