@@ -599,8 +599,10 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
 
 // ------------------------------------------------------------------ K4: render
 // One ray per lane; a workgroup covers a 16x16 pixel tile (four 8x8 waves).
-// Workgroup i runs on XCD i % 8, so tiles are dealt to XCDs in contiguous
-// bands: each XCD's L2 then holds the part of the model its rays touch.
+// The cost of a tile follows the image content (rays that miss the volume
+// or cross only transparent cells are cheap), so tiles are dealt to the
+// XCDs by interleaved tile rows (see frame_tile) rather than in contiguous
+// bands, which left the XCDs holding the frame's edges idle.
 constexpr int kTile = 16;
 
 
@@ -773,6 +775,23 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   }
 }
 
+// Tile rows are dealt round-robin to the XCDs (row % 8), so every XCD
+// gets rows from the whole frame; workgroups resident on one XCD still
+// cover neighbouring rows of its share.
+__device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
+  const int i = xcd_tile(bid, tx * ty);
+  int base = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int nr = (ty - c + 7) >> 3;
+    if (i < base + nr * tx) {
+      const int o = i - base;
+      return ((o / tx) * 8 + c) * tx + (o % tx);
+    }
+    base += nr * tx;
+  }
+  return 0;
+}
+
 // LDSREC: single-block model whose span records and basis tables are copied
 // into LDS once per workgroup.
 template <int P, Storage S, bool MULTI, bool LDSREC>
@@ -794,8 +813,8 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
     MT = lm;
   }
   stage_tf(r.tf, tf, zpre, wtot);
-  const int ntiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
-  render_tile<P, S, MULTI>(m, r, xcd_tile(blockIdx.x, ntiles), R, MT, tf, zpre);
+  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+  render_tile<P, S, MULTI>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
 }
 
 // ------------------------------------------------------------------ K6: persistent serving
