@@ -197,7 +197,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_ws};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_bwin, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -466,6 +466,32 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     acc += t;
   }
   m->n_buckets = buckets;
+  // control-point window of each sort bucket, in bucket order: the tile's
+  // spans widened by one span on each side, clamped to the block
+  std::vector<BucketWin> bwin;
+  if (buckets <= kMaxBuckets) {
+    bwin.reserve((size_t)buckets);
+    for (int64_t b = 0; b < nb; ++b) {
+      int td[3];
+      for (int a = 0; a < 3; ++a) td[a] = (dblk[b].nsp[a] + (1 << sort_shift) - 1) >> sort_shift;
+      for (int t0 = 0; t0 < td[0]; ++t0)
+        for (int t1 = 0; t1 < td[1]; ++t1)
+          for (int t2 = 0; t2 < td[2]; ++t2) {
+            const int t[3] = {t0, t1, t2};
+            BucketWin w{};
+            w.block = (int32_t)b;
+            for (int a = 0; a < 3; ++a) {
+              const int j0 = std::max((t[a] << sort_shift) - 1, 0);
+              const int j1 = std::min((t[a] + 1) << sort_shift, dblk[b].nsp[a] - 1);
+              w.o[a] = j0;
+              w.w[a] = j1 + p - j0 + 1;
+            }
+            bwin.push_back(w);
+          }
+    }
+  }
+  int32_t win_max = 0;
+  for (const BucketWin& w : bwin) win_max = std::max(win_max, w.w[0] * w.w[1] * w.w[2]);
   const int64_t pool_bytes = off * es + 64;       // tail pad: 16-bit rows read one word ahead
   if (pool_bytes > 0xFFFFFFFFll) {
     free_model(m);
@@ -543,7 +569,9 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_mats, mats.data(), mats.size() * sizeof(float), m, "basis upload")) != MFA_OK ||
       (st = upload(&m->d_blocks, dblk.data(), dblk.size() * sizeof(DevBlock), m, "block upload")) != MFA_OK ||
       (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK ||
-      (st = upload(&m->d_mcb, mcb16.data(), mcb16.size() * sizeof(uint32_t), m, "bounds upload")) != MFA_OK) {
+      (st = upload(&m->d_mcb, mcb16.data(), mcb16.size() * sizeof(uint32_t), m, "bounds upload")) != MFA_OK ||
+      (!bwin.empty() &&
+       (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK)) {
     free_model(m);
     return st;
   }
@@ -571,6 +599,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   dm.mc_shift = mc_shift;
   dm.sort_shift = sort_shift;
   dm.mcb = m->d_mcb;
+  dm.bwin = m->d_bwin;
+  dm.win_max = win_max;
   dm.b0 = dblk[0];
   *out = m;
   return MFA_OK;
@@ -640,7 +670,7 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
   if (st != MFA_OK) return st;
   if (flags & MFA_DECODE_SORTED) {
     // scratch: one 16-byte sorted record per point; counts, starts and
-    // cursors per bucket
+    // cursors per bucket; the decode items
     if (m->n_buckets > kMaxBuckets)
       return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -648,7 +678,9 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     const size_t o_rec = 0;
     const size_t o_hist = o_rec + al(16 * (size_t)n), o_start = o_hist + al(4 * nbk);
     const size_t o_cur = o_start + al(4 * nbk);
-    const size_t need = o_cur + al(4 * nbk);
+    const size_t n_items = (size_t)((n + kTilePoints - 1) / kTilePoints) + nbk;
+    const size_t o_items = o_cur + al(4 * nbk), o_nitems = o_items + al(8 * n_items);
+    const size_t need = o_nitems + al(4);
     if (need > m->ws_bytes) {
       if (m->d_ws) {
         hipError_t fe = hipFree(m->d_ws);   // waits for work still using it
@@ -670,6 +702,8 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     sa.hist = (uint32_t*)(w + o_hist);
     sa.start = (uint32_t*)(w + o_start);
     sa.cursor = (uint32_t*)(w + o_cur);
+    sa.items = (int2*)(w + o_items);
+    sa.n_items = (int32_t*)(w + o_nitems);
     sa.nb = (int32_t)nbk;
     hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), m->nblocks > 1, sa, out, dbg,
                                         (hipStream_t)stream);

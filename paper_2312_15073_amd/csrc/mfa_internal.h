@@ -51,6 +51,22 @@ static_assert(sizeof(DevBlock) == 144, "DevBlock layout");
 // are at most kMaxBuckets buckets.
 constexpr int kMaxBuckets = 4096;
 
+// Sorted decode works on items of at most kTilePoints consecutive sorted
+// points of one bucket.  The control points a bucket's points can touch
+// (its spans widened by one span on each side, where the exact span of a
+// point can differ from the estimate that chose its bucket) form a window
+// that is staged in LDS when it holds at most kWinMax values.
+constexpr int kTilePoints = 2048;
+constexpr int kWinMax = 8192;
+
+struct BucketWin {
+  int32_t block;        // owning block
+  int32_t o[3];         // first control index of the window per axis
+  int32_t w[3];         // window extent per axis (control points)
+  int32_t pad;
+};
+static_assert(sizeof(BucketWin) == 32, "BucketWin layout");
+
 // Spans per axis grouped into one macro cell for the value bounds used to
 // skip samples that the transfer function makes fully transparent: 2^shift,
 // shift in [0, kMaxMacroShift], chosen per model (DevModel::mc_shift).
@@ -72,6 +88,8 @@ struct DevModel {
   int32_t imat;          // id of the uniform interior table (UniformTable), or -1
   int32_t mc_shift;      // log2 of the spans per macro cell and axis
   int32_t sort_shift;    // log2 of the spans per sort tile and axis
+  const BucketWin* bwin;  // per sort bucket: control-point window
+  int32_t win_max;       // largest window (values)
   const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
@@ -141,6 +159,8 @@ struct SortArgs {
   uint32_t* hist;        // [nb] points per bucket
   uint32_t* start;       // [nb] first sorted position of each bucket
   uint32_t* cursor;      // [nb] positions handed out so far per bucket
+  int2* items;           // [<= n / kTilePoints + nb] (bucket, part) per decode item
+  int32_t* n_items;      // number of items
   int32_t nb;            // buckets (<= kMaxBuckets)
 };
 

@@ -195,15 +195,15 @@ __device__ __forceinline__ void basis(const float* __restrict__ mats, int stride
 // ------------------------------------------------------------------ contraction
 // f = sum_ijk Nx_i Ny_j Nz_k P_ijk and the three partials with one factor
 // replaced by its derivative, summed axis 2 first, then axis 1, then axis 0.
-// e0: element index of P[i0][j0][k0] (per lane); rows at + i*s0 + j*s1.
-// UNIFORM_STRIDES: s0, s1 are wave-uniform and go into the scalar offset.
-template <int P, Storage S, bool UNIFORM_STRIDES>
-__device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0, uint32_t s0,
-                                         uint32_t s1, const float (&Nx)[P + 1],
-                                         const float (&Dx)[P + 1], const float (&Ny)[P + 1],
-                                         const float (&Dy)[P + 1], const float (&Nz)[P + 1],
-                                         const float (&Dz)[P + 1], float& f, float& fx, float& fy,
-                                         float& fz) {
+// row(i, j, v) fills v with the P+1 control points P[i0+i][j0+j][k0..k0+P];
+// every source of rows goes through this one summation order, so results do
+// not depend on where the rows come from.
+template <int P, class RowFn>
+__device__ __forceinline__ void contract_rows(RowFn row, const float (&Nx)[P + 1],
+                                              const float (&Dx)[P + 1], const float (&Ny)[P + 1],
+                                              const float (&Dy)[P + 1], const float (&Nz)[P + 1],
+                                              const float (&Dz)[P + 1], float& f, float& fx,
+                                              float& fy, float& fz) {
   f = fx = fy = fz = 0.f;
 #pragma unroll
   for (int i = 0; i <= P; ++i) {
@@ -211,10 +211,7 @@ __device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0,
 #pragma unroll
     for (int j = 0; j <= P; ++j) {
       float v[P + 1];
-      if constexpr (UNIFORM_STRIDES)
-        Row<P, S>::load(rs, e0, (uint32_t)i * s0 + (uint32_t)j * s1, v);
-      else
-        Row<P, S>::load(rs, e0 + (uint32_t)i * s0 + (uint32_t)j * s1, 0u, v);
+      row(i, j, v);
       float z = 0.f, zd = 0.f;
 #pragma unroll
       for (int k = 0; k <= P; ++k) {
@@ -230,6 +227,25 @@ __device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0,
     fy = fmaf(Nx[i], yy, fy);
     fz = fmaf(Nx[i], yz, fz);
   }
+}
+
+// Rows from the control-point pool in global memory.
+// e0: element index of P[i0][j0][k0] (per lane); rows at + i*s0 + j*s1.
+// UNIFORM_STRIDES: s0, s1 are wave-uniform and go into the scalar offset.
+template <int P, Storage S, bool UNIFORM_STRIDES>
+__device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0, uint32_t s0,
+                                         uint32_t s1, const float (&Nx)[P + 1],
+                                         const float (&Dx)[P + 1], const float (&Ny)[P + 1],
+                                         const float (&Dy)[P + 1], const float (&Nz)[P + 1],
+                                         const float (&Dz)[P + 1], float& f, float& fx, float& fy,
+                                         float& fz) {
+  auto row = [&](int i, int j, float (&v)[P + 1]) {
+    if constexpr (UNIFORM_STRIDES)
+      Row<P, S>::load(rs, e0, (uint32_t)i * s0 + (uint32_t)j * s1, v);
+    else
+      Row<P, S>::load(rs, e0 + (uint32_t)i * s0 + (uint32_t)j * s1, 0u, v);
+  };
+  contract_rows<P>(row, Nx, Dx, Ny, Dy, Nz, Dz, f, fx, fy, fz);
 }
 
 // ------------------------------------------------------------------ point location
@@ -399,37 +415,57 @@ __global__ __launch_bounds__(kBlock) void sort_hist_k(DevModel m, SortArgs sa) {
     if (h[b]) atomicAdd(sa.hist + b, h[b]);
 }
 
-// Exclusive scan of the bucket counts (one workgroup) and reset of cursors.
-__global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
-  __shared__ uint32_t wsum[kBlock / kWave];
-  constexpr int kPer = kMaxBuckets / kBlock;
+// Exclusive scan over the workgroup of one value per thread; returns the
+// thread's exclusive prefix, the total in *tot.  wsum: kBlock / kWave words.
+__device__ __forceinline__ uint32_t block_scan(uint32_t s, uint32_t* wsum, uint32_t* tot) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  uint32_t v[kPer], s = 0;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int b = threadIdx.x * kPer + q;
-    v[q] = b < sa.nb ? sa.hist[b] : 0u;
-    s += v[q];
-  }
   uint32_t inc = s;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const uint32_t o = __shfl_up(inc, off);
     if (lane >= off) inc += o;
   }
+  __syncthreads();
   if (lane == kWave - 1) wsum[wave] = inc;
   __syncthreads();
-  uint32_t run = inc - s;
-  for (int w = 0; w < wave; ++w) run += wsum[w];
+  uint32_t run = inc - s, all = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    if (w < wave) run += wsum[w];
+    all += wsum[w];
+  }
+  *tot = all;
+  return run;
+}
+
+// One workgroup: exclusive scan of the bucket counts, reset of the cursors,
+// and the list of decode items (bucket, part), ceil(count / kTilePoints)
+// parts per bucket in bucket order.
+__global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
+  __shared__ uint32_t wsum[kBlock / kWave];
+  constexpr int kPer = kMaxBuckets / kBlock;
+  uint32_t v[kPer], s = 0, parts = 0, tot;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int b = threadIdx.x * kPer + q;
+    v[q] = b < sa.nb ? sa.hist[b] : 0u;
+    s += v[q];
+    parts += (v[q] + kTilePoints - 1) / kTilePoints;
+  }
+  uint32_t run = block_scan(s, wsum, &tot);
+  uint32_t irun = block_scan(parts, wsum, &tot);
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int b = threadIdx.x * kPer + q;
     if (b < sa.nb) {
       sa.start[b] = run;
       sa.cursor[b] = 0u;
+      const uint32_t np = (v[q] + kTilePoints - 1) / kTilePoints;
+      for (uint32_t u = 0; u < np; ++u) sa.items[irun + u] = make_int2(b, (int)u);
+      irun += np;
     }
     run += v[q];
   }
+  if (threadIdx.x == 0) *sa.n_items = (int32_t)tot;
 }
 
 template <bool MULTI>
@@ -465,23 +501,141 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
   }
 }
 
-// Decode in sorted order (workgroup ranges dealt to XCDs in contiguous
-// bands); results go to the input positions.
-template <int P, Storage S, bool MULTI>
-__global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
-                                                          float* __restrict__ out,
-                                                          int32_t* __restrict__ dbg) {
-  const int nchunks = (int)((sa.n + kBlock - 1) / kBlock);
-  const int64_t t = (int64_t)xcd_tile(blockIdx.x, nchunks) * kBlock + threadIdx.x;
-  if (t >= sa.n) return;
+// One stored control point, converted to FP32 as the row loaders do.
+template <Storage S>
+__device__ __forceinline__ float load_one(__amdgpu_buffer_rsrc_t rs, uint32_t e) {
+  if constexpr (S == Storage::F32) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, e * 4u, 0u, 0));
+  } else {
+    const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(rs, e * 2u, 0u, 0);
+    if constexpr (S == Storage::BF16)
+      return __uint_as_float((uint32_t)h << 16);
+    else
+      return __half2float(__ushort_as_half(h));
+  }
+}
+
+// Value and world gradient with the control rows read from an LDS window:
+// Wp points at P[i0][j0][k0] of the window, rows at + i*sw0 + j*sw1.
+template <int P>
+__device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, int sw0, int sw1,
+                                               const float* __restrict__ mats, int stride,
+                                               int imat) {
+  float N[3][P + 1], D[3][P + 1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) basis<P>(mats, stride, L.mat[a], imat, L.tau[a], N[a], D[a]);
+  float f, fx, fy, fz;
+  auto row = [&](int i, int j, float (&v)[P + 1]) {
+    const float* r = Wp + i * sw0 + j * sw1;
+#pragma unroll
+    for (int k = 0; k <= P; ++k) v[k] = r[k];
+  };
+  contract_rows<P>(row, N[0], D[0], N[1], D[1], N[2], D[2], f, fx, fy, fz);
+  return make_float4(f, fx * L.ds[0], fy * L.ds[1], fz * L.ds[2]);
+}
+
+// Decode in sorted order, one item (up to kTilePoints points of one bucket)
+// per workgroup; results go to the input positions.  The bucket's window of
+// control points is staged in LDS once (when it holds at most win_cap
+// values); a point whose exact spans fall outside the window (possible only
+// for non-uniform knots) reads its rows from global memory.  Both paths sum
+// in the same order.  LDSREC: the span records and basis tables of a
+// single-block model are staged too, ahead of the window.
+template <int P, Storage S, bool MULTI, bool LDSREC>
+__global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
+                                                         float* __restrict__ out,
+                                                         int32_t* __restrict__ dbg) {
+  extern __shared__ float4 dyn[];
+  const int item = blockIdx.x;
+  if (item >= *sa.n_items) return;                 // whole workgroup
+  const SpanRec* R = m.rec;
+  const float* MT = m.mats;
+  float* W = reinterpret_cast<float*>(dyn);
+  if constexpr (LDSREC) {
+    SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
+    float* lm = reinterpret_cast<float*>(lr + m.n_rec);
+    for (int q = threadIdx.x; q < m.n_rec * 2; q += kBlock)
+      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
+    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    R = lr;
+    MT = lm;
+    W = lm + m.n_mats * m.mat_stride;
+  }
+  const int2 it = sa.items[item];
+  const int b = it.x;
+  const uint32_t end = b + 1 < sa.nb ? sa.start[b + 1] : (uint32_t)sa.n;
+  const uint32_t s0 = sa.start[b] + (uint32_t)it.y * (uint32_t)kTilePoints;
+  const uint32_t s1 = min(s0 + (uint32_t)kTilePoints, end);
+  const BucketWin bw = m.bwin[b];
+  const int w12 = bw.w[1] * bw.w[2];
+  const int wn = bw.w[0] * w12;
+  const bool staged = wn <= win_cap;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
-  const float4 q = sa.rec[t];
-  const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
-  const Loc L = locate<P, MULTI>(m, m.rec, x);
-  const uint32_t i = __float_as_uint(q.w);
-  if ((int64_t)i >= sa.n) return;
-  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
-  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
+  if (staged) {
+    // lanes cover rpi whole rows of the window per pass (k = lane % w2);
+    // the row index (i, j) of each lane advances without divisions
+    const DevBlock* __restrict__ B = MULTI ? m.blocks + bw.block : &m.b0;
+    const uint32_t n1 = (uint32_t)B->n[1], rs1 = (uint32_t)B->rs1;
+    const int w1 = bw.w[1], w2 = bw.w[2], rows = bw.w[0] * w1;
+    if (w2 <= kWave) {
+      const int rpi = kWave / w2, lane = threadIdx.x & (kWave - 1);
+      const int sub = lane / w2, k = lane - sub * w2;
+      const int step = rpi * (kBlock / kWave);
+      int row = (threadIdx.x / kWave) * rpi + sub;
+      int i = row / w1, j = row - i * w1;
+      const int di = step / w1, dj = step - di * w1;
+      for (; row < rows; row += step) {
+        if (sub < rpi) {
+          const uint32_t e = (uint32_t)B->ctrl_off +
+                             ((uint32_t)(bw.o[0] + i) * n1 + (uint32_t)(bw.o[1] + j)) * rs1 +
+                             (uint32_t)(bw.o[2] + k);
+          W[row * w2 + k] = load_one<S>(rs, e);
+        }
+        i += di;
+        j += dj;
+        if (j >= w1) {
+          j -= w1;
+          ++i;
+        }
+      }
+    } else {
+      for (int q = threadIdx.x; q < wn; q += kBlock) {
+        const int i = q / w12, r = q - i * w12, j = r / w2, k = r - j * w2;
+        const uint32_t e = (uint32_t)B->ctrl_off +
+                           ((uint32_t)(bw.o[0] + i) * n1 + (uint32_t)(bw.o[1] + j)) * rs1 +
+                           (uint32_t)(bw.o[2] + k);
+        W[q] = load_one<S>(rs, e);
+      }
+    }
+  }
+  __syncthreads();
+  if (s0 >= s1) return;
+  uint32_t t = s0 + threadIdx.x;
+  float4 q = sa.rec[min(t, s1 - 1)];
+  for (; t < s1; t += kBlock) {
+    const float4 qn = sa.rec[min(t + kBlock, s1 - 1)];   // next record in flight
+    const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
+    const Loc L = locate<P, MULTI>(m, R, x);
+    const uint32_t i = __float_as_uint(q.w);
+    q = qn;
+    if ((int64_t)i >= sa.n) continue;
+    int d[3];
+    bool in = staged && L.block == bw.block;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d[a] = L.j[a] - bw.o[a];
+      in = in && d[a] >= 0 && d[a] <= bw.w[a] - 1 - P;
+    }
+    float4 res;
+    if (in)
+      res = evaluate_lds<P>(L, W + (d[0] * bw.w[1] + d[1]) * bw.w[2] + d[2], w12, bw.w[2], MT,
+                            m.mat_stride, m.imat);
+    else
+      res = evaluate<P, S, !MULTI>(L, rs, MT, m.mat_stride, m.imat);
+    reinterpret_cast<float4*>(out)[i] = res;
+    if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
+  }
 }
 
 // ------------------------------------------------------------------ K3: grid
@@ -861,6 +1015,9 @@ __global__ __launch_bounds__(kBlock) void serve_k(const DevModel* __restrict__ m
 }
 
 // ------------------------------------------------------------------ launchers
+// Span records and tables go to LDS when they fit this budget.
+constexpr int kLdsRecBytes = 40 * 1024;
+
 template <int P, Storage S>
 static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int64_t n, float* out,
                            int32_t* dbg, hipStream_t st) {
@@ -877,7 +1034,6 @@ static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int6
 template <int P, Storage S>
 static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
-  const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
   const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
   const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
@@ -890,10 +1046,20 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
     hipLaunchKernelGGL(sort_scatter_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
   else
     hipLaunchKernelGGL(sort_scatter_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+  // items: at most ceil(n / kTilePoints) + nb; the surplus workgroups exit
+  const unsigned gi = (unsigned)((sa.n + kTilePoints - 1) / kTilePoints + sa.nb);
+  const int cap = m.win_max <= kWinMax ? m.win_max : kWinMax;
+  const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
+  const size_t wb = (size_t)cap * 4;
   if (multi)
-    hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+    hipLaunchKernelGGL((decode_tiles_k<P, S, true, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
+                       cap, out, dbg);
+  else if (tabs <= (size_t)kLdsRecBytes)
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true>), dim3(gi), dim3(kBlock), tabs + wb, st,
+                       m, sa, cap, out, dbg);
   else
-    hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
+                       cap, out, dbg);
   return hipGetLastError();
 }
 
@@ -916,9 +1082,6 @@ static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
   hipLaunchKernelGGL((decode_grid_k<P, S>), grid, dim3(kBlock), 0, st, m, ga);
   return hipGetLastError();
 }
-
-// Span records and tables go to LDS when they fit this budget.
-constexpr int kLdsRecBytes = 40 * 1024;
 
 template <int P, Storage S>
 static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {

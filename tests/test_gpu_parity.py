@@ -424,7 +424,7 @@ def _sorted_matches_unsorted(mfa, dev, model, pts, storage="f32"):
     return a
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 def test_sorted_decode_single_block(mfa, dev, c1, storage):
     rng = np.random.default_rng(30)
     pts = adversarial_points(c1, rng, 50000).T.copy()
@@ -433,6 +433,26 @@ def test_sorted_decode_single_block(mfa, dev, c1, storage):
     if storage == "f32":
         ref = oracle_points(c1, pts.T)
         assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(c1.blocks[0].ctrl)))
+
+
+def test_sorted_decode_graded_knots(mfa, dev):
+    # Knots crowded towards 0 along every axis: the bucket estimate
+    # floor(u * nsp) then lies far from the exact span for most points, whose
+    # rows come from global memory instead of the bucket's LDS window.
+    rng = np.random.default_rng(41)
+    p = 3
+    ns = (40, 33, 47)
+    knots = []
+    for n in ns:
+        inner = np.linspace(0, 1, n - p + 1)[1:-1] ** 2
+        knots.append(np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)]))
+    P = rng.standard_normal(ns)
+    model = synth.single_block_model(P, [p] * 3, knots, lo=(-1.0, 0.0, 2.0), hi=(1.0, 0.5, 5.0))
+    pts = (model.lo + rng.random((200000, 3)) * (model.hi - model.lo)).astype(np.float32).T.copy()
+    announce("sorted decode graded knots")
+    out = _sorted_matches_unsorted(mfa, dev, model, pts)
+    ref = oracle_points(model, pts.T)
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)))
 
 
 def test_sorted_decode_multiblock_and_scratch_regrowth(mfa, dev):
