@@ -42,6 +42,32 @@ GRID_N = 512
 N_POINTS = 10_000_000
 FRAME = 1024
 
+# HBM bytes per launch of a kernel of the default workload (FP32 storage),
+# from rocprofv3 --pmc runs of this script, one counter per run (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+# reads on the plain copy that --copy-calibration adds (bytes moved / KiB
+# read).  An entry holds only for the kernel source it was measured on.
+TRAFFIC = {
+    # 1024^2 frame of the 128^3 model; copy reference: 512 MiB read + 512 MiB
+    # written, FETCH_SIZE 262158 KiB (scale 2.0), WRITE_SIZE 524288 KiB (1.0)
+    "render": {"kernels_sha256": "2aeb26500d89798148a98fe15fa2d4369c2ce6c639907aa1f40307e6069f0706",
+               "fetch_kib": 39975.0, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0},
+}
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2312_15073_amd", "csrc", "mfa_kernels.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_bytes(kernel: str, storage: str):
+    t = TRAFFIC.get(kernel)
+    if t is None or storage != "f32" or t["kernels_sha256"] != kernel_source_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def flop_per_sample(p: int) -> int:
     q = p + 1
@@ -124,10 +150,16 @@ def main(argv=None):
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single128",
-                    choices=["single128", "multiblock", "serving"],
+                    choices=["single128", "multiblock", "serving", "points"],
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
-                         "serving: open-loop request trace over three resident models")
+                         "serving: open-loop request trace over three resident models; "
+                         "points: point decode alone, input order vs block/tile-sorted order")
+    ap.add_argument("--points-model", default="single128", choices=["single128", "multiblock"],
+                    help="points: the 128^3 model with 1e7 points or the 8x8x8-block model with 1e8")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run two plain device copies of this many MiB before timing (reference "
+                         "for HBM byte counters)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: measured requests")
     ap.add_argument("--batch-items", type=int, default=4096, help="serving: work items per batch")
     ap.add_argument("--load", type=float, default=0.6, help="serving: offered load / capacity")
@@ -141,6 +173,8 @@ def main(argv=None):
         return run_multiblock(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "points":
+        return run_points(args)
     if args.steps is None:
         args.steps = 20
     return run_single128(args)
@@ -160,6 +194,7 @@ def run_single128(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    copy_calibration(torch, dev, args.copy_calibration)
     model = mfa.Model(spec, args.storage)
     axes = [torch.as_tensor(synth.grid_axis(GRID_N), device=dev) for _ in range(3)]
     xyz = torch.as_tensor(pts, device=dev)
@@ -232,7 +267,8 @@ def run_single128(args):
     dom = max(kernels, key=lambda n: kernels[n]["ms"])
     dk = kernels[dom]
     roofline = {"bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
-                "unit": dk["unit"], "frac": dk["frac"], "traffic": None, "kernel": dom}
+                "unit": dk["unit"], "frac": dk["frac"],
+                "traffic": traffic_bytes(dom, args.storage), "kernel": dom}
     if dk["bound"] == "alu":
         roofline["peak_unpacked_fp32"] = PEAK_FP32_ISSUABLE_TFLOPS
         roofline["frac_unpacked_fp32"] = dk["achieved"] / PEAK_FP32_ISSUABLE_TFLOPS
@@ -386,6 +422,67 @@ def run_multiblock(args):
                    "frame_samples_evaluated": s_eval, "parallelism": "single GPU"},
         "ms_per_frame": kms["render"], "kernels": kernels, "roofline": roofline,
         "cpu_baseline": cpu}), flush=True)
+    model.close()
+    return 0
+
+
+def copy_calibration(torch, dev, mib):
+    """Two plain device-to-device copies of `mib` MiB: the reference the HBM
+    byte counters (FETCH_SIZE, WRITE_SIZE) are scaled by."""
+    if mib <= 0:
+        return
+    a = torch.ones(mib * 2 ** 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+# ------------------------------------------------------------------ point-decode workload
+def run_points(args):
+    """Point decode alone: the same points in input order and through the
+    block/tile sort, timed per call with HIP events."""
+    steps = 5 if args.steps is None else args.steps
+    if args.points_model == "multiblock":
+        spec, n, seed, name = synth.model_c4(), MB_POINTS, 14, "8x8x8-block model"
+    else:
+        spec, n, seed, name = synth.model_c2(), N_POINTS, 12, "single block, 128^3 control points"
+    pts = synth.random_points(n, seed=seed)
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    copy_calibration(torch, dev, args.copy_calibration)
+    model = mfa.Model(spec, args.storage)
+    xyz = torch.as_tensor(pts, device=dev)
+    del pts
+    out = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    res = {}
+    for label, srt in (("input_order", False), ("sorted", True)):
+        for _ in range(args.warmup):
+            mfa.decode_points(model, xyz, out=out, sorted_order=srt)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            mfa.decode_points(model, xyz, out=out, sorted_order=srt)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+        res[label] = {"ms": ms, "samples_per_s": n / (ms * 1e-3)}
+    info = model.info()
+    print(json.dumps({
+        "metric": "decoded samples/s (value+grad), random points", "value": res["sorted"]["samples_per_s"],
+        "unit": "samples/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": res["sorted"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.storage == "f32" else f"f32 ({args.storage} storage)",
+        "data": "synthetic",
+        "config": {"workload": f"{name} ({info['n_ctrl_total']} control points, degree 3, "
+                               f"{args.storage} storage), {n} uniform random points",
+                   "parallelism": "single GPU"},
+        "decode": res, "sorted_speedup": res["input_order"]["ms"] / res["sorted"]["ms"]}), flush=True)
     model.close()
     return 0
 

@@ -638,6 +638,26 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   }
 }
 
+// Sorted decode for models whose bucket windows exceed the LDS budget: one
+// point per thread over the sorted records (workgroup ranges dealt to XCDs
+// in contiguous bands), rows from global memory.
+template <int P, Storage S, bool MULTI>
+__global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
+                                                          float* __restrict__ out,
+                                                          int32_t* __restrict__ dbg) {
+  const int nchunks = (int)((sa.n + kBlock - 1) / kBlock);
+  const int64_t t = (int64_t)xcd_tile(blockIdx.x, nchunks) * kBlock + threadIdx.x;
+  if (t >= sa.n) return;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const float4 q = sa.rec[t];
+  const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
+  const Loc L = locate<P, MULTI>(m, m.rec, x);
+  const uint32_t i = __float_as_uint(q.w);
+  if ((int64_t)i >= sa.n) return;
+  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
+  if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
+}
+
 // ------------------------------------------------------------------ K3: grid
 // One wave = 64 consecutive entries c of axis 2 for one entry b of axis 1
 // and a run of up to ga.ta entries a of axis 0.  The axis-0 bases of the
@@ -1046,9 +1066,18 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
     hipLaunchKernelGGL(sort_scatter_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
   else
     hipLaunchKernelGGL(sort_scatter_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+  if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
+    const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
+    if (multi)
+      hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
+    else
+      hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out,
+                         dbg);
+    return hipGetLastError();
+  }
   // items: at most ceil(n / kTilePoints) + nb; the surplus workgroups exit
   const unsigned gi = (unsigned)((sa.n + kTilePoints - 1) / kTilePoints + sa.nb);
-  const int cap = m.win_max <= kWinMax ? m.win_max : kWinMax;
+  const int cap = m.win_max;
   const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   const size_t wb = (size_t)cap * 4;
   if (multi)
