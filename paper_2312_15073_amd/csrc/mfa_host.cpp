@@ -197,7 +197,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_bwin, m->d_ws};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -443,8 +443,13 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       break;
     }
   }
+  const int sc_shift[2] = {mc_shift + kSuperShift[0], mc_shift + kSuperShift[1]};
   for (int64_t b = 0; b < nb; ++b)
-    for (int a = 0; a < 3; ++a) dblk[b].mc[a] = (dblk[b].nsp[a] + (1 << mc_shift) - 1) >> mc_shift;
+    for (int a = 0; a < 3; ++a) {
+      dblk[b].mc[a] = (dblk[b].nsp[a] + (1 << mc_shift) - 1) >> mc_shift;
+      for (int l = 0; l < 2; ++l)
+        dblk[b].sc[l][a] = (dblk[b].nsp[a] + (1 << sc_shift[l]) - 1) >> sc_shift[l];
+    }
   // sort tiles: the finest power-of-two span groups giving at most
   // kMaxBuckets buckets (blocks count at least one bucket each)
   int sort_shift = -1;
@@ -501,7 +506,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   // storage rounding
   std::vector<uint8_t> pool((size_t)pool_bytes, 0);
   float vmin = INFINITY, vmax = -INFINITY;
-  std::vector<float2> mcb;
+  std::vector<float2> mcb, scb[2];
   for (int64_t b = 0; b < nb; ++b) {
     const mfa_block_desc& B = blocks[b];
     const int n0 = B.n_ctrl[0], n1 = B.n_ctrl[1], n2 = B.n_ctrl[2];
@@ -541,6 +546,10 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     }
     dblk[b].mc_off = (int32_t)mcb.size();
     macro_bounds(V, B.n_ctrl, p, mc_shift, dblk[b].mc, mcb);
+    for (int l = 0; l < 2; ++l) {
+      dblk[b].sc_off[l] = (int32_t)scb[l].size();
+      macro_bounds(V, B.n_ctrl, p, sc_shift[l], dblk[b].sc[l], scb[l]);
+    }
   }
   m->vmin = vmin;
   m->vmax = vmax;
@@ -548,10 +557,14 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   // tables and sums in FP32 stay within ~1e-6 of the exact convex
   // combination relative to max |P|).
   const float margin = 1e-4f * std::fmax(std::fabs(vmin), std::fabs(vmax));
-  std::vector<uint32_t> mcb16(mcb.size());
-  for (size_t q = 0; q < mcb.size(); ++q)
-    mcb16[q] = (uint32_t)f16_directed(mcb[q].x - margin, false) |
-               ((uint32_t)f16_directed(mcb[q].y + margin, true) << 16);
+  auto pack16 = [margin](const std::vector<float2>& v) {
+    std::vector<uint32_t> o(v.size());
+    for (size_t q = 0; q < v.size(); ++q)
+      o[q] = (uint32_t)f16_directed(v[q].x - margin, false) |
+             ((uint32_t)f16_directed(v[q].y + margin, true) << 16);
+    return o;
+  };
+  const std::vector<uint32_t> mcb16 = pack16(mcb), scb16[2] = {pack16(scb[0]), pack16(scb[1])};
   // the uniform interior table, evaluated from literals by the kernels
   const auto ic = mat_ids.find(canon);
   const int imat = ic == mat_ids.end() ? -1 : ic->second;
@@ -570,6 +583,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_blocks, dblk.data(), dblk.size() * sizeof(DevBlock), m, "block upload")) != MFA_OK ||
       (st = upload(&m->d_edges, edge_pool.data(), edge_pool.size() * sizeof(double), m, "edge upload")) != MFA_OK ||
       (st = upload(&m->d_mcb, mcb16.data(), mcb16.size() * sizeof(uint32_t), m, "bounds upload")) != MFA_OK ||
+      (st = upload(&m->d_scb[0], scb16[0].data(), scb16[0].size() * 4, m, "bounds upload")) != MFA_OK ||
+      (st = upload(&m->d_scb[1], scb16[1].data(), scb16[1].size() * 4, m, "bounds upload")) != MFA_OK ||
       (!bwin.empty() &&
        (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK)) {
     free_model(m);
@@ -599,6 +614,10 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   dm.mc_shift = mc_shift;
   dm.sort_shift = sort_shift;
   dm.mcb = m->d_mcb;
+  for (int l = 0; l < 2; ++l) {
+    dm.scb[l] = m->d_scb[l];
+    dm.sc_shift[l] = sc_shift[l];
+  }
   dm.bwin = m->d_bwin;
   dm.win_max = win_max;
   dm.b0 = dblk[0];

@@ -42,9 +42,11 @@ struct DevBlock {
   int32_t mc_off;       // index of the block's first macro cell in the bounds pool
   double ext[3];        // hi - lo (estimates of cell exits only)
   int32_t tile_off;     // first sort bucket of the block
+  int32_t sc_off[2];    // per super-cell level: the block's first cell in that level's pool
+  int32_t sc[2][3];     // per level: cells per axis = ceil(nsp / 2^sc_shift[level])
   int32_t pad;
 };
-static_assert(sizeof(DevBlock) == 144, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 176, "DevBlock layout");
 
 // Points sorted for decode are grouped by (block, tile); a tile spans
 // 2^sort_shift knot spans per axis, the shift chosen per model so that there
@@ -72,6 +74,11 @@ static_assert(sizeof(BucketWin) == 32, "BucketWin layout");
 // shift in [0, kMaxMacroShift], chosen per model (DevModel::mc_shift).
 constexpr int kMaxMacroShift = 2;
 
+// Two coarser levels of the same bounds, super cells of 2^3 and 2^2 macro
+// cells per axis, let a ray cross the transparent stretch in front of its
+// first visible cell in a few leaps.
+constexpr int kSuperShift[2] = {3, 2};
+
 struct DevModel {
   const void* ctrl;
   const SpanRec* rec;
@@ -93,6 +100,8 @@ struct DevModel {
   const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
+  const uint32_t* scb[2];  // the same bounds per super cell, coarse level first
+  int32_t sc_shift[2];     // log2 of the spans per super cell and axis, per level
   double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
   double box_lo[3];
   double box_hi[3];

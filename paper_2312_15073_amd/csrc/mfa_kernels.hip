@@ -859,6 +859,95 @@ __device__ __forceinline__ void stage_tf(const float* __restrict__ tfp, float4* 
   __syncthreads();
 }
 
+// True when the transfer function has zero opacity over the whole value
+// range of a cell's bounds (FP16 pair lo | hi << 16): every sample in the
+// cell then has alpha = 0 exactly.  Two table entries bracket a value, so the
+// entries from that of lo to the one after that of hi must all be zero.
+__device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, const int* zpre) {
+  const float blo = __half2float(__ushort_as_half((unsigned short)(bh & 0xFFFFu)));
+  const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
+  return zpre[tf_entry(tf_coord(bhi, r.vmin, r.inv_range)) + 2] ==
+         zpre[tf_entry(tf_coord(blo, r.vmin, r.inv_range))];
+}
+
+// Transparent stretch in front of a ray's first visible super cell, lane by
+// lane: returns the first sample the per-sample loop has to look at (K if
+// none).  A sample in a transparent coarse super cell (else in a
+// transparent fine one) leaps to the estimated last sample inside that cell
+// (FP32 exit from the uniform-knot position of the cell faces, less one
+// step), which is then located by the exact rules.  If the landing sample
+// lies in the same cell, so does every sample between: the span index per
+// axis is monotone along the ray (each rounding step of the position and of
+// the parameter map is monotone), so the cell coordinates of a sample in
+// between lie between those of the two ends.  All of them then have
+// alpha = 0.  If the landing sample lies elsewhere, the leap is undone and
+// that cell is crossed sample by sample.  The search stops at the first
+// sample whose fine super cell is not transparent; compositing from there
+// gives the same pixel as compositing from sample 0.
+template <int P, bool MULTI>
+__device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs& r,
+                                             const SpanRec* __restrict__ R, const Ray& ray,
+                                             const int* zpre) {
+  int k = 0, from = -1, lvl = 0, cell = -1, noleap = -1, last_c0 = -1;
+  bool c0_empty = false;
+  while (k < ray.K) {
+    double x[3];
+    sample_point(ray, r.step, k, x);
+    const Loc Lc = locate<P, MULTI>(m, R, x);
+    const DevBlock* __restrict__ B = MULTI ? m.blocks + Lc.block : &m.b0;
+    int c[2];
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const int sh = m.sc_shift[l];
+      c[l] = B->sc_off[l] + (((Lc.j[0] >> sh) * B->sc[l][1] + (Lc.j[1] >> sh)) * B->sc[l][2] +
+                             (Lc.j[2] >> sh));
+    }
+    if (from >= 0) {                       // landing sample of a leap at level lvl
+      if (c[lvl] != cell) {
+        noleap = 2 * cell + lvl;           // no second leap in this cell
+        k = from + 1;
+      } else {
+        ++k;
+      }
+      from = -1;
+      continue;
+    }
+    if (c[0] != last_c0) {
+      c0_empty = transparent(m.scb[0][c[0]], r, zpre);
+      last_c0 = c[0];
+    }
+    lvl = 0;
+    if (!c0_empty) {
+      if (!transparent(m.scb[1][c[1]], r, zpre)) return k;
+      lvl = 1;
+    }
+    cell = c[lvl];
+    int kl = k;
+    if (2 * cell + lvl != noleap) {
+      const int sh = m.sc_shift[lvl];
+      float te = __builtin_inff();
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (ray.d[a] == 0.0) continue;
+        const int cc = Lc.j[a] >> sh;
+        const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
+        const float xb =
+            fmaf(__fdividef((float)jb, (float)B->nsp[a]), (float)B->ext[a], (float)B->lo[a]);
+        te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
+      }
+      kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
+                      (float)(ray.K - 1));
+    }
+    if (kl > k + 1) {
+      from = k;
+      k = kl;
+    } else {
+      ++k;
+    }
+  }
+  return ray.K;
+}
+
 // One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
 // and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
 template <int P, Storage S, bool MULTI>
@@ -883,11 +972,14 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const int64_t pid = (int64_t)j * r.w + i;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
-  int used = 0, nev = 0;
+  const int k0 = pix ? first_visible<P, MULTI>(m, r, R, ray, zpre) : 0;
+  if (r.alpha)
+    for (int q = 0; q < k0; ++q) r.alpha[pid * r.alpha_stride + q] = 0.f;
+  int used = k0, nev = 0;
   bool done = false;
   int last_mc = -1;
   bool last_empty = false;
-  for (int k = 0;; ++k) {
+  for (int k = k0;; ++k) {
     const bool act = pix && !done && k < ray.K;
     if (__ballot(act) == 0) break;                 // whole wave finished
     if (!act) continue;
@@ -899,11 +991,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     // and leaves C and A unchanged.
     // The verdict is kept while the ray stays in the same cell.
     if (Lc.mc != last_mc) {
-      const uint32_t bh = m.mcb[Lc.mc];
-      const float blo = __half2float(__ushort_as_half((unsigned short)(bh & 0xFFFFu)));
-      const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
-      last_empty = zpre[tf_entry(tf_coord(bhi, r.vmin, r.inv_range)) + 2] ==
-                   zpre[tf_entry(tf_coord(blo, r.vmin, r.inv_range))];
+      last_empty = transparent(m.mcb[Lc.mc], r, zpre);
       last_mc = Lc.mc;
     }
     const bool empty = last_empty;

@@ -28,6 +28,7 @@ struct mfa_model_s {
   mfa::DevBlock* d_blocks = nullptr;
   double* d_edges = nullptr;
   uint32_t* d_mcb = nullptr;
+  uint32_t* d_scb[2] = {nullptr, nullptr};
   mfa::BucketWin* d_bwin = nullptr;
   int64_t device_bytes = 0;
   int64_t n_buckets = 0;        // sort buckets (block, tile)
