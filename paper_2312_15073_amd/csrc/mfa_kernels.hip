@@ -112,6 +112,14 @@ struct Row<P, Storage::F16> {
   }
 };
 
+// Streaming 16-byte store: the line bypasses the caches.  Only for outputs
+// written in whole lines (scattered 16-byte writes become twice as slow).
+__device__ __forceinline__ void store_stream(float4* p, float4 v) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+}
+
 // ------------------------------------------------------------------ FP64 decisions
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {
   return fmin(fmax(v, lo), hi);
@@ -765,9 +773,9 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
       fy = fmaf(nx, YY[r], fy);
       fz = fmaf(nx, YZ[r], fz);
     }
-    if (cvalid)
-      out[(int64_t)(a0 + t) * plane + (int64_t)b * ga.res[2] + c] =
-          make_float4(f, fx * sa[t].ds, fy * dsy, fz * dsz);
+    if (cvalid)     // whole lines, written once: streaming store
+      store_stream(&out[(int64_t)(a0 + t) * plane + (int64_t)b * ga.res[2] + c],
+                   make_float4(f, fx * sa[t].ds, fy * dsy, fz * dsz));
   }
 }
 
