@@ -1015,9 +1015,10 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
       const float cg = fmaf(w, c1.y - c0.y, c0.y);
       const float cb = fmaf(w, c1.z - c0.z, c0.z);
       alpha = fmaf(w, c1.w - c0.w, c0.w);
-      // headlight Phong, two-sided
-      const float gn = sqrtf(e.y * e.y + e.z * e.z + e.w * e.w);
-      const float inv = 1.f / fmaxf(gn, r.g0);
+      // headlight Phong, two-sided; 1 / max(|g|, g0) as one hardware
+      // reciprocal square root of max(|g|^2, g0^2)
+      const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
+      const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
       const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
       float spec = 1.f, bse = diff;
       for (int ex = r.shininess; ex; ex >>= 1) {
