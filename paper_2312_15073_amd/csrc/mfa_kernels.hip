@@ -53,43 +53,53 @@ __device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t v
 }
 
 // One row of P+1 control points along axis 2 starting at element e (per
-// lane) + es (uniform), converted to FP32.
+// lane) + es (uniform): load() fetches the raw words, unpack() converts them
+// to FP32, so a caller can put every load of a sample in flight before the
+// first conversion waits for one.
 template <int P, Storage S>
 struct Row;
 
 template <int P>
 struct Row<P, Storage::F32> {
   static constexpr int kElem = 4;
+  static constexpr int kWords = P + 1;
   static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
-                                              float (&v)[P + 1]) {
-    uint32_t w[P + 1];
+                                              uint32_t (&w)[kWords]) {
     load_words<P + 1>(rs, e * 4u, es * 4u, w);
+  }
+  static __device__ __forceinline__ void unpack(const uint32_t (&w)[kWords], uint32_t,
+                                                float (&v)[P + 1]) {
 #pragma unroll
     for (int k = 0; k <= P; ++k) v[k] = __uint_as_float(w[k]);
   }
 };
 
-// 16-bit rows: load the dword-aligned window holding elements e..e+P, then
-// funnel-shift by one half-word when e is odd.
-template <int P, Storage S>
-__device__ __forceinline__ void load_halves(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
-                                            uint32_t (&h)[(P + 2) / 2]) {
-  constexpr int kOut = (P + 2) / 2;       // dwords holding P+1 halves
-  constexpr int kIn = kOut + 1;
-  uint32_t w[kIn];
-  load_words<kIn>(rs, (e & ~1u) * 2u, es * 2u, w);
-  const uint32_t sh = (e & 1u) * 16u;
+// 16-bit rows: the dword-aligned window holding elements e..e+P, funnel-
+// shifted by one half-word when e is odd (e and the uniform part of the
+// offset are even-aligned together: row strides are even).
+template <int P>
+struct Halves {
+  static constexpr int kOut = (P + 2) / 2;   // dwords holding P+1 halves
+  static constexpr int kWords = kOut + 1;
+  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
+                                              uint32_t (&w)[kWords]) {
+    load_words<kWords>(rs, (e & ~1u) * 2u, es * 2u, w);
+  }
+  static __device__ __forceinline__ void align(const uint32_t (&w)[kWords], uint32_t e,
+                                               uint32_t (&h)[kOut]) {
+    const uint32_t sh = (e & 1u) * 16u;
 #pragma unroll
-  for (int q = 0; q < kOut; ++q) h[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
-}
+    for (int q = 0; q < kOut; ++q) h[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
+  }
+};
 
 template <int P>
-struct Row<P, Storage::BF16> {
+struct Row<P, Storage::BF16> : Halves<P> {
   static constexpr int kElem = 2;
-  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
-                                              float (&v)[P + 1]) {
-    uint32_t h[(P + 2) / 2];
-    load_halves<P, Storage::BF16>(rs, e, es, h);
+  static __device__ __forceinline__ void unpack(const uint32_t (&w)[Halves<P>::kWords], uint32_t e,
+                                                float (&v)[P + 1]) {
+    uint32_t h[Halves<P>::kOut];
+    Halves<P>::align(w, e, h);
 #pragma unroll
     for (int k = 0; k <= P; ++k)
       v[k] = (k & 1) ? __uint_as_float(h[k >> 1] & 0xFFFF0000u) : __uint_as_float(h[k >> 1] << 16);
@@ -97,12 +107,12 @@ struct Row<P, Storage::BF16> {
 };
 
 template <int P>
-struct Row<P, Storage::F16> {
+struct Row<P, Storage::F16> : Halves<P> {
   static constexpr int kElem = 2;
-  static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t es,
-                                              float (&v)[P + 1]) {
-    uint32_t h[(P + 2) / 2];
-    load_halves<P, Storage::F16>(rs, e, es, h);
+  static __device__ __forceinline__ void unpack(const uint32_t (&w)[Halves<P>::kWords], uint32_t e,
+                                                float (&v)[P + 1]) {
+    uint32_t h[Halves<P>::kOut];
+    Halves<P>::align(w, e, h);
 #pragma unroll
     for (int k = 0; k <= P; ++k) {
       const unsigned short bits = (k & 1) ? (unsigned short)(h[k >> 1] >> 16)
@@ -126,15 +136,32 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
 }
 
 // Span rule s = max{ i in [p, n-1] : T[i] <= u } over the span records
-// R[0..nsp-1] of one axis (record j describes span s = p + j).  The guess
-// floor(u * nsp) is corrected by exact comparisons with the stored knots.
-__device__ __forceinline__ int locate_span(const SpanRec* __restrict__ R, int nsp, double u,
-                                           SpanRec& rec) {
-  int j = (int)(u * (double)nsp);
-  j = j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
-  rec = R[j];
+// R[0..nsp-1] of one axis (record j describes span s = p + j), in steps so
+// that the record loads of the three axes of a point can be in flight
+// together: guess_span() takes floor(u * nsp), span_ok() checks the guess by
+// exact comparisons with the stored knots, and fix_span() walks to the exact
+// span where the check fails (u within rounding of a knot, or non-uniform
+// knots).
+__device__ __forceinline__ int guess_span(int nsp, double u) {
+  const int j = (int)(u * (double)nsp);
+  return j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
+}
+
+__device__ __forceinline__ bool span_ok(int nsp, double u, int j, const SpanRec& rec) {
+  return !(j < nsp - 1 && rec.t_next <= u) & !(j > 0 && rec.t > u);
+}
+
+__device__ __forceinline__ void fix_span(const SpanRec* __restrict__ R, int nsp, double u, int& j,
+                                         SpanRec& rec) {
   while (j < nsp - 1 && rec.t_next <= u) { ++j; rec = R[j]; }
   while (j > 0 && rec.t > u) { --j; rec = R[j]; }
+}
+
+__device__ __forceinline__ int locate_span(const SpanRec* __restrict__ R, int nsp, double u,
+                                           SpanRec& rec) {
+  int j = guess_span(nsp, u);
+  rec = R[j];
+  if (!span_ok(nsp, u, j, rec)) fix_span(R, nsp, u, j, rec);
   return j;
 }
 
@@ -237,24 +264,33 @@ __device__ __forceinline__ void contract_rows(RowFn row, const float (&Nx)[P + 1
   }
 }
 
-// Rows from the control-point pool in global memory.
-// e0: element index of P[i0][j0][k0] (per lane); rows at + i*s0 + j*s1.
-// UNIFORM_STRIDES: s0, s1 are wave-uniform and go into the scalar offset.
+// The (P+1)^2 control rows of a located point from the control-point pool
+// in global memory, kept as raw words so that all loads of a sample are in
+// flight before the first use.  e0: element index of P[i0][j0][k0] (per
+// lane); rows at + i*s0 + j*s1 (even for 16-bit storage, so every row has
+// the parity of e0).  UNIFORM_STRIDES: s0, s1 are wave-uniform and go into
+// the scalar offset.
 template <int P, Storage S, bool UNIFORM_STRIDES>
-__device__ __forceinline__ void contract(__amdgpu_buffer_rsrc_t rs, uint32_t e0, uint32_t s0,
-                                         uint32_t s1, const float (&Nx)[P + 1],
-                                         const float (&Dx)[P + 1], const float (&Ny)[P + 1],
-                                         const float (&Dy)[P + 1], const float (&Nz)[P + 1],
-                                         const float (&Dz)[P + 1], float& f, float& fx, float& fy,
-                                         float& fz) {
-  auto row = [&](int i, int j, float (&v)[P + 1]) {
-    if constexpr (UNIFORM_STRIDES)
-      Row<P, S>::load(rs, e0, (uint32_t)i * s0 + (uint32_t)j * s1, v);
-    else
-      Row<P, S>::load(rs, e0 + (uint32_t)i * s0 + (uint32_t)j * s1, 0u, v);
-  };
-  contract_rows<P>(row, Nx, Dx, Ny, Dy, Nz, Dz, f, fx, fy, fz);
-}
+struct Rows {
+  uint32_t w[P + 1][P + 1][Row<P, S>::kWords];
+  uint32_t e0;
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t e, uint32_t s0,
+                                       uint32_t s1) {
+    e0 = e;
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+#pragma unroll
+      for (int j = 0; j <= P; ++j) {
+        if constexpr (UNIFORM_STRIDES)
+          Row<P, S>::load(rs, e, (uint32_t)i * s0 + (uint32_t)j * s1, w[i][j]);
+        else
+          Row<P, S>::load(rs, e + (uint32_t)i * s0 + (uint32_t)j * s1, 0u, w[i][j]);
+      }
+  }
+  __device__ __forceinline__ void get(int i, int j, float (&v)[P + 1]) const {
+    Row<P, S>::unpack(w[i][j], e0, v);
+  }
+};
 
 // ------------------------------------------------------------------ point location
 // Owning block along one axis: b = max{ i in [0, G-1] : E[i] <= xc }.  The
@@ -278,13 +314,29 @@ struct Loc {
   int mc;
 };
 
-// R: span records (global pool or its LDS copy).
-template <int P, bool MULTI>
-__device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
-                                      const double (&x)[3]) {
-  Loc L;
-  const DevBlock* __restrict__ B = &m.b0;
+// A point after the exact FP64 map: owning block, parameters, and per axis
+// the guessed span with its record (loads issued, not yet waited for).
+struct Probe {
+  const DevBlock* B;
   double u[3];
+  SpanRec rec[3];
+  int j[3];
+  int block;
+};
+
+// Macro cell of the spans j of block B.
+__device__ __forceinline__ int macro_cell(const DevModel& m, const DevBlock* __restrict__ B,
+                                          const int (&j)[3]) {
+  const int sh = m.mc_shift;
+  return B->mc_off + (((j[0] >> sh) * B->mc[1] + (j[1] >> sh)) * B->mc[2] + (j[2] >> sh));
+}
+
+// R: span records (global pool or its LDS copy).
+template <bool MULTI>
+__device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restrict__ R,
+                                       const double (&x)[3]) {
+  Probe q;
+  q.B = &m.b0;
   if constexpr (MULTI) {
     int b[3];
     double xc[3];
@@ -294,34 +346,61 @@ __device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restri
       xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
       b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
     }
-    L.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
-    B = m.blocks + L.block;
+    q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
+    q.B = m.blocks + q.block;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
+    for (int a = 0; a < 3; ++a) q.u[a] = param_of(xc[a], q.B->lo[a], q.B->inv_ext[a]);
   } else {
-    L.block = 0;
+    q.block = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+      q.u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], q.B->inv_ext[a]);
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    SpanRec rec;
-    L.j[a] = locate_span(R + B->rec_off[a], B->nsp[a], u[a], rec);
-    L.tau[a] = local_tau(rec, u[a]);
-    L.ds[a] = rec.dscale;
-    L.mat[a] = rec.mat;
+    q.j[a] = guess_span(q.B->nsp[a], q.u[a]);
+    q.rec[a] = R[q.B->rec_off[a] + q.j[a]];
+  }
+  return q;
+}
+
+// Exact spans (a walk only where a guess fails its check), local
+// coordinates, first control row and macro cell of a probed point.
+__device__ __forceinline__ Loc finish(const DevModel& m, const SpanRec* __restrict__ R, Probe& q) {
+  const DevBlock* __restrict__ B = q.B;
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok &= span_ok(B->nsp[a], q.u[a], q.j[a], q.rec[a]);
+  if (!ok) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fix_span(R + B->rec_off[a], B->nsp[a], q.u[a], q.j[a], q.rec[a]);
+  }
+  Loc L;
+  L.block = q.block;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    L.j[a] = q.j[a];
+    L.tau[a] = local_tau(q.rec[a], q.u[a]);
+    L.ds[a] = q.rec[a].dscale;
+    L.mat[a] = q.rec[a].mat;
   }
   const uint32_t n1 = (uint32_t)B->n[1], s1 = (uint32_t)B->rs1;
   L.s1 = s1;
   L.s0 = n1 * s1;
   L.e0 = (uint32_t)B->ctrl_off + ((uint32_t)L.j[0] * n1 + (uint32_t)L.j[1]) * s1 + (uint32_t)L.j[2];
-  const int sh = m.mc_shift;
-  L.mc = B->mc_off + (((L.j[0] >> sh) * B->mc[1] + (L.j[1] >> sh)) * B->mc[2] + (L.j[2] >> sh));
+  L.mc = macro_cell(m, B, L.j);
   return L;
 }
 
-// Value and world gradient at a located point.
+template <int P, bool MULTI>
+__device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
+                                      const double (&x)[3]) {
+  Probe q = probe<MULTI>(m, R, x);
+  return finish(m, R, q);
+}
+
+// Value and world gradient at a located point: the control-row loads are
+// issued first, so the basis is computed while they are in flight.
 template <int P, Storage S, bool UNIFORM_STRIDES>
 __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t rs,
                                            const float* __restrict__ mats, int stride, int imat) {
@@ -329,8 +408,15 @@ __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t 
 #pragma unroll
   for (int a = 0; a < 3; ++a) basis<P>(mats, stride, L.mat[a], imat, L.tau[a], N[a], D[a]);
   float f, fx, fy, fz;
-  contract<P, S, UNIFORM_STRIDES>(rs, L.e0, L.s0, L.s1, N[0], D[0], N[1], D[1], N[2], D[2], f, fx,
-                                  fy, fz);
+  auto row = [&](int i, int j, float (&v)[P + 1]) {
+    uint32_t w[Row<P, S>::kWords];
+    if constexpr (UNIFORM_STRIDES)
+      Row<P, S>::load(rs, L.e0, (uint32_t)i * L.s0 + (uint32_t)j * L.s1, w);
+    else
+      Row<P, S>::load(rs, L.e0 + (uint32_t)i * L.s0 + (uint32_t)j * L.s1, 0u, w);
+    Row<P, S>::unpack(w, L.e0, v);
+  };
+  contract_rows<P>(row, N[0], D[0], N[1], D[1], N[2], D[2], f, fx, fy, fz);
   return make_float4(f, fx * L.ds[0], fy * L.ds[1], fz * L.ds[2]);
 }
 
@@ -733,8 +819,10 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
 #pragma unroll
     for (int jj = 0; jj <= P; ++jj) {
       float v[P + 1];
+      uint32_t w[Row<P, S>::kWords];
       const uint32_t es = ((uint32_t)i * n1 + (uint32_t)(jy + jj)) * s1;
-      Row<P, S>::load(rs, ez, es, v);
+      Row<P, S>::load(rs, ez, es, w);
+      Row<P, S>::unpack(w, ez, v);
       float z = 0.f, zd = 0.f;
 #pragma unroll
       for (int k = 0; k <= P; ++k) {
@@ -993,13 +1081,20 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, k, x);
-    const Loc Lc = locate<P, MULTI>(m, R, x);
+    Probe q = probe<MULTI>(m, R, x);
     // Skip the evaluation where the transfer function is zero over the
     // value bounds of the macro cell: such a sample has alpha = 0 exactly
-    // and leaves C and A unchanged.
-    // The verdict is kept while the ray stays in the same cell.
+    // and leaves C and A unchanged.  The verdict is kept while the ray
+    // stays in the same cell.  The bounds of the cell of the guessed spans
+    // are fetched while the guesses are checked (reloaded in the rare case
+    // that the exact spans lie in another cell).
+    const int mcg = macro_cell(m, q.B, q.j);
+    uint32_t bh = 0;
+    if (mcg != last_mc) bh = m.mcb[mcg];
+    const Loc Lc = finish(m, R, q);
     if (Lc.mc != last_mc) {
-      last_empty = transparent(m.mcb[Lc.mc], r, zpre);
+      if (Lc.mc != mcg) bh = m.mcb[Lc.mc];
+      last_empty = transparent(bh, r, zpre);
       last_mc = Lc.mc;
     }
     const bool empty = last_empty;
