@@ -50,8 +50,8 @@ FRAME = 1024
 TRAFFIC = {
     # 1024^2 frame of the 128^3 model; copy reference: 512 MiB read + 512 MiB
     # written, FETCH_SIZE 262161 KiB (scale 2.0), WRITE_SIZE 524288 KiB (1.0)
-    "render": {"kernels_sha256": "70b2a2b09d3078914953354344de4fa66584b478d8e9b33811b10123266debe7",
-               "fetch_kib": 31645.0, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0},
+    "render": {"kernels_sha256": "2e3c7333d9470a59755a4d1018e1771a862311df9b30cfd36353328800f308d6",
+               "fetch_kib": 31648.0, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0},
 }
 
 

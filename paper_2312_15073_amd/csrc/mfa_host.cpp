@@ -688,8 +688,8 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
   mfa_status st = check_device(m);
   if (st != MFA_OK) return st;
   if (flags & MFA_DECODE_SORTED) {
-    // scratch: one 16-byte sorted record per point; counts, starts and
-    // cursors per bucket; the decode items
+    // scratch: one 16-byte sorted record per point (two with the two-level
+    // split); counts, starts and cursors per bucket; the decode items
     if (m->n_buckets > kMaxBuckets)
       return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -699,7 +699,9 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     const size_t o_cur = o_start + al(4 * nbk);
     const size_t n_items = (size_t)((n + kTilePoints - 1) / kTilePoints) + nbk;
     const size_t o_items = o_cur + al(4 * nbk), o_nitems = o_items + al(8 * n_items);
-    const size_t need = o_nitems + al(4);
+    const bool two = nbk > (size_t)kCoarseBuckets;
+    const size_t o_ccur = o_nitems + al(4), o_tmp = o_ccur + al(4 * kCoarseBuckets * kCursorStride);
+    const size_t need = two ? o_tmp + al(16 * (size_t)n) : o_ccur;
     if (need > m->ws_bytes) {
       if (m->d_ws) {
         hipError_t fe = hipFree(m->d_ws);   // waits for work still using it
@@ -724,6 +726,8 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     sa.items = (int2*)(w + o_items);
     sa.n_items = (int32_t*)(w + o_nitems);
     sa.nb = (int32_t)nbk;
+    sa.tmp = two ? (float4*)(w + o_tmp) : nullptr;
+    sa.ccursor = two ? (uint32_t*)(w + o_ccur) : nullptr;
     hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), m->nblocks > 1, sa, out, dbg,
                                         (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sorted decode launch");

@@ -59,6 +59,15 @@ constexpr int kMaxBuckets = 4096;
 // point can differ from the estimate that chose its bucket) form a window
 // that is staged in LDS when it holds at most kWinMax values.
 constexpr int kTilePoints = 2048;
+
+// Above kCoarseBuckets buckets the points are split in two passes, first by
+// bucket >> kFineShift, so that every pass writes long runs of records.
+constexpr int kFineShift = 6;
+constexpr int kCoarseBuckets = 64;
+// The coarse cursors sit one per 128-byte line: every chunk updates all of
+// them, and 64 counters in two lines would put every atomic of the pass on
+// the same two L2 channels.
+constexpr int kCursorStride = 32;
 constexpr int kWinMax = 8192;
 
 struct BucketWin {
@@ -171,6 +180,10 @@ struct SortArgs {
   int2* items;           // [<= n / kTilePoints + nb] (bucket, part) per decode item
   int32_t* n_items;      // number of items
   int32_t nb;            // buckets (<= kMaxBuckets)
+  // two-level split (nb > kCoarseBuckets): records grouped by coarse bucket
+  // (bucket >> kFineShift) first, then by bucket
+  float4* tmp;           // [n] records in coarse-bucket order, or null (one level)
+  uint32_t* ccursor;     // [kCoarseBuckets * kCursorStride] positions handed out per coarse bucket
 };
 
 struct GridArgs {

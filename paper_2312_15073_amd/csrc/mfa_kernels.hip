@@ -293,14 +293,23 @@ struct Rows {
 };
 
 // ------------------------------------------------------------------ point location
-// Owning block along one axis: b = max{ i in [0, G-1] : E[i] <= xc }.  The
-// guess from the mean block width is corrected by exact edge comparisons.
-__device__ __forceinline__ int owner(const double* __restrict__ E, int G, double scale, double xc) {
-  int b = (int)((xc - E[0]) * scale);
-  b = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
+// Owning block along one axis: b = max{ i in [0, G-1] : E[i] <= xc }, in
+// the same steps as the span rule (guess from the mean block width, one
+// exact check against the two bracketing edges, a walk only where it fails),
+// so the edge loads of the three axes are in flight together.
+__device__ __forceinline__ int guess_owner(const double* __restrict__ E, int G, double scale,
+                                           double xc) {
+  const int b = (int)((xc - E[0]) * scale);
+  return b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
+}
+
+__device__ __forceinline__ bool owner_ok(int G, double xc, int b, double e0, double e1) {
+  return !(b < G - 1 && e1 <= xc) & !(b > 0 && e0 > xc);
+}
+
+__device__ __forceinline__ void fix_owner(const double* __restrict__ E, int G, double xc, int& b) {
   while (b < G - 1 && E[b + 1] <= xc) ++b;
   while (b > 0 && E[b] > xc) --b;
-  return b;
 }
 
 // Everything the evaluation needs about one world point after the exact
@@ -339,12 +348,21 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
   q.B = &m.b0;
   if constexpr (MULTI) {
     int b[3];
-    double xc[3];
+    double xc[3], e0[3], e1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double* E = m.edges + m.edge_off[a];
       xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
-      b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+      b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+      e0[a] = E[b[a]];
+      e1[a] = E[b[a] + 1];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
+    if (!ok) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) fix_owner(m.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
     }
     q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
     q.B = m.blocks + q.block;
@@ -448,10 +466,20 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 // evaluated by the same exact rules, so the results do not depend on it.
 // Pass 1 counts the buckets of each 8192-point chunk in LDS and adds the
 // counts to the global histogram; a one-workgroup scan gives each bucket's
-// start; pass 2 recounts each chunk, claims a run per bucket with one
-// global atomic, and writes its points into those runs.
+// start; a scatter pass recounts each chunk, claims a run per key with one
+// global atomic, and writes its records (x, y, z, input index) into those
+// runs.  With thousands of buckets a chunk has only a few points per
+// bucket, and runs that short reach HBM as partial-line writes; so above
+// kCoarseBuckets buckets the scatter is done twice: by coarse bucket
+// (bucket >> kFineShift, at most 64 keys: runs of ~128 records), then the
+// coarse runs by bucket (a chunk of them spans one or two coarse buckets:
+// again runs of ~128 records).
 constexpr int kSortPer = 32;                   // points per thread
 constexpr int kSortChunk = kBlock * kSortPer;  // points per workgroup
+// points per thread in the passes of the two-level split: chunks of 2048
+// points still write runs of >= 32 records per key, and the smaller
+// chunks keep more workgroups in flight
+constexpr int kSortPer2 = 8;
 
 template <bool MULTI>
 __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double (&x)[3]) {
@@ -459,12 +487,21 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
   double u[3];
   if constexpr (MULTI) {
     int b[3];
-    double xc[3];
+    double xc[3], e0[3], e1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double* E = m.edges + m.edge_off[a];
       xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
-      b[a] = owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+      b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+      e0[a] = E[b[a]];
+      e1[a] = E[b[a] + 1];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
+    if (!ok) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) fix_owner(m.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
     }
     B = m.blocks + ((b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]);
 #pragma unroll
@@ -560,38 +597,63 @@ __global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
     run += v[q];
   }
   if (threadIdx.x == 0) *sa.n_items = (int32_t)tot;
+  if (sa.tmp && threadIdx.x < kCoarseBuckets) sa.ccursor[threadIdx.x * kCursorStride] = 0u;
 }
 
-template <bool MULTI>
+// Point q of a chunk (q = 0..kSortPer-1) of the pass input: the points in
+// input order, or (FROM_TMP) the records of the coarse pass.
+template <bool FROM_TMP>
+__device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
+  if constexpr (FROM_TMP)
+    return sa.tmp[i];
+  else
+    return make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i], __uint_as_float((uint32_t)i));
+}
+
+// Scatter pass of the multisplit over one chunk: ranks within the chunk
+// from LDS counters, one run claimed per key and chunk with one global
+// atomic, records written to run start + rank.  COARSE: key = bucket >>
+// kFineShift (the coarse pass, runs from sa.ccursor, records to sa.tmp);
+// otherwise key = bucket (runs from sa.cursor, records to sa.rec).
+template <bool MULTI, bool COARSE, bool FROM_TMP, int PER>
 __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
-  __shared__ uint32_t h[kMaxBuckets];
-  __shared__ uint32_t base[kMaxBuckets];
-  for (int b = threadIdx.x; b < sa.nb; b += kBlock) h[b] = 0u;
+  constexpr int kKeys = COARSE ? kCoarseBuckets : kMaxBuckets;
+  __shared__ uint32_t h[kKeys];
+  __shared__ uint32_t base[kKeys];
+  const int nk = COARSE ? ((sa.nb + (1 << kFineShift) - 1) >> kFineShift) : sa.nb;
+  for (int b = threadIdx.x; b < nk; b += kBlock) h[b] = 0u;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
-  uint32_t key[kSortPer], rank[kSortPer];
+  const int64_t c0 = (int64_t)blockIdx.x * (kBlock * PER);
+  uint32_t key[PER], rank[PER];
 #pragma unroll
-  for (int q = 0; q < kSortPer; ++q) {
+  for (int q = 0; q < PER; ++q) {
     const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
     key[q] = 0xFFFFFFFFu;
     if (i < sa.n) {
-      const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
-      key[q] = sort_bucket<MULTI>(m, x);
+      const float4 r = sort_input<FROM_TMP>(sa, i);
+      const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+      const uint32_t b = sort_bucket<MULTI>(m, x);
+      key[q] = COARSE ? b >> kFineShift : b;
       rank[q] = atomicAdd(h + key[q], 1u);
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < sa.nb; b += kBlock)
-    if (h[b]) base[b] = sa.start[b] + atomicAdd(sa.cursor + b, h[b]);
+  for (int b = threadIdx.x; b < nk; b += kBlock)
+    if (h[b]) {
+      if constexpr (COARSE)
+        base[b] = sa.start[b << kFineShift] + atomicAdd(sa.ccursor + b * kCursorStride, h[b]);
+      else
+        base[b] = sa.start[b] + atomicAdd(sa.cursor + b, h[b]);
+    }
   __syncthreads();
+  float4* dst = COARSE ? sa.tmp : sa.rec;
 #pragma unroll
-  for (int q = 0; q < kSortPer; ++q) {
+  for (int q = 0; q < PER; ++q) {
     const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
     if (key[q] == 0xFFFFFFFFu) continue;
     const uint32_t pos = base[key[q]] + rank[q];
     if ((int64_t)pos >= sa.n) continue;        // cannot happen when the counts are consistent
-    sa.rec[pos] = make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i],
-                              __uint_as_float((uint32_t)i));
+    dst[pos] = sort_input<FROM_TMP>(sa, i);
   }
 }
 
@@ -1254,10 +1316,26 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
   else
     hipLaunchKernelGGL(sort_hist_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
   hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kBlock), 0, st, sa);
-  if (multi)
-    hipLaunchKernelGGL(sort_scatter_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
-  else
-    hipLaunchKernelGGL(sort_scatter_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+  if (sa.tmp) {                        // two levels: coarse runs, then buckets
+    const unsigned g2 = (unsigned)((sa.n + kBlock * kSortPer2 - 1) / (kBlock * kSortPer2));
+    if (multi) {
+      hipLaunchKernelGGL((sort_scatter_k<true, true, false, kSortPer2>), dim3(g2), dim3(kBlock), 0, st,
+                         m, sa);
+      hipLaunchKernelGGL((sort_scatter_k<true, false, true, kSortPer2>), dim3(g2), dim3(kBlock), 0, st,
+                         m, sa);
+    } else {
+      hipLaunchKernelGGL((sort_scatter_k<false, true, false, kSortPer2>), dim3(g2), dim3(kBlock), 0,
+                         st, m, sa);
+      hipLaunchKernelGGL((sort_scatter_k<false, false, true, kSortPer2>), dim3(g2), dim3(kBlock), 0,
+                         st, m, sa);
+    }
+  } else if (multi) {
+    hipLaunchKernelGGL((sort_scatter_k<true, false, false, kSortPer>), dim3(gc), dim3(kBlock), 0, st,
+                       m, sa);
+  } else {
+    hipLaunchKernelGGL((sort_scatter_k<false, false, false, kSortPer>), dim3(gc), dim3(kBlock), 0, st,
+                       m, sa);
+  }
   if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
     const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
     if (multi)

@@ -457,6 +457,19 @@ def test_sorted_decode_single_block(mfa, dev, c1, storage):
         assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(c1.blocks[0].ctrl)))
 
 
+def test_sorted_decode_few_buckets(mfa, dev):
+    # 2 x 3 x 4 spans: few enough buckets for the one-level split (the models
+    # above take the two-level one).
+    rng = np.random.default_rng(31)
+    P = rng.standard_normal((5, 6, 7))
+    model = synth.single_block_model(P, [3] * 3)
+    pts = synth.random_points(30001, seed=31, lo=(-0.05, -0.05, -0.05), hi=(1.05, 1.05, 1.05))
+    announce("sorted decode, 24 buckets")
+    out = _sorted_matches_unsorted(mfa, dev, model, pts)
+    ref = oracle_points(model, pts.T)
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)))
+
+
 def test_sorted_decode_graded_knots(mfa, dev):
     # Knots crowded towards 0 along every axis: the bucket estimate
     # floor(u * nsp) then lies far from the exact span for most points, whose
