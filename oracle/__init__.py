@@ -13,6 +13,8 @@ render   ray generation, slab test, sample schedule, transfer function,
          Phong shading, front-to-back "over" and early ray termination.
 quant    storage rounding FP64 -> FP32 -> BF16 / FP16 (bit level).
 metrics  MSE, RMSE, 8-bit PSNR, compression ratio.
+encode   fixed-knot least-squares encoding of samples on a tensor grid
+         (collocation matrices, per-axis pseudo-inverses, mode products).
 
 Every function cites the passage of the paper it follows.  The paper gives
 the model as a tensor product of B-spline functions with control points and
@@ -28,4 +30,4 @@ rays whose accumulated opacity lies within 1e-5 of the threshold, which is
 "parity unpinned" (an FP64 reference cannot decide it for an FP32 kernel; the
 FP32 replay in ``render.ert_replay_f32`` covers it instead).
 """
-from . import bspline, render, quant, metrics  # noqa: F401
+from . import bspline, render, quant, metrics, encode  # noqa: F401

@@ -1,0 +1,143 @@
+"""Pins of the oracle's fixed-knot encoding (CPU only).
+
+The oracle computes the least-squares control points by three mode products
+with per-axis pseudo-inverses.  Each test checks it against something other
+than that formula: the dense Kronecker least-squares problem solved directly
+on tiny grids (brute force), exact reproduction of a spline of the same
+space, reproduction of polynomials of degree <= p, and the normal equations
+(the residual is orthogonal to every basis function of the model).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import bspline as ob
+from oracle import encode as oe
+
+
+def nonuniform_knots(n, p, rng):
+    inner = np.sort(rng.uniform(0.05, 0.95, size=n - p - 1))
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def spaced_knots(n, p, rng):
+    """Non-uniform clamped knots whose spans are 0.4 to 1.6 times the mean
+    span, so that a uniform grid of 3n samples puts samples in every span
+    (the collocation matrices then have full column rank)."""
+    m = n - p
+    inner = (np.arange(1, m) + rng.uniform(-0.3, 0.3, size=m - 1)) / m
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def grid_params(N, rng, kind):
+    if kind == "uniform":
+        return np.arange(N, dtype=np.float64) / (N - 1)
+    u = np.sort(rng.random(N))
+    u[0], u[-1] = 0.0, 1.0
+    return u
+
+
+def kron_design(axis_u, degree, knots, n_ctrl):
+    """Dense design matrix of the tensor grid, rows in C order of the samples
+    and columns in C order of the control points, built point by point from
+    the oracle's scalar basis (not from the collocation routine)."""
+    rows = []
+    for u0 in axis_u[0]:
+        for u1 in axis_u[1]:
+            for u2 in axis_u[2]:
+                vals = []
+                for a, u in enumerate((u0, u1, u2)):
+                    T, p, n = knots[a], degree[a], n_ctrl[a]
+                    s = ob.find_span(T, p, n, np.array([u]))
+                    N, _ = ob.basis_and_derivs(T, p, s, np.array([u]))
+                    v = np.zeros(n)
+                    v[s[0] - p:s[0] + 1] = N[0]
+                    vals.append(v)
+                rows.append(np.einsum("i,j,k->ijk", *vals).ravel())
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "random"])
+@pytest.mark.parametrize("degree", [(3, 3, 3), (2, 3, 1), (4, 2, 3)])
+def test_fit_equals_dense_kronecker_least_squares(kind, degree):
+    rng = np.random.default_rng(sum(degree) + (kind == "random"))
+    res = (9, 7, 8)
+    n_ctrl = [degree[a] + 2 + a for a in range(3)]
+    knots = [nonuniform_knots(n_ctrl[a], degree[a], rng) if kind == "random"
+             else synth.clamped_uniform_knots(n_ctrl[a], degree[a]) for a in range(3)]
+    axis_u = [grid_params(res[a], rng, kind) for a in range(3)]
+    F = rng.standard_normal(res)
+    P = oe.fit_grid(F, axis_u, degree, knots, n_ctrl)
+    A = kron_design(axis_u, degree, knots, n_ctrl)
+    want, *_ = np.linalg.lstsq(A, F.ravel(), rcond=None)
+    np.testing.assert_allclose(P.ravel(), want, rtol=0, atol=1e-10 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_fit_reproduces_a_spline_of_the_same_space(p):
+    rng = np.random.default_rng(40 + p)
+    n = (p + 5, p + 3, p + 7)
+    knots = [spaced_knots(n[a], p, rng) for a in range(3)]
+    C = rng.standard_normal(n)
+    model = synth.single_block_model(C, [p] * 3, knots)
+    axis_u = [grid_params(3 * n[a], rng, "uniform") for a in range(3)]
+    F = ob.decode_grid(model, axis_u)[..., 0]          # samples of the spline itself
+    P = oe.fit_grid(F, axis_u, [p] * 3, knots, n)
+    np.testing.assert_allclose(P, C, rtol=0, atol=1e-9 * np.abs(C).max())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_fit_reproduces_polynomials_up_to_degree_p(p):
+    rng = np.random.default_rng(50 + p)
+    n = (p + 4, p + 6, p + 5)
+    knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
+    axis_u = [grid_params(2 * n[a] + 1, rng, "uniform") for a in range(3)]
+    coef = rng.standard_normal((p + 1, p + 1, p + 1))
+
+    def poly(x, y, z):
+        out = 0.0
+        for i in range(p + 1):
+            for j in range(p + 1 - i):
+                for k in range(p + 1 - i - j):
+                    out = out + coef[i, j, k] * x ** i * y ** j * z ** k
+        return out
+
+    g = np.meshgrid(*axis_u, indexing="ij")
+    P = oe.fit_grid(poly(*g), axis_u, [p] * 3, knots, n)
+    model = synth.single_block_model(P, [p] * 3, knots)
+    x = rng.random((500, 3))
+    f = ob.evaluate(model, x)["f"]
+    np.testing.assert_allclose(f, poly(x[:, 0], x[:, 1], x[:, 2]), rtol=0, atol=1e-10)
+
+
+def test_residual_satisfies_the_normal_equations():
+    rng = np.random.default_rng(60)
+    p, n, res = 3, (11, 9, 13), (40, 31, 45)
+    knots = [nonuniform_knots(n[a], p, rng) for a in range(3)]
+    axis_u = [grid_params(res[a], rng, "random") for a in range(3)]
+    F = rng.standard_normal(res)
+    P = oe.fit_grid(F, axis_u, [p] * 3, knots, n)
+    model = synth.single_block_model(P, [p] * 3, knots)
+    R = ob.decode_grid(model, axis_u)[..., 0] - F
+    G = R
+    for a in range(3):                                  # B^T applied along every axis
+        T = knots[a]
+        s = ob.find_span(T, p, n[a], axis_u[a])
+        N, _ = ob.basis_and_derivs(T, p, s, axis_u[a])
+        Bt = np.zeros((n[a], res[a]))
+        for r in range(p + 1):
+            Bt[s - p + r, np.arange(res[a])] = N[:, r]
+        G = np.moveaxis(np.tensordot(Bt, G, axes=([1], [a])), 0, a)
+    assert np.abs(G).max() < 1e-10 * np.abs(F).max() * np.prod(res)
+
+
+def test_collocation_rows_partition_unity_and_band():
+    rng = np.random.default_rng(70)
+    for p in (1, 3, 5):
+        n = p + 9
+        T = nonuniform_knots(n, p, rng)
+        u = grid_params(50, rng, "random")
+        B = oe.collocation(T, p, n, u)
+        np.testing.assert_allclose(B.sum(axis=1), 1.0, rtol=0, atol=1e-14)
+        assert np.all(B >= 0.0)
+        assert np.all((B != 0.0).sum(axis=1) <= p + 1)
