@@ -323,6 +323,39 @@ mfa_status mfa_server_destroy(mfa_server server);
 
 /* ------------------------------------------------------------------ host utilities */
 
+/* ------------------------------------------------------------------ encoding */
+
+/* Fixed-knot encoding of one block from samples on a tensor grid (Sec. IV-A2
+ * "MFA Encoding"; the parameterisation and initial knot distribution of
+ * Fig. 1, without the knot insertion that follows it there).  The control
+ * points minimise the sum of squared differences between the spline and the
+ * samples,
+ *     P = argmin sum_i ( f(u0[i0], u1[i1], u2[i2]; P) - F[i0][i1][i2] )^2,
+ * which for a tensor grid is P = F x_0 B0+ x_1 B1+ x_2 B2+ with B_a the
+ * collocation matrix N_{j,p}(u_a[i]) of axis a and B+ = (B^T B)^-1 B^T.
+ * The host builds B_a+ (FP64; banded Cholesky of B_a^T B_a); the device
+ * computes the three mode products in FP64 on the matrix cores.
+ *  res      : samples per axis, n_ctrl[a] <= res[a] <= 65536.
+ *  axis_u   : host FP64 parameters of the samples, res[a] values per axis,
+ *             each in [0, 1], any order.
+ *  values   : device FP32 [res0][res1][res2] samples, axis 2 fastest.
+ *  degree, n_ctrl, knots : as in mfa_block_desc (knots[a] NULL = clamped
+ *             uniform); the result can be passed to mfa_model_create as the
+ *             block's control points after a copy to the host.
+ *  ctrl     : device FP64 [n0][n1][n2] out, axis 2 fastest.
+ *  work     : device scratch of at least mfa_encode_workspace() bytes
+ *             (caller-owned; not to be shared by calls in flight together).
+ * Errors (before any device work): MFA_E_ARG for bad sizes, parameters or
+ * knots, and when some B_a^T B_a is not positive definite (a basis function
+ * with too few samples in its support: raise res or lower n_ctrl).
+ * The call waits for the upload of the B_a+ tables on the stream (so for
+ * the work queued before it); the mode products are left in flight.      */
+mfa_status mfa_encode_workspace(const int32_t res[3], const int32_t n_ctrl[3], int64_t* bytes);
+mfa_status mfa_encode_grid(const int32_t res[3], const double* const axis_u[3], const float* values,
+                           const int32_t degree[3], const int32_t n_ctrl[3],
+                           const double* const knots[3], double* ctrl, void* work,
+                           int64_t work_bytes, void* stream);
+
 /* Host-only helpers (no device work): the storage rounding and the default
  * knot vector the library uses, exported so they can be checked on a CPU.
  *  mfa_quantize : n FP64 values -> stored bits of dtype (MFA_F32: uint32

@@ -184,6 +184,52 @@ def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False, s
     return (out, sp) if spans else out
 
 
+def encode_workspace_bytes(res: Sequence[int], n_ctrl: Sequence[int]) -> int:
+    """Device scratch bytes that encode_grid needs for these sizes."""
+    out = C.c_int64()
+    L.check(L.lib().mfa_encode_workspace((C.c_int32 * 3)(*[int(v) for v in res]),
+                                         (C.c_int32 * 3)(*[int(v) for v in n_ctrl]), C.byref(out)))
+    return int(out.value)
+
+
+def encode_grid(values, axis_u: Sequence, degree: Sequence[int], n_ctrl: Sequence[int],
+                knots: Optional[Sequence] = None, out=None, work=None, stream=None):
+    """Fixed-knot least-squares control points (FP64 CUDA tensor (n0, n1,
+    n2)) of the CUDA float32 samples values (r0, r1, r2) at the tensor grid
+    of host float64 parameter tables axis_u; knots[a] None = clamped
+    uniform.  work: optional CUDA uint8 scratch of encode_workspace_bytes."""
+    torch = _torch()
+    if len(axis_u) != 3 or len(degree) != 3 or len(n_ctrl) != 3:
+        raise ValueError("need three axes")
+    res = [int(v) for v in values.shape] if values.dim() == 3 else None
+    if res is None:
+        raise ValueError("values must be (r0, r1, r2)")
+    tabs = [np.ascontiguousarray(np.asarray(u, dtype=np.float64)) for u in axis_u]
+    for a in range(3):
+        if tabs[a].shape != (res[a],):
+            raise ValueError(f"axis_u[{a}] must hold {res[a]} parameters")
+    pv = _dev_ptr(values, torch.float32, tuple(res), "values")
+    nb = encode_workspace_bytes(res, n_ctrl)
+    if work is None:
+        work = torch.empty((nb,), dtype=torch.uint8, device=values.device)
+    pw = _dev_ptr(work, torch.uint8, name="work")
+    shape = tuple(int(v) for v in n_ctrl)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=values.device)
+    po = _dev_ptr(out, torch.float64, shape, "out")
+    kn = None
+    if knots is not None:
+        kts = [None if k is None else np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+               for k in knots]
+        kn = (C.c_void_p * 3)(*[None if k is None else k.ctypes.data for k in kts])
+    L.check(L.lib().mfa_encode_grid((C.c_int32 * 3)(*res),
+                                    (C.c_void_p * 3)(*[t.ctypes.data for t in tabs]), pv,
+                                    (C.c_int32 * 3)(*[int(v) for v in degree]),
+                                    (C.c_int32 * 3)(*[int(v) for v in n_ctrl]), kn, po, pw,
+                                    int(work.numel()), _stream_ptr(stream)))
+    return out
+
+
 def make_camera(cam: dict) -> L.Camera:
     c = L.Camera()
     c.kind = int(cam["kind"])

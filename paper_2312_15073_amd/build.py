@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmfa.so")
-SOURCES = ["mfa_host.cpp", "mfa_server.cpp", "mfa_kernels.hip"]
+SOURCES = ["mfa_host.cpp", "mfa_server.cpp", "mfa_kernels.hip", "mfa_encode.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for all device code.

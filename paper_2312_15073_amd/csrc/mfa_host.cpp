@@ -205,7 +205,7 @@ static void free_model(mfa_model m) {
 
 static bool is_fin(double v) { return std::isfinite(v); }
 
-static mfa_status check_knots(const double* T, int n, int p, int blk, int axis) {
+mfa_status check_knots(const double* T, int n, int p, int blk, int axis) {
   for (int i = 0; i < n + p + 1; ++i)
     if (!is_fin(T[i])) return fail(MFA_E_ARG, "block %d axis %d: knot %d not finite", blk, axis, i);
   for (int i = 0; i + 1 < n + p + 1; ++i)
@@ -219,7 +219,7 @@ static mfa_status check_knots(const double* T, int n, int p, int blk, int axis) 
   return MFA_OK;
 }
 
-static void default_knots(int n, int p, double* T) {
+void default_knots(int n, int p, double* T) {
   for (int i = 0; i <= p; ++i) {
     T[i] = 0.0;
     T[n + i] = 1.0;

@@ -41,6 +41,11 @@ struct mfa_model_s {
 mfa_status fail(mfa_status st, const char* fmt, ...);
 mfa_status hip_fail(hipError_t e, const char* what);
 mfa::Storage storage_of(mfa_model m);
+// Knot vectors: validation of a clamped nondecreasing vector on [0, 1]
+// (n + p + 1 values; blk/axis only label the message) and the clamped
+// uniform default T[p + j] = j / (n - p).
+mfa_status check_knots(const double* T, int n, int p, int blk, int axis);
+void default_knots(int n, int p, double* T);
 mfa_status check_device(mfa_model m);
 // Validated kernel arguments of a render of model m (shared by the direct
 // entry point and the server).

@@ -121,3 +121,51 @@ def test_null_model_calls_are_rejected():
     assert lib.mfa_quantize(None, 5, L.MFA_F32, None) == L.MFA_E_ARG
     assert lib.mfa_default_knots(2, 3, None) == L.MFA_E_ARG
     assert "mfa-gfx950" in lib.mfa_version().decode()
+
+
+def _i3(*v):
+    return (C.c_int32 * 3)(*v)
+
+
+def test_encode_workspace_size_and_rejections():
+    lib = L.lib()
+    nb = C.c_int64()
+    assert lib.mfa_encode_workspace(_i3(10, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_OK
+    al = lambda v: (v + 255) // 256 * 256
+    want = sum(al(8 * n * r) for n, r in ((5, 10), (6, 12), (7, 14))) \
+        + al(8 * 5 * 12 * 14) + al(8 * 5 * 6 * 14)
+    assert nb.value == want
+    assert lib.mfa_encode_workspace(_i3(4, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_E_ARG
+    assert lib.mfa_encode_workspace(_i3(10, 12, 14), _i3(5, 6, 7), None) == L.MFA_E_ARG
+
+
+def test_encode_rejects_bad_arguments_before_device_work():
+    """Every call here fails validation on the host, so the fake device
+    pointers are never used."""
+    lib = L.lib()
+    res, nc = (10, 9, 8), (5, 5, 6)
+    tabs = [np.linspace(0.0, 1.0, r) for r in res]
+    fake = C.c_void_p(0x1000)
+
+    def call(tabs=tabs, degree=(3, 3, 3), nc=nc, res=res, knots=None, work_bytes=1 << 30):
+        ptrs = (C.c_void_p * 3)(*[t.ctypes.data for t in tabs])
+        kn = None if knots is None else (C.c_void_p * 3)(*[k.ctypes.data for k in knots])
+        st = lib.mfa_encode_grid(_i3(*res), ptrs, fake, _i3(*degree), _i3(*nc), kn, fake, fake,
+                                 work_bytes, None)
+        return st, lib.mfa_last_error().decode()
+
+    assert call(degree=(0, 3, 3))[0] == L.MFA_E_ARG
+    assert call(nc=(11, 5, 6))[0] == L.MFA_E_ARG                        # res < n_ctrl
+    assert call(work_bytes=16)[0] == L.MFA_E_ARG
+    bad = [t.copy() for t in tabs]
+    bad[1][3] = 1.5
+    st, msg = call(tabs=bad)
+    assert st == L.MFA_E_ARG and "outside [0, 1]" in msg
+    bad = [t.copy() for t in tabs]
+    bad[2][:] = 0.5                                                     # every sample in one span
+    st, msg = call(tabs=bad)
+    assert st == L.MFA_E_ARG and "dependent columns" in msg
+    k = [synth.clamped_uniform_knots(n, 3) for n in nc]
+    k[0] = k[0][::-1].copy()                                            # decreasing knots
+    assert call(knots=k)[0] == L.MFA_E_ARG
+    assert lib.mfa_encode_grid(None, None, None, None, None, None, None, None, 0, None) == L.MFA_E_ARG
