@@ -349,12 +349,27 @@ mfa_status mfa_server_destroy(mfa_server server);
  * knots, and when some B_a^T B_a is not positive definite (a basis function
  * with too few samples in its support: raise res or lower n_ctrl).
  * The call waits for the upload of the B_a+ tables on the stream (so for
- * the work queued before it); the mode products are left in flight.      */
+ * the work queued before it); the mode products are left in flight.
+ * mfa_encode_grid = mfa_encode_plan + mfa_encode_apply: blocks of one
+ * partition have equal sizes and knots (Sec. IV-A1, IV-A2), so a plan,
+ * made once into work, serves every block:
+ *  mfa_encode_plan  : validates the arguments, builds the B_a+ tables and
+ *                     uploads them into work (waits for the upload);
+ *  mfa_encode_apply : the three mode products of one block's values into
+ *                     ctrl, left in flight; work must hold a plan made for
+ *                     the same res and n_ctrl (and the apply of one block
+ *                     must finish before another uses the same work).   */
 mfa_status mfa_encode_workspace(const int32_t res[3], const int32_t n_ctrl[3], int64_t* bytes);
 mfa_status mfa_encode_grid(const int32_t res[3], const double* const axis_u[3], const float* values,
                            const int32_t degree[3], const int32_t n_ctrl[3],
                            const double* const knots[3], double* ctrl, void* work,
                            int64_t work_bytes, void* stream);
+mfa_status mfa_encode_plan(const int32_t res[3], const double* const axis_u[3],
+                           const int32_t degree[3], const int32_t n_ctrl[3],
+                           const double* const knots[3], void* work, int64_t work_bytes,
+                           void* stream);
+mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctrl[3], const float* values,
+                            double* ctrl, void* work, int64_t work_bytes, void* stream);
 
 /* Host-only helpers (no device work): the storage rounding and the default
  * knot vector the library uses, exported so they can be checked on a CPU.

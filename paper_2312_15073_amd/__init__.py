@@ -230,6 +230,47 @@ def encode_grid(values, axis_u: Sequence, degree: Sequence[int], n_ctrl: Sequenc
     return out
 
 
+class EncodePlan:
+    """mfa_encode_plan for one grid shape (res samples -> n_ctrl control
+    points, degrees, knots, parameter tables), holding its CUDA workspace;
+    apply() encodes one block's CUDA float32 samples (res) into FP64 control
+    points (n_ctrl) on the stream, asynchronously."""
+
+    def __init__(self, res, axis_u, degree, n_ctrl, knots=None, device=None, stream=None):
+        torch = _torch()
+        self.res = tuple(int(v) for v in res)
+        self.n_ctrl = tuple(int(v) for v in n_ctrl)
+        tabs = [np.ascontiguousarray(np.asarray(u, dtype=np.float64)) for u in axis_u]
+        for a in range(3):
+            if tabs[a].shape != (self.res[a],):
+                raise ValueError(f"axis_u[{a}] must hold {self.res[a]} parameters")
+        nb = encode_workspace_bytes(self.res, self.n_ctrl)
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        self.work = torch.empty((nb,), dtype=torch.uint8, device=dev)
+        kn = None
+        if knots is not None:
+            kts = [None if k is None else np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+                   for k in knots]
+            kn = (C.c_void_p * 3)(*[None if k is None else k.ctypes.data for k in kts])
+        L.check(L.lib().mfa_encode_plan((C.c_int32 * 3)(*self.res),
+                                        (C.c_void_p * 3)(*[t.ctypes.data for t in tabs]),
+                                        (C.c_int32 * 3)(*[int(v) for v in degree]),
+                                        (C.c_int32 * 3)(*self.n_ctrl), kn,
+                                        C.c_void_p(self.work.data_ptr()), int(self.work.numel()),
+                                        _stream_ptr(stream)))
+
+    def apply(self, values, out=None, stream=None):
+        torch = _torch()
+        pv = _dev_ptr(values, torch.float32, self.res, "values")
+        if out is None:
+            out = torch.empty(self.n_ctrl, dtype=torch.float64, device=values.device)
+        po = _dev_ptr(out, torch.float64, self.n_ctrl, "out")
+        L.check(L.lib().mfa_encode_apply((C.c_int32 * 3)(*self.res), (C.c_int32 * 3)(*self.n_ctrl),
+                                         pv, po, C.c_void_p(self.work.data_ptr()),
+                                         int(self.work.numel()), _stream_ptr(stream)))
+        return out
+
+
 def make_camera(cam: dict) -> L.Camera:
     c = L.Camera()
     c.kind = int(cam["kind"])

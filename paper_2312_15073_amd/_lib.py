@@ -100,6 +100,11 @@ SIGNATURES = {
     "mfa_encode_grid": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_void_p), C.c_void_p,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mfa_encode_plan": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                                  C.c_void_p, C.c_int64, C.c_void_p]),
+    "mfa_encode_apply": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "mfa_quantize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     "mfa_default_knots": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
     "mfa_last_error": (C.c_char_p, []),

@@ -17,8 +17,12 @@ LIB = os.path.join(HERE, "libmfa.so")
 SOURCES = ["mfa_host.cpp", "mfa_server.cpp", "mfa_kernels.hip", "mfa_encode.hip"]
 ARCH = "gfx950"
 
-# Packed FP32 instructions are switched off for all device code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are switched off for all device code.  Matrix-
+# core accumulators stay in ordinary VGPRs (gfx950 takes them there), which
+# spares the encoder's GEMM loop a copy of every accumulator to and from the
+# accumulation registers on each step.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function"] + DEVICE_FLAGS
 

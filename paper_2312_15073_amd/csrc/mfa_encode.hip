@@ -24,9 +24,11 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// C[b] = A[b] * B[b] for b < batch: A is M x K row-major (lda), B is K x N
-// (element (k, n) at B[k * ldb + n], or at B[n * ldb + k] when TRANS_B),
-// C is M x N row-major (ldc); s* are the batch strides in elements.
+// C[b] = A[b] * B[b] for b < batch: element (m, k) of A at A[m * lda + k]
+// (A[k * lda + m] when TRANS_A), element (k, n) of B at B[k * ldb + n];
+// C is M x N row-major (ldc); s* are the batch strides in elements.  The
+// per-axis tables are stored transposed (N_a x n_a), so that the 16 lanes
+// reading one k of a fragment read 16 consecutive values.
 struct GemmArgs {
   int64_t M, N, K, batch;
   const double* A;
@@ -42,48 +44,96 @@ constexpr int kGemmTile = 32;     // C tile per wave: 2 x 2 MFMA blocks of 16 x 
 
 // One wave per 32 x 32 tile of C; tiles are numbered with the M tile
 // fastest, so the waves of a workgroup share the columns of B they read.
-// Per step of 4 along K each lane supplies A[m0 + 16t + lane % 16][k] and
-// B[k][n0 + 16u + lane % 16] with k = k0 + lane / 16 (zero outside the
-// matrices), and the MFMA leaves element (i, j) of a 16 x 16 block in lane
-// j + 16 * (i % 4), register i / 4.
-template <typename TB, bool TRANS_B>
-__global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(GemmArgs g) {
+// Per step of 4 along K each lane supplies A(m0 + 16t + lane % 16, k) and
+// B(k, n0 + 16u + lane % 16) with k = k0 + lane / 16, and the MFMA leaves
+// element (i, j) of a 16 x 16 block in lane j + 16 * (i % 4), register
+// i / 4.  Lanes past the last row of A or column of B read the last one
+// instead (in bounds): they only feed outputs that are not stored, so the
+// main loop has no predicates; the K tail runs one step with zeros past K.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;   // global-memory pointer
+
+constexpr int kGemmUnroll = 4;    // K steps whose loads are issued together
+
+template <typename TB, bool TRANS_A>
+__global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restrict__ gA,
+                                                         const TB* __restrict__ gB,
+                                                         double* __restrict__ gC, GemmArgs g) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * (kGemmBlock / 64) + (threadIdx.x >> 6);
   const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + kGemmTile - 1) / kGemmTile;
   if (w >= tm * tn * g.batch) return;                  // whole wave
   const int64_t im = w % tm, rest = w / tm, jn = rest % tn, b = rest / tn;
-  const double* __restrict__ A = g.A + b * g.sA;
-  const TB* __restrict__ B = static_cast<const TB*>(g.B) + b * g.sB;
-  double* __restrict__ C = g.C + b * g.sC;
   const int c16 = lane & 15, q = lane >> 4;
   const int64_t m0 = im * kGemmTile, n0 = jn * kGemmTile;
+  const double* A0 = gA + b * g.sA;
+  const TB* B0 = gB + b * g.sB;
+  gptr<double> pa[2];
+  gptr<TB> pb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t m = min(m0 + 16 * t + c16, g.M - 1), n = min(n0 + 16 * t + c16, g.N - 1);
+    pa[t] = (gptr<double>)(TRANS_A ? A0 + (int64_t)q * g.lda + m : A0 + m * g.lda + q);
+    pb[t] = (gptr<TB>)(B0 + (int64_t)q * g.ldb + n);
+  }
+  const int64_t step_a = TRANS_A ? 4 * g.lda : 4, step_b = 4 * g.ldb;
   v4d acc[2][2];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) acc[t][u] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int64_t k0 = 0; k0 < g.K; k0 += 4) {
-    const int64_t k = k0 + q;
-    const bool kin = k < g.K;
-    double a[2], bv[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t m = m0 + 16 * t + c16;
-      a[t] = (kin && m < g.M) ? A[m * g.lda + k] : 0.0;
-      const int64_t n = n0 + 16 * t + c16;
-      if (kin && n < g.N)
-        bv[t] = (double)(TRANS_B ? B[n * g.ldb + k] : B[k * g.ldb + n]);
-      else
-        bv[t] = 0.0;
-    }
+  auto mma = [&](const double (&a)[2], const double (&bv)[2]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u)
         acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[u], acc[t][u], 0, 0, 0);
+  };
+  const int64_t kfull = g.K & ~(int64_t)3;
+  int64_t k0 = 0;
+  for (; k0 + 4 * kGemmUnroll <= kfull; k0 += 4 * kGemmUnroll) {
+    double a[kGemmUnroll][2];
+    TB bt[kGemmUnroll][2];
+#pragma unroll
+    for (int s = 0; s < kGemmUnroll; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[s][t] = pa[t][s * step_a];
+        bt[s][t] = pb[t][s * step_b];
+      }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      pa[t] += kGemmUnroll * step_a;
+      pb[t] += kGemmUnroll * step_b;
+    }
+#pragma unroll
+    for (int s = 0; s < kGemmUnroll; ++s) {
+      const double bv[2] = {(double)bt[s][0], (double)bt[s][1]};
+      mma(a[s], bv);
+    }
   }
+  for (; k0 < kfull; k0 += 4) {
+    double a[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = *pa[t];
+      bv[t] = (double)*pb[t];
+      pa[t] += step_a;
+      pb[t] += step_b;
+    }
+    mma(a, bv);
+  }
+  if (kfull < g.K) {
+    const bool kin = kfull + q < g.K;
+    double a[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = kin ? *pa[t] : 0.0;
+      bv[t] = kin ? (double)*pb[t] : 0.0;
+    }
+    mma(a, bv);
+  }
+  double* __restrict__ C = gC + b * g.sC;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -95,14 +145,15 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(GemmArgs g) {
       }
 }
 
-template <typename TB, bool TRANS_B>
+template <typename TB, bool TRANS_A>
 hipError_t gemm(const GemmArgs& g, hipStream_t st) {
   const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + kGemmTile - 1) / kGemmTile) *
                         g.batch;
   const int64_t blocks = (tiles + kGemmBlock / 64 - 1) / (kGemmBlock / 64);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_B>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st, g);
+  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st, g.A,
+                     static_cast<const TB*>(g.B), g.C, g);
   return hipGetLastError();
 }
 
@@ -133,7 +184,7 @@ void basis_values(const double* T, int p, int s, double u, double* N) {
   }
 }
 
-// Q = (B^T B)^-1 B^T (n x N row-major) for the collocation matrix B of one
+// Q = (B^T B)^-1 B^T, stored transposed (N x n row-major), for the collocation matrix B of one
 // axis: the Gram matrix is banded (bandwidth p), factorised as L L^T, and
 // each column B^T e_i (non-zero on rows s_i - p .. s_i) is solved for.
 mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N, int axis,
@@ -185,14 +236,14 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
       for (int m = j + 1; m <= std::min(n - 1, j + p); ++m) v -= L[(size_t)m * w + (m - j)] * y[m];
       y[j] = v / L[(size_t)j * w];
     }
-    for (int j = 0; j < n; ++j) Q[(size_t)j * N + i] = y[j];
+    for (int j = 0; j < n; ++j) Q[(size_t)i * n + j] = y[j];
   }
   return MFA_OK;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace layout (FP64): Q0, Q1, Q2, then Y0 = F x_0 B0+ (n0 x N1 x N2)
+// Workspace layout (FP64): Q0, Q1, Q2 (B_a+ transposed), then Y0 = F x_0 B0+ (n0 x N1 x N2)
 // and Y1 = Y0 x_1 B1+ (n0 x n1 x N2).
 struct EncodeLayout {
   size_t q[3], y0, y1, total;
@@ -243,14 +294,14 @@ extern "C" mfa_status mfa_encode_workspace(const int32_t res[3], const int32_t n
   return MFA_OK;
 }
 
-extern "C" mfa_status mfa_encode_grid(const int32_t res[3], const double* const axis_u[3],
-                                      const float* values, const int32_t degree[3],
-                                      const int32_t n_ctrl[3], const double* const knots[3],
-                                      double* ctrl, void* work, int64_t work_bytes, void* stream) {
+extern "C" mfa_status mfa_encode_plan(const int32_t res[3], const double* const axis_u[3],
+                                      const int32_t degree[3], const int32_t n_ctrl[3],
+                                      const double* const knots[3], void* work, int64_t work_bytes,
+                                      void* stream) {
   if (!degree) return fail(MFA_E_ARG, "null degree");
   mfa_status st = check_sizes(res, n_ctrl, degree);
   if (st != MFA_OK) return st;
-  if (!axis_u || !values || !ctrl || !work) return fail(MFA_E_ARG, "null axis_u / values / ctrl / work");
+  if (!axis_u || !work) return fail(MFA_E_ARG, "null axis_u / work");
   const EncodeLayout lay = encode_layout(res, n_ctrl);
   if (work_bytes < (int64_t)lay.total)
     return fail(MFA_E_ARG, "workspace of %lld bytes, %lld needed", (long long)work_bytes,
@@ -275,27 +326,53 @@ extern "C" mfa_status mfa_encode_grid(const int32_t res[3], const double* const 
   }
   hipStream_t hs = (hipStream_t)stream;
   uint8_t* wb = static_cast<uint8_t*>(work);
-  double* dq[3];
   for (int a = 0; a < 3; ++a) {
-    dq[a] = reinterpret_cast<double*>(wb + lay.q[a]);
-    hipError_t e = hipMemcpyAsync(dq[a], Q[a].data(), Q[a].size() * sizeof(double),
+    hipError_t e = hipMemcpyAsync(wb + lay.q[a], Q[a].data(), Q[a].size() * sizeof(double),
                                   hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "encode: pseudo-inverse upload");
   }
   // the host tables must outlive their upload: wait for it (and for the
-  // work queued before it); the GEMMs below are left in flight
+  // work queued before it on the stream)
   hipError_t e = hipStreamSynchronize(hs);
   if (e != hipSuccess) return hip_fail(e, "encode: pseudo-inverse upload");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctrl[3],
+                                       const float* values, double* ctrl, void* work,
+                                       int64_t work_bytes, void* stream) {
+  mfa_status st = check_sizes(res, n_ctrl, nullptr);
+  if (st != MFA_OK) return st;
+  if (!values || !ctrl || !work) return fail(MFA_E_ARG, "null values / ctrl / work");
+  const EncodeLayout lay = encode_layout(res, n_ctrl);
+  if (work_bytes < (int64_t)lay.total)
+    return fail(MFA_E_ARG, "workspace of %lld bytes, %lld needed", (long long)work_bytes,
+                (long long)lay.total);
+  hipStream_t hs = (hipStream_t)stream;
+  uint8_t* wb = static_cast<uint8_t*>(work);
+  const double* dq[3];
+  for (int a = 0; a < 3; ++a) dq[a] = reinterpret_cast<const double*>(wb + lay.q[a]);
   double* y0 = reinterpret_cast<double*>(wb + lay.y0);
   double* y1 = reinterpret_cast<double*>(wb + lay.y1);
   const int64_t N0 = res[0], N1 = res[1], N2 = res[2];
   const int64_t n0 = n_ctrl[0], n1 = n_ctrl[1], n2 = n_ctrl[2];
-  GemmArgs g0{n0, N1 * N2, N0, 1, dq[0], N0, 0, values, N1 * N2, 0, y0, N1 * N2, 0};
-  GemmArgs g1{n1, N2, N1, n0, dq[1], N1, 0, y0, N2, N1 * N2, y1, N2, n1 * N2};
-  GemmArgs g2{n0 * n1, n2, N2, 1, y1, N2, 0, dq[2], N2, 0, ctrl, n2, 0};
-  e = gemm<float, false>(g0, hs);
-  if (e == hipSuccess) e = gemm<double, false>(g1, hs);
-  if (e == hipSuccess) e = gemm<double, true>(g2, hs);
+  // tables dq[a] are B_a+ transposed: N_a x n_a
+  GemmArgs g0{n0, N1 * N2, N0, 1, dq[0], n0, 0, values, N1 * N2, 0, y0, N1 * N2, 0};
+  GemmArgs g1{n1, N2, N1, n0, dq[1], n1, 0, y0, N2, N1 * N2, y1, N2, n1 * N2};
+  GemmArgs g2{n0 * n1, n2, N2, 1, y1, N2, 0, dq[2], n2, 0, ctrl, n2, 0};
+  hipError_t e = gemm<float, true>(g0, hs);
+  if (e == hipSuccess) e = gemm<double, true>(g1, hs);
+  if (e == hipSuccess) e = gemm<double, false>(g2, hs);
   if (e != hipSuccess) return hip_fail(e, "encode: GEMM launch");
   return MFA_OK;
+}
+
+extern "C" mfa_status mfa_encode_grid(const int32_t res[3], const double* const axis_u[3],
+                                      const float* values, const int32_t degree[3],
+                                      const int32_t n_ctrl[3], const double* const knots[3],
+                                      double* ctrl, void* work, int64_t work_bytes, void* stream) {
+  if (!values || !ctrl) return fail(MFA_E_ARG, "null values / ctrl");
+  mfa_status st = mfa_encode_plan(res, axis_u, degree, n_ctrl, knots, work, work_bytes, stream);
+  if (st != MFA_OK) return st;
+  return mfa_encode_apply(res, n_ctrl, values, ctrl, work, work_bytes, stream);
 }

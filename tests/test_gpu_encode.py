@@ -105,3 +105,21 @@ def test_encode_reproduces_spline_and_reuses_workspace(mfa, dev):
     got = run_case(mfa, dev, F, axis_u, (p, p, p), n, knots, work=work)
     # F holds the spline rounded to FP32: the fit reproduces C0 to that rounding
     assert np.abs(got - C0).max() <= 1e-5 * np.abs(C0).max()
+
+
+def test_encode_plan_serves_several_blocks(mfa, dev):
+    """One plan, eight octant blocks of one volume (the partition of
+    Sec. IV-A1): each apply equals the oracle fit of its block."""
+    import torch
+    rng = np.random.default_rng(30)
+    res, n_ctrl = (24, 20, 28), (10, 9, 12)
+    axis_u = [np.linspace(0.0, 1.0, r) for r in res]
+    announce("encode plan, 8 blocks")
+    plan = mfa.EncodePlan(res, axis_u, (3, 3, 3), n_ctrl, device=dev)
+    blocks = [rng.standard_normal(res).astype(np.float32) for _ in range(8)]
+    outs = [plan.apply(torch.as_tensor(b).to(dev)) for b in blocks]
+    torch.cuda.synchronize()
+    kn = [synth.clamped_uniform_knots(n, 3) for n in n_ctrl]
+    for b, o in zip(blocks, outs):
+        ref = oe.fit_grid(b.astype(np.float64), axis_u, (3, 3, 3), kn, n_ctrl)
+        assert np.abs(o.cpu().numpy() - ref).max() <= REL_ENC * np.abs(b).max()
