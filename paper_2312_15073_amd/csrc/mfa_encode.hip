@@ -25,8 +25,9 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C[b] = A[b] * B[b] for b < batch: element (m, k) of A at A[m * lda + k]
-// (A[k * lda + m] when TRANS_A), element (k, n) of B at B[k * ldb + n];
-// C is M x N row-major (ldc); s* are the batch strides in elements.  The
+// (A[k * lda + m] when TRANS_A), element (k, n) of B at B[k * ldb + n],
+// element (m, n) of C at C[m * ldc + n] (C[n * ldc + m] when c_trans);
+// s* are the batch strides in elements.  The
 // per-axis tables are stored transposed (N_a x n_a), so that the 16 lanes
 // reading one k of a fragment read 16 consecutive values.
 struct GemmArgs {
@@ -37,6 +38,7 @@ struct GemmArgs {
   int64_t ldb, sB;
   double* C;
   int64_t ldc, sC;
+  int32_t c_trans;     // element (m, n) of C at C[n * ldc + m]
 };
 
 constexpr int kGemmBlock = 256;   // 4 waves, each computing its own C tile
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
-        if (m < g.M && n < g.N) C[m * g.ldc + n] = acc[t][u][r];
+        if (m < g.M && n < g.N) C[g.c_trans ? n * g.ldc + m : m * g.ldc + n] = acc[t][u][r];
       }
 }
 
@@ -244,7 +246,7 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace layout (FP64): Q0, Q1, Q2 (B_a+ transposed), then Y0 = F x_0 B0+ (n0 x N1 x N2)
-// and Y1 = Y0 x_1 B1+ (n0 x n1 x N2).
+// and Y1 = Y0 x_1 B1+ (stored N2 x n0 x n1).
 struct EncodeLayout {
   size_t q[3], y0, y1, total;
 };
@@ -357,12 +359,14 @@ extern "C" mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctr
   const int64_t N0 = res[0], N1 = res[1], N2 = res[2];
   const int64_t n0 = n_ctrl[0], n1 = n_ctrl[1], n2 = n_ctrl[2];
   // tables dq[a] are B_a+ transposed: N_a x n_a
-  GemmArgs g0{n0, N1 * N2, N0, 1, dq[0], n0, 0, values, N1 * N2, 0, y0, N1 * N2, 0};
-  GemmArgs g1{n1, N2, N1, n0, dq[1], n1, 0, y0, N2, N1 * N2, y1, N2, n1 * N2};
-  GemmArgs g2{n0 * n1, n2, N2, 1, y1, N2, 0, dq[2], n2, 0, ctrl, n2, 0};
+  // Y1 is written transposed, [N2][n0 * n1], so that the third product
+  // reads its A operand along rows of 16 consecutive values
+  GemmArgs g0{n0, N1 * N2, N0, 1, dq[0], n0, 0, values, N1 * N2, 0, y0, N1 * N2, 0, 0};
+  GemmArgs g1{n1, N2, N1, n0, dq[1], n1, 0, y0, N2, N1 * N2, y1, n0 * n1, n1, 1};
+  GemmArgs g2{n0 * n1, n2, N2, 1, y1, n0 * n1, 0, dq[2], n2, 0, ctrl, n2, 0, 0};
   hipError_t e = gemm<float, true>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
-  if (e == hipSuccess) e = gemm<double, false>(g2, hs);
+  if (e == hipSuccess) e = gemm<double, true>(g2, hs);
   if (e != hipSuccess) return hip_fail(e, "encode: GEMM launch");
   return MFA_OK;
 }
