@@ -118,7 +118,7 @@ def phong(rgb: np.ndarray, g: np.ndarray, L: np.ndarray, ka, kd, ks, g0, m: int)
 
 
 def render(field, box_lo, box_hi, cam: dict, params: dict, W: int, H: int,
-           pixels=None, record_alpha: bool = False, k_range=None):
+           pixels=None, record_alpha: bool = False, k_range=None, region=None):
     """Ray-cast the field (callable x(m,3) -> (f (m,), grad (m,3))).
 
     Returns dict(rgba (m,4) premultiplied colour + opacity, K (m,) scheduled
@@ -126,12 +126,28 @@ def render(field, box_lo, box_hi, cam: dict, params: dict, W: int, H: int,
     the m listed pixels (all pixels in row-major order by default).
     k_range=(k0,k1) composites only samples k0 <= k < k1 (for segment
     compositing; termination then disabled).
+
+    region=(owner, blo, bhi, rlo, rhi): a partial render of the paper's
+    object-space split (Sec. IV-A4: each node renders its own blocks to a
+    partial image, composited afterwards by "over", Sec. IV-A5).  Reading:
+    the model's sample schedule is kept and only samples whose owning block
+    (owner(x) -> (m,3) block indices, D3) lies in the block box [blo, bhi)
+    are composited; termination applies to the partial's own opacity.  The
+    result also holds key (m,): the entry parameter of the ray into the
+    region's world box [rlo, rhi] (slab test as above), +inf when the ray
+    misses that box or the model box; partial images are composited in the
+    order of their keys (regions are disjoint boxes, so along a ray the
+    samples of each form one run, in key order).
     """
     lo = np.asarray(box_lo, dtype=np.float64)
     hi = np.asarray(box_hi, dtype=np.float64)
     o, d = pixel_rays(cam, W, H, pixels)
     m = o.shape[0]
     t_near, t_far, miss = slab(o, d, lo, hi)
+    key = None
+    if region is not None:
+        owner, blo, bhi, rlo, rhi = region
+        r_near, _, r_miss = slab(o, d, np.asarray(rlo, np.float64), np.asarray(rhi, np.float64))
     dt = float(params["step"])
     K = sample_counts(t_near, t_far, miss, dt, int(params["max_samples"]))
     L = -d / np.sqrt((d * d).sum(axis=1))[:, None]
@@ -144,6 +160,8 @@ def render(field, box_lo, box_hi, cam: dict, params: dict, W: int, H: int,
     ert = float(params["ert_alpha"])
     k0, k1 = (0, kmax) if k_range is None else k_range
     use_ert = k_range is None
+    if region is not None:
+        key = np.where(r_miss | (K == 0), np.inf, r_near)
     for k in range(kmax):
         sel = np.nonzero(active & (k < K))[0]
         if len(sel) == 0:
@@ -152,6 +170,12 @@ def render(field, box_lo, box_hi, cam: dict, params: dict, W: int, H: int,
             continue
         tk = t_near[sel] + (k + 0.5) * dt
         x = o[sel] + tk[:, None] * d[sel]
+        if region is not None:
+            b = owner(x)
+            inr = np.all((b >= np.asarray(blo)) & (b < np.asarray(bhi)), axis=1)
+            sel, x = sel[inr], x[inr]
+            if len(sel) == 0:
+                continue
         f, g = field(x)
         rgba = transfer(f, params["tf"], params["vmin"], params["vmax"])
         a = rgba[:, 3]
@@ -168,6 +192,8 @@ def render(field, box_lo, box_hi, cam: dict, params: dict, W: int, H: int,
             active[stop] = False
     rgba_out = np.concatenate([C, A[:, None]], axis=1)
     out = dict(rgba=rgba_out, K=K, used=used, t_near=t_near, t_far=t_far, miss=miss)
+    if key is not None:
+        out["key"] = key
     if record_alpha:
         out["alpha"] = alpha_rec
     return out
@@ -187,6 +213,31 @@ def over(front: np.ndarray, back: np.ndarray) -> np.ndarray:
     """Composite premultiplied RGBA 'front' over 'back' (Sec. IV-A5)."""
     af = front[..., 3:4]
     return front + (1.0 - af) * back
+
+
+def composite(images, keys) -> np.ndarray:
+    """Depth-ordered compositing of partial images (Sec. IV-A5): per pixel
+    the partials in increasing key order (ties in list order), folded front
+    to back with "over".  images: (G, m, 4), keys: (G, m)."""
+    images = np.asarray(images, dtype=np.float64)
+    keys = np.asarray(keys, dtype=np.float64)
+    order = np.argsort(keys, axis=0, kind="stable")          # (G, m)
+    m = images.shape[1]
+    out = np.zeros((m, 4))
+    cols = np.arange(m)
+    for g in range(images.shape[0]):
+        out = over(out, images[order[g], cols])
+    return out
+
+
+def block_owner_fn(model):
+    """owner(x) -> (m,3) owning block per axis (D3) for region renders."""
+    from .bspline import world_to_param
+
+    def fn(x):
+        bids, _, _ = world_to_param(model, x)
+        return bids
+    return fn
 
 
 def ert_replay_f32(alpha: np.ndarray, K: np.ndarray, ert_alpha) -> np.ndarray:

@@ -237,3 +237,107 @@ def test_ert_replay_matches_fp64_decision_outside_band():
     rep = orr.ert_replay_f32(out["alpha"], out["K"], params["ert_alpha"])
     assert (out["used"] < out["K"]).sum() >= 5           # some rays terminate early
     np.testing.assert_array_equal(rep, out["used"])
+
+
+# ---------------------------------------------------------------- object-space compositing
+def small_multiblock_model(seed=21, p=3):
+    """3x2x2 blocks with uneven edges and control-point counts."""
+    rng = np.random.default_rng(seed)
+    edges = [np.array([0.0, 0.3, 0.55, 1.0]), np.array([0.0, 0.6, 1.0]), np.array([0.0, 0.45, 1.0])]
+    blocks = []
+    for _ in range(12):
+        n = [int(v) for v in rng.integers(p + 2, 9, size=3)]
+        knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
+        blocks.append(synth.BlockSpec([p] * 3, knots, rng.uniform(0.0, 1.0, size=n)))
+    return synth.ModelSpec([3, 2, 2], np.zeros(3), np.ones(3), edges, blocks, voxel=1.0 / 40)
+
+
+def region_arg(model, blo, bhi):
+    rlo = [model.edges[a][blo[a]] for a in range(3)]
+    rhi = [model.edges[a][bhi[a]] for a in range(3)]
+    return (orr.block_owner_fn(model), blo, bhi, rlo, rhi)
+
+
+def _partition(model, cuts):
+    """Block boxes of the split of the block grid at the given cut per axis."""
+    out = []
+    for a0 in ((0, cuts[0]), (cuts[0], model.grid[0])):
+        for a1 in ((0, cuts[1]), (cuts[1], model.grid[1])):
+            out.append(((a0[0], a1[0], 0), (a0[1], a1[1], model.grid[2])))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["ortho", "persp"])
+def test_composite_of_partials_equals_full_render_without_termination(kind):
+    """Associativity of "over" (Sec. IV-A5): the key-ordered composite of
+    the partial images of a partition of the blocks equals the full render
+    when termination is off; every ray crosses several regions."""
+    model = small_multiblock_model()
+    W, H = 14, 11
+    cam = (synth.ortho_camera(W, H, az_deg=35.0, el_deg=25.0) if kind == "ortho"
+           else synth.perspective_camera(W, H, az_deg=35.0, el_deg=25.0))
+    lo, hi = model.ctrl_min_max()
+    params = synth.render_params(model, tf=synth.tf_table_constant([0.9, 0.4, 0.2, 0.03]),
+                                 vmin=lo, vmax=hi)
+    params["ert_alpha"] = 2.0
+    field = orr.model_field(model)
+    full = orr.render(field, model.lo, model.hi, cam, params, W, H)
+    parts = [orr.render(field, model.lo, model.hi, cam, params, W, H,
+                        region=region_arg(model, blo, bhi))
+             for blo, bhi in _partition(model, (1, 1))]
+    comp = orr.composite([p["rgba"] for p in parts], [p["key"] for p in parts])
+    np.testing.assert_allclose(comp, full["rgba"], rtol=0, atol=1e-12)
+    crossing = sum(np.isfinite(p["key"]).astype(int) for p in parts)
+    assert (crossing >= 2).sum() >= 10 and crossing.max() >= 3     # rays through several regions
+
+
+def test_region_keys_order_the_sample_runs():
+    """Along each ray the composited samples of a region form one run, and
+    the runs come in the order of the region keys."""
+    model = small_multiblock_model(seed=22)
+    W, H = 9, 7
+    cam = synth.perspective_camera(W, H, az_deg=200.0, el_deg=-30.0)
+    lo, hi = model.ctrl_min_max()
+    params = synth.render_params(model, tf=synth.tf_table_constant([1, 1, 1, 0.02]),
+                                 vmin=lo, vmax=hi)
+    params["ert_alpha"] = 2.0
+    field = orr.model_field(model)
+    boxes = _partition(model, (2, 1))
+    parts = [orr.render(field, model.lo, model.hi, cam, params, W, H, record_alpha=True,
+                        region=region_arg(model, blo, bhi)) for blo, bhi in boxes]
+    for pix in range(W * H):
+        runs = []
+        for g, p in enumerate(parts):
+            nz = np.nonzero(p["alpha"][pix] > 0)[0]
+            if len(nz):
+                assert np.all(np.diff(nz) == 1)          # one contiguous run
+                runs.append((p["key"][pix], nz[0], nz[-1]))
+        runs.sort()
+        for (k1, a1, b1), (k2, a2, b2) in zip(runs, runs[1:]):
+            assert b1 < a2                               # key order = sample order
+
+
+def test_composite_brute_force_and_single_region():
+    rng = np.random.default_rng(7)
+    G, m = 4, 50
+    imgs = rng.uniform(0, 1, size=(G, m, 4))
+    keys = rng.permutation(np.concatenate([rng.uniform(0, 5, size=(G - 1) * m), np.full(m, np.inf)]))
+    keys = keys.reshape(G, m)
+    got = orr.composite(imgs, keys)
+    for i in range(m):
+        C, A = np.zeros(3), 0.0
+        for g in sorted(range(G), key=lambda g: (keys[g, i], g)):
+            C = C + (1.0 - A) * imgs[g, i, :3]
+            A = A + (1.0 - A) * imgs[g, i, 3]
+        np.testing.assert_allclose(got[i], np.append(C, A), rtol=0, atol=1e-14)
+    # one region holding every block: the partial render is the full render
+    model = small_multiblock_model(seed=23)
+    cam = synth.ortho_camera(8, 8)
+    lo, hi = model.ctrl_min_max()
+    params = synth.render_params(model, vmin=lo, vmax=hi)
+    field = orr.model_field(model)
+    full = orr.render(field, model.lo, model.hi, cam, params, 8, 8)
+    part = orr.render(field, model.lo, model.hi, cam, params, 8, 8,
+                      region=region_arg(model, (0, 0, 0), tuple(model.grid)))
+    np.testing.assert_array_equal(part["rgba"], full["rgba"])
+    np.testing.assert_array_equal(part["used"], full["used"])
