@@ -243,6 +243,31 @@ mfa_status mfa_render_frame(mfa_model model, const mfa_camera* camera, const mfa
                             int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
                             void* stream);
 
+/* Object-space split (Sec. IV-A4: each node ray-casts the blocks it holds
+ * into a partially rendered image; Sec. IV-A5: the partial images are
+ * combined by "over" in depth order).
+ *  mfa_render_partial : as mfa_render_frame, but only the samples owned by
+ *     blocks with block_lo[a] <= b[a] < block_hi[a] (the block-owner rule)
+ *     are composited, on the model's own sample schedule, and early
+ *     termination tests the partial's own opacity.  key: device FP64
+ *     [h][w] out, the entry parameter of the ray into the region's world box
+ *     (+inf when the ray misses that box or the model); the samples of
+ *     disjoint regions form runs along a ray in increasing key order.
+ *     Errors: MFA_E_ARG for an empty block range or one outside the grid.
+ *  mfa_composite_over : per pixel, the g partial images (host array of g
+ *     device FP32 [h][w][4] pointers, premultiplied) sorted by their keys
+ *     (host array of g device FP64 [h][w] pointers; equal keys keep list
+ *     order) and folded front to back, C += (1 - A) c, A += (1 - A) a, into
+ *     out (device FP32 [h][w][4]).  1 <= g <= 16.  With termination off and
+ *     regions that partition the blocks, the composite equals
+ *     mfa_render_frame up to FP32 rounding (associativity of "over").     */
+mfa_status mfa_render_partial(mfa_model model, const mfa_camera* camera,
+                              const mfa_render_params* params, const int32_t block_lo[3],
+                              const int32_t block_hi[3], int32_t w, int32_t h, float* rgba,
+                              double* key, const mfa_render_debug* dbg, void* stream);
+mfa_status mfa_composite_over(int32_t g, const float* const* images, const double* const* keys,
+                              int32_t w, int32_t h, float* out, void* stream);
+
 /* ------------------------------------------------------------------ serving */
 
 /* A request loop for many clients sharing one GPU: the visualisation

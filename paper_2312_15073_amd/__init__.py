@@ -184,6 +184,56 @@ def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False, s
     return (out, sp) if spans else out
 
 
+def render_partial(model: Model, cam: dict, params: dict, w: int, h: int, block_lo, block_hi,
+                   tf_dev=None, out=None, key=None, nsamp: bool = False, stream=None, device=None):
+    """Partial image of the samples owned by blocks in [block_lo, block_hi)
+    per axis (object-space split).  Returns rgba (h, w, 4) float32 and the
+    depth keys (h, w) float64, plus int32 (h, w, 2) sample counts if nsamp."""
+    torch = _torch()
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    if tf_dev is None:
+        tf_dev = torch.as_tensor(np.ascontiguousarray(params["tf"], dtype=np.float32), device=dev)
+    cobj = make_camera(cam)
+    pobj = make_params(params, tf_dev)
+    if out is None:
+        out = torch.empty((h, w, 4), dtype=torch.float32, device=dev)
+    if key is None:
+        key = torch.empty((h, w), dtype=torch.float64, device=dev)
+    po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
+    pk = _dev_ptr(key, torch.float64, (h, w), "key")
+    dbg = None
+    ns = None
+    if nsamp:
+        dbg = L.RenderDebug()
+        ns = torch.zeros((h, w, 2), dtype=torch.int32, device=dev)
+        dbg.nsamp = ns.data_ptr()
+    L.check(L.lib().mfa_render_partial(model.handle, C.byref(cobj), C.byref(pobj),
+                                       (C.c_int32 * 3)(*[int(v) for v in block_lo]),
+                                       (C.c_int32 * 3)(*[int(v) for v in block_hi]), int(w), int(h),
+                                       po, pk, C.byref(dbg) if dbg is not None else None,
+                                       _stream_ptr(stream)))
+    return (out, key, ns) if nsamp else (out, key)
+
+
+def composite_over(images: Sequence, keys: Sequence, out=None, stream=None):
+    """Depth-ordered "over" of partial images (CUDA float32 (h, w, 4) each)
+    by their keys (CUDA float64 (h, w) each)."""
+    torch = _torch()
+    g = len(images)
+    if g != len(keys) or g == 0:
+        raise ValueError("need as many keys as images")
+    h, w = int(images[0].shape[0]), int(images[0].shape[1])
+    pi = (C.c_void_p * g)(*[_dev_ptr(t, torch.float32, (h, w, 4), f"images[{i}]").value
+                            for i, t in enumerate(images)])
+    pk = (C.c_void_p * g)(*[_dev_ptr(t, torch.float64, (h, w), f"keys[{i}]").value
+                            for i, t in enumerate(keys)])
+    if out is None:
+        out = torch.empty((h, w, 4), dtype=torch.float32, device=images[0].device)
+    po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
+    L.check(L.lib().mfa_composite_over(g, pi, pk, w, h, po, _stream_ptr(stream)))
+    return out
+
+
 def encode_workspace_bytes(res: Sequence[int], n_ctrl: Sequence[int]) -> int:
     """Device scratch bytes that encode_grid needs for these sizes."""
     out = C.c_int64()

@@ -88,6 +88,11 @@ SIGNATURES = {
     "mfa_render_frame": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(RenderDebug),
                                    C.c_void_p]),
+    "mfa_render_partial": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.POINTER(RenderDebug), C.c_void_p]),
+    "mfa_composite_over": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "mfa_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
     "mfa_server_add_model": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "mfa_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),

@@ -25,6 +25,7 @@ hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st);
 hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
                          hipStream_t st);
+hipError_t launch_composite(const CompositeArgs& c, hipStream_t st);
 }  // namespace mfa
 
 using namespace mfa;
@@ -570,6 +571,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   const int imat = ic == mat_ids.end() ? -1 : ic->second;
 
   std::vector<double> edge_pool;
+  for (int a = 0; a < 3; ++a) m->edges[a] = edges[a];
   int edge_off[3];
   for (int a = 0; a < 3; ++a) {
     edge_off[a] = (int)edge_pool.size();
@@ -832,6 +834,54 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
   if (st != MFA_OK) return st;
   hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_render_partial(mfa_model m, const mfa_camera* cam,
+                                         const mfa_render_params* rp, const int32_t block_lo[3],
+                                         const int32_t block_hi[3], int32_t w, int32_t h,
+                                         float* rgba, double* key, const mfa_render_debug* dbg,
+                                         void* stream) {
+  RenderArgs r;
+  mfa_status st = make_render_args(m, cam, rp, w, h, rgba, dbg, &r);
+  if (st != MFA_OK) return st;
+  if (!block_lo || !block_hi || !key) return fail(MFA_E_ARG, "null block_lo / block_hi / key");
+  for (int a = 0; a < 3; ++a)
+    if (block_lo[a] < 0 || block_lo[a] >= block_hi[a] || block_hi[a] > m->grid[a])
+      return fail(MFA_E_ARG, "axis %d: block range [%d, %d) outside [0, %d) or empty", a,
+                  block_lo[a], block_hi[a], m->grid[a]);
+  r.partial = 1;
+  for (int a = 0; a < 3; ++a) {
+    r.reg_lo[a] = block_lo[a];
+    r.reg_hi[a] = block_hi[a];
+    r.reg_box_lo[a] = m->edges[a][block_lo[a]];
+    r.reg_box_hi[a] = m->edges[a][block_hi[a]];
+  }
+  r.key = key;
+  st = check_device(m);
+  if (st != MFA_OK) return st;
+  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "partial render launch");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_composite_over(int32_t g, const float* const* images,
+                                         const double* const* keys, int32_t w, int32_t h,
+                                         float* out, void* stream) {
+  if (g < 1 || g > kMaxPartials) return fail(MFA_E_ARG, "g = %d outside [1, %d]", g, kMaxPartials);
+  if (!images || !keys || !out) return fail(MFA_E_ARG, "null images / keys / out");
+  if (w < 1 || h < 1 || w > 16384 || h > 16384) return fail(MFA_E_ARG, "image %dx%d out of range", w, h);
+  CompositeArgs c{};
+  for (int i = 0; i < g; ++i) {
+    if (!images[i] || !keys[i]) return fail(MFA_E_ARG, "null image or key %d", i);
+    c.images[i] = reinterpret_cast<const float4*>(images[i]);
+    c.keys[i] = keys[i];
+  }
+  c.g = g;
+  c.npix = (int64_t)w * h;
+  c.out = reinterpret_cast<float4*>(out);
+  hipError_t e = launch_composite(c, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "composite launch");
   return MFA_OK;
 }
 

@@ -211,6 +211,25 @@ struct RenderArgs {
   double eye[3], fwd[3], right[3], up[3];
   double sx, sy, step;
   double inv_step;        // 1 / step (estimates only)
+  // partial render (object-space split): composite only the samples owned
+  // by blocks in [reg_lo, reg_hi) per axis, whose world box is
+  // [reg_box_lo, reg_box_hi]; key[pixel] = entry parameter of the ray into
+  // that box (+inf when the ray misses it or the model box)
+  int32_t partial;
+  int32_t reg_lo[3], reg_hi[3];
+  double reg_box_lo[3], reg_box_hi[3];
+  double* key;
+};
+
+// Depth-ordered compositing of up to kMaxPartials partial images.
+constexpr int kMaxPartials = 16;
+
+struct CompositeArgs {
+  const float4* images[kMaxPartials];   // [npix] premultiplied RGBA each
+  const double* keys[kMaxPartials];     // [npix] depth key each (+inf: empty)
+  int32_t g;
+  int64_t npix;
+  float4* out;
 };
 
 }  // namespace mfa

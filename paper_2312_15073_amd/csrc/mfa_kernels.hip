@@ -330,6 +330,7 @@ struct Probe {
   double u[3];
   SpanRec rec[3];
   int j[3];
+  int b[3];        // owning block per axis (0 for single-block models)
   int block;
 };
 
@@ -367,12 +368,16 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
     q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
     q.B = m.blocks + q.block;
 #pragma unroll
+    for (int a = 0; a < 3; ++a) q.b[a] = b[a];
+#pragma unroll
     for (int a = 0; a < 3; ++a) q.u[a] = param_of(xc[a], q.B->lo[a], q.B->inv_ext[a]);
   } else {
     q.block = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+      q.b[a] = 0;
       q.u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], q.B->inv_ext[a]);
+    }
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -990,6 +995,41 @@ __device__ __forceinline__ void sample_point(const Ray& ray, double step, int k,
   for (int a = 0; a < 3; ++a) x[a] = ray.o[a] + t * ray.d[a];
 }
 
+// Partial render: entry parameter t_in of the ray into the region's world
+// box (FP64 slab test, the same formula as the model box's) and the range
+// [k_lo, k_hi) of samples that can lie in it, widened by one sample on each
+// side (the block-owner rule decides the samples at the faces exactly).
+__device__ __forceinline__ void region_range(const RenderArgs& r, const Ray& ray, int& k_lo,
+                                             int& k_hi, double& t_in) {
+#pragma clang fp contract(off)
+  double tn = 0.0, tf = __builtin_inf();
+  bool miss = ray.K == 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (ray.d[a] == 0.0) {
+      miss |= (ray.o[a] < r.reg_box_lo[a]) || (ray.o[a] > r.reg_box_hi[a]);
+    } else {
+      const double inv = 1.0 / ray.d[a];
+      const double t1 = (r.reg_box_lo[a] - ray.o[a]) * inv;
+      const double t2 = (r.reg_box_hi[a] - ray.o[a]) * inv;
+      tn = fmax(tn, fmin(t1, t2));
+      tf = fmin(tf, fmax(t1, t2));
+    }
+  }
+  miss |= tn >= tf;
+  if (miss) {
+    t_in = __builtin_inf();
+    k_lo = k_hi = 0;
+    return;
+  }
+  t_in = tn;
+  const double a0 = (tn - ray.t_near) * r.inv_step - 0.5;
+  const double a1 = (tf - ray.t_near) * r.inv_step - 0.5;
+  k_lo = (int)fmax(floor(a0) - 1.0, 0.0);
+  k_hi = (int)fmin(ceil(a1) + 2.0, (double)ray.K);
+  if (k_lo > k_hi) k_lo = k_hi;
+}
+
 // Transfer-function coordinate s in [0, 255] of a value (shared by the
 // lookup and by the transparency test so both round identically).
 __device__ __forceinline__ float tf_coord(float f, float vmin, float inv_range) {
@@ -1045,10 +1085,10 @@ __device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, co
 template <int P, bool MULTI>
 __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs& r,
                                              const SpanRec* __restrict__ R, const Ray& ray,
-                                             const int* zpre) {
-  int k = 0, from = -1, lvl = 0, cell = -1, noleap = -1, last_c0 = -1;
+                                             const int* zpre, int k_lo, int k_hi) {
+  int k = k_lo, from = -1, lvl = 0, cell = -1, noleap = -1, last_c0 = -1;
   bool c0_empty = false;
-  while (k < ray.K) {
+  while (k < k_hi) {
     double x[3];
     sample_point(ray, r.step, k, x);
     const Loc Lc = locate<P, MULTI>(m, R, x);
@@ -1094,7 +1134,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
         te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
       }
       kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
-                      (float)(ray.K - 1));
+                      (float)(k_hi - 1));
     }
     if (kl > k + 1) {
       from = k;
@@ -1103,12 +1143,12 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
       ++k;
     }
   }
-  return ray.K;
+  return k_hi;
 }
 
 // One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
 // and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
-template <int P, Storage S, bool MULTI>
+template <int P, Storage S, bool MULTI, bool PARTIAL = false>
 __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs& r, int tile,
                                             const SpanRec* __restrict__ R,
                                             const float* __restrict__ MT, const float4* tf,
@@ -1130,7 +1170,12 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const int64_t pid = (int64_t)j * r.w + i;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
-  const int k0 = pix ? first_visible<P, MULTI>(m, r, R, ray, zpre) : 0;
+  int k_lo = 0, k_hi = ray.K;
+  double t_in = __builtin_inf();
+  if constexpr (PARTIAL) {
+    if (pix) region_range(r, ray, k_lo, k_hi, t_in);
+  }
+  const int k0 = pix ? first_visible<P, MULTI>(m, r, R, ray, zpre, k_lo, k_hi) : 0;
   if (r.alpha)
     for (int q = 0; q < k0; ++q) r.alpha[pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
@@ -1138,7 +1183,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   int last_mc = -1;
   bool last_empty = false;
   for (int k = k0;; ++k) {
-    const bool act = pix && !done && k < ray.K;
+    const bool act = pix && !done && k < k_hi;
     if (__ballot(act) == 0) break;                 // whole wave finished
     if (!act) continue;
     double x[3];
@@ -1159,7 +1204,13 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
       last_empty = transparent(bh, r, zpre);
       last_mc = Lc.mc;
     }
-    const bool empty = last_empty;
+    // a partial render skips the samples owned by blocks outside its region
+    bool outside = false;
+    if constexpr (PARTIAL) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) outside |= q.b[a] < r.reg_lo[a] || q.b[a] >= r.reg_hi[a];
+    }
+    const bool empty = last_empty || outside;
     float alpha = 0.f;
     if (!empty) {
       const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat);
@@ -1197,6 +1248,8 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     done = A >= r.ert_alpha;
   }
   if (pix) {
+    if (r.key)    // entry key: of the region, else of the model box
+      r.key[pid] = PARTIAL ? t_in : (ray.K > 0 ? ray.t_near : __builtin_inf());
     reinterpret_cast<float4*>(r.rgba)[pid] = make_float4(C0, C1, C2, A);
     if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, used);
     if (r.neval) r.neval[pid] = nev;
@@ -1222,7 +1275,7 @@ __device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
 
 // LDSREC: single-block model whose span records and basis tables are copied
 // into LDS once per workgroup.
-template <int P, Storage S, bool MULTI, bool LDSREC>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   __shared__ float4 tf[256];
@@ -1242,7 +1295,7 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   }
   stage_tf(r.tf, tf, zpre, wtot);
   const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-  render_tile<P, S, MULTI>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
+  render_tile<P, S, MULTI, PARTIAL>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
 }
 
 // ------------------------------------------------------------------ K6: persistent serving
@@ -1386,7 +1439,12 @@ template <int P, Storage S>
 static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
-  if (multi)
+  // a partial render of a single-block model holds every sample (its
+  // region is the model box): it is the full render, whose key is the
+  // entry parameter of the model box
+  if (multi && r.partial)
+    hipLaunchKernelGGL((render_k<P, S, true, false, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else if (multi)
     hipLaunchKernelGGL((render_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   else if (lds <= (size_t)kLdsRecBytes)
     hipLaunchKernelGGL((render_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
@@ -1438,6 +1496,61 @@ hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArg
 hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
                          hipStream_t st) {
   MFA_DISPATCH(render_p, m, multi, r, st)
+}
+
+// ------------------------------------------------------------------ K7: compositing
+// Depth-ordered "over" of partial images (Sec. IV-A5: compositing relies on
+// the associativity of the operator, in depth order).  One thread per pixel:
+// the (key, index) pairs of the G partials are sorted by an odd-even
+// transposition network over kMaxPartials registers (unused slots hold
+// +inf and sort last; equal keys keep list order), then folded front to
+// back: C += (1 - A) c_g, A += (1 - A) a_g.  Reads 24 bytes per partial and
+// writes 16 per pixel; HBM-bound.
+__global__ __launch_bounds__(kBlock) void composite_k(CompositeArgs c) {
+  const int64_t px = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (px >= c.npix) return;
+  double kv[kMaxPartials];
+  int id[kMaxPartials];
+#pragma unroll
+  for (int g = 0; g < kMaxPartials; ++g) {
+    kv[g] = g < c.g ? c.keys[g][px] : __builtin_inf();
+    id[g] = g;
+  }
+#pragma unroll
+  for (int round = 0; round < kMaxPartials; ++round) {
+#pragma unroll
+    for (int g = round & 1; g + 1 < kMaxPartials; g += 2) {
+      const bool swap = kv[g + 1] < kv[g] || (kv[g + 1] == kv[g] && id[g + 1] < id[g]);
+      const double tk = swap ? kv[g + 1] : kv[g];
+      const double uk = swap ? kv[g] : kv[g + 1];
+      const int ti = swap ? id[g + 1] : id[g];
+      const int ui = swap ? id[g] : id[g + 1];
+      kv[g] = tk;
+      kv[g + 1] = uk;
+      id[g] = ti;
+      id[g + 1] = ui;
+    }
+  }
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+#pragma unroll
+  for (int g = 0; g < kMaxPartials; ++g) {
+    if (id[g] < c.g) {
+      const float4 v = c.images[id[g]][px];
+      const float om = 1.f - A;
+      C0 = fmaf(om, v.x, C0);
+      C1 = fmaf(om, v.y, C1);
+      C2 = fmaf(om, v.z, C2);
+      A = fmaf(om, v.w, A);
+    }
+  }
+  store_stream(&c.out[px], make_float4(C0, C1, C2, A));
+}
+
+hipError_t launch_composite(const CompositeArgs& c, hipStream_t st) {
+  const int64_t blocks = (c.npix + kBlock - 1) / kBlock;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(composite_k, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
+  return hipGetLastError();
 }
 
 }  // namespace mfa

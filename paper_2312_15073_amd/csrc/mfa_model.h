@@ -20,6 +20,7 @@ struct mfa_model_s {
   std::vector<int64_t> coff;    // element offset per block
   std::vector<int32_t> rs1;     // row stride per block
   int64_t n_ctrl_total = 0;
+  std::vector<double> edges[3]; // block edges per axis (host copy), grid[a] + 1 each
   float vmin = 0.f, vmax = 0.f;
   void* d_ctrl = nullptr;
   int64_t ctrl_bytes = 0;
