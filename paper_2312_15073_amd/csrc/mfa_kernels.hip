@@ -1501,47 +1501,51 @@ hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const 
 // ------------------------------------------------------------------ K7: compositing
 // Depth-ordered "over" of partial images (Sec. IV-A5: compositing relies on
 // the associativity of the operator, in depth order).  One thread per pixel:
-// the (key, index) pairs of the G partials are sorted by an odd-even
-// transposition network over kMaxPartials registers (unused slots hold
-// +inf and sort last; equal keys keep list order), then folded front to
-// back: C += (1 - A) c_g, A += (1 - A) a_g.  Reads 24 bytes per partial and
-// writes 16 per pixel; HBM-bound.
+// the pixel of every partial is loaded first (coalesced 16-byte reads, in
+// list order), the (key, colour) tuples are sorted in registers by an
+// odd-even transposition network over GMAX slots (GMAX the smallest of 2, 4,
+// 8, 16 holding the G partials; unused slots hold +inf and sort last; a
+// swap needs a strictly smaller key, so equal keys keep list order), then
+// folded front to back: C += (1 - A) c, A += (1 - A) a.  Reads 24 bytes per
+// partial and writes 16 per pixel: HBM-bound.
+template <int GMAX>
 __global__ __launch_bounds__(kBlock) void composite_k(CompositeArgs c) {
   const int64_t px = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (px >= c.npix) return;
-  double kv[kMaxPartials];
-  int id[kMaxPartials];
+  double kv[GMAX];
+  float4 v[GMAX];
 #pragma unroll
-  for (int g = 0; g < kMaxPartials; ++g) {
-    kv[g] = g < c.g ? c.keys[g][px] : __builtin_inf();
-    id[g] = g;
+  for (int g = 0; g < GMAX; ++g) {
+    if (g < c.g) {
+      kv[g] = c.keys[g][px];
+      v[g] = c.images[g][px];
+    } else {
+      kv[g] = __builtin_inf();
+      v[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
 #pragma unroll
-  for (int round = 0; round < kMaxPartials; ++round) {
+  for (int round = 0; round < GMAX; ++round) {
 #pragma unroll
-    for (int g = round & 1; g + 1 < kMaxPartials; g += 2) {
-      const bool swap = kv[g + 1] < kv[g] || (kv[g + 1] == kv[g] && id[g + 1] < id[g]);
-      const double tk = swap ? kv[g + 1] : kv[g];
-      const double uk = swap ? kv[g] : kv[g + 1];
-      const int ti = swap ? id[g + 1] : id[g];
-      const int ui = swap ? id[g] : id[g + 1];
-      kv[g] = tk;
-      kv[g + 1] = uk;
-      id[g] = ti;
-      id[g + 1] = ui;
+    for (int g = round & 1; g + 1 < GMAX; g += 2) {
+      if (kv[g + 1] < kv[g]) {                 // adjacent transposition keeps ties stable
+        const double tk = kv[g];
+        kv[g] = kv[g + 1];
+        kv[g + 1] = tk;
+        const float4 tv = v[g];
+        v[g] = v[g + 1];
+        v[g + 1] = tv;
+      }
     }
   }
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
 #pragma unroll
-  for (int g = 0; g < kMaxPartials; ++g) {
-    if (id[g] < c.g) {
-      const float4 v = c.images[id[g]][px];
-      const float om = 1.f - A;
-      C0 = fmaf(om, v.x, C0);
-      C1 = fmaf(om, v.y, C1);
-      C2 = fmaf(om, v.z, C2);
-      A = fmaf(om, v.w, A);
-    }
+  for (int g = 0; g < GMAX; ++g) {
+    const float om = 1.f - A;
+    C0 = fmaf(om, v[g].x, C0);
+    C1 = fmaf(om, v[g].y, C1);
+    C2 = fmaf(om, v[g].z, C2);
+    A = fmaf(om, v[g].w, A);
   }
   store_stream(&c.out[px], make_float4(C0, C1, C2, A));
 }
@@ -1549,7 +1553,14 @@ __global__ __launch_bounds__(kBlock) void composite_k(CompositeArgs c) {
 hipError_t launch_composite(const CompositeArgs& c, hipStream_t st) {
   const int64_t blocks = (c.npix + kBlock - 1) / kBlock;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(composite_k, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
+  if (c.g <= 2)
+    hipLaunchKernelGGL(composite_k<2>, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
+  else if (c.g <= 4)
+    hipLaunchKernelGGL(composite_k<4>, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
+  else if (c.g <= 8)
+    hipLaunchKernelGGL(composite_k<8>, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
+  else
+    hipLaunchKernelGGL(composite_k<16>, dim3((unsigned)blocks), dim3(kBlock), 0, st, c);
   return hipGetLastError();
 }
 
