@@ -59,3 +59,71 @@ def fit_grid(F: np.ndarray, axis_u, degree, knots, n_ctrl) -> np.ndarray:
         B = collocation(np.asarray(knots[a], np.float64), int(degree[a]), int(n_ctrl[a]), axis_u[a])
         P = mode_product(P, np.linalg.pinv(B), a)
     return P
+
+
+def reconstruct_grid(P: np.ndarray, axis_u, degree, knots) -> np.ndarray:
+    """Values of the spline with control points P on the tensor grid of
+    parameters axis_u: P x_0 B0 x_1 B1 x_2 B2."""
+    R = np.asarray(P, dtype=np.float64)
+    for a in range(3):
+        B = collocation(np.asarray(knots[a], np.float64), int(degree[a]), R.shape[a], axis_u[a])
+        R = mode_product(R, B, a)
+    return R
+
+
+def span_errors(err: np.ndarray, axis_u, degree, knots):
+    """Per axis, the largest error over the samples whose parameter lies in
+    each knot span (span rule D2): a list of three arrays (n_a - p_a,)."""
+    out = []
+    for a in range(3):
+        T = np.asarray(knots[a], np.float64)
+        p, n = int(degree[a]), len(knots[a]) - int(degree[a]) - 1
+        s = find_span(T, p, n, axis_u[a]) - p
+        axes = tuple(b for b in range(3) if b != a)
+        marg = err.max(axis=axes)                    # max over the other two axes
+        e = np.zeros(n - p)
+        np.maximum.at(e, s, marg)
+        out.append(e)
+    return out
+
+
+def fit_adaptive(F: np.ndarray, axis_u, degree, n_init, e_max: float, max_iter: int = 10):
+    """Fixed-knot fits with knot insertion (paper Fig. 1): starting from
+    clamped uniform knots with n_init control points per axis, fit, measure
+    the error of every sample relative to the data range, and halve every
+    knot span (per axis) whose largest error exceeds e_max and whose two
+    halves would each hold a sample parameter; refit; stop when no span is
+    halved or after max_iter fits.  Returns (knots, P, history), history
+    holding per fit the control-point counts and the largest error."""
+    F = np.asarray(F, dtype=np.float64)
+    rng = float(F.max() - F.min()) or 1.0
+    knots = []
+    for a in range(3):
+        p, n = int(degree[a]), int(n_init[a])
+        inner = np.arange(1, n - p) / (n - p)
+        knots.append(np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)]))
+    history = []
+    for _ in range(max_iter):
+        n_ctrl = [len(knots[a]) - degree[a] - 1 for a in range(3)]
+        fitted = [k.copy() for k in knots]
+        P = fit_grid(F, axis_u, degree, knots, n_ctrl)
+        err = np.abs(reconstruct_grid(P, axis_u, degree, knots) - F) / rng
+        history.append((list(n_ctrl), float(err.max())))
+        E = span_errors(err, axis_u, degree, knots)
+        grown = False
+        for a in range(3):
+            p = int(degree[a])
+            T = knots[a]
+            u = np.asarray(axis_u[a], np.float64)
+            new = []
+            for j, e in enumerate(E[a]):
+                t0, t1 = T[p + j], T[p + j + 1]
+                mid = 0.5 * (t0 + t1)
+                if e > e_max and np.any((u >= t0) & (u < mid)) and np.any((u >= mid) & (u <= t1)):
+                    new.append(mid)
+            if new:
+                knots[a] = np.sort(np.concatenate([T, new]))
+                grown = True
+        if not grown:
+            break
+    return fitted, P, history

@@ -141,3 +141,61 @@ def test_collocation_rows_partition_unity_and_band():
         np.testing.assert_allclose(B.sum(axis=1), 1.0, rtol=0, atol=1e-14)
         assert np.all(B >= 0.0)
         assert np.all((B != 0.0).sum(axis=1) <= p + 1)
+
+
+# ---------------------------------------------------------------- knot insertion (Fig. 1)
+def _c1_samples(N=40):
+    field = synth.field_c1(1)
+    xs = np.arange(N, dtype=np.float64) / (N - 1)
+    return field.value_separable(xs, xs, xs), [xs] * 3
+
+
+def test_span_errors_match_a_scalar_scan():
+    rng = np.random.default_rng(80)
+    p, n, res = 3, (7, 9, 6), (23, 17, 19)
+    knots = [nonuniform_knots(n[a], p, rng) for a in range(3)]
+    axis_u = [grid_params(res[a], rng, "random") for a in range(3)]
+    err = rng.random(res)
+    got = oe.span_errors(err, axis_u, [p] * 3, knots)
+    for a in range(3):
+        want = np.zeros(n[a] - p)
+        for idx in np.ndindex(*res):
+            u = axis_u[a][idx[a]]
+            s = max(i for i in range(p, n[a]) if knots[a][i] <= u) - p   # the span rule
+            want[s] = max(want[s], err[idx])
+        np.testing.assert_array_equal(got[a], want)
+
+
+def test_adaptive_fit_reaches_the_bound_with_nested_knots():
+    F, axis_u = _c1_samples()
+    e_max = 2e-3
+    prev = None
+    for it in range(1, 6):
+        knots, P, hist = oe.fit_adaptive(F, axis_u, [3] * 3, [6] * 3, e_max, max_iter=it)
+        if prev is not None:
+            for a in range(3):                               # knot vectors only grow
+                assert set(np.round(prev[a], 15)) <= set(np.round(knots[a], 15))
+        prev = knots
+    assert len(hist) < 5 and hist[-1][1] <= e_max           # stopped because the bound holds
+    assert all(h[1] > e_max for h in hist[:-1])
+    # the returned control points are the fixed-knot fit on the final knots
+    n = [len(knots[a]) - 4 for a in range(3)]
+    np.testing.assert_allclose(P, oe.fit_grid(F, axis_u, [3] * 3, knots, n), rtol=0, atol=1e-12)
+
+
+def test_adaptive_residual_never_grows_and_loose_bound_keeps_initial_knots():
+    """Knot insertion nests the spline spaces, so the least-squares residual
+    (sum of squares) cannot grow from one fit to the next."""
+    x = np.arange(33, dtype=np.float64) / 32
+    g = np.meshgrid(x, x, x, indexing="ij")
+    F = np.abs(g[0] - 0.3) ** 3 + 0.5 * np.abs(g[1] - 0.71) ** 2 * g[2]
+    axis_u = [x] * 3
+    rss = []
+    for it in range(1, 5):
+        knots, P, hist = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 1e-6, max_iter=it)
+        R = oe.reconstruct_grid(P, axis_u, [3] * 3, knots) - F
+        rss.append(float((R * R).sum()))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(rss, rss[1:]))
+    assert rss[-1] < 0.05 * rss[0]
+    knots, P, hist = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 10.0)
+    assert len(hist) == 1 and all(len(k) == 5 + 4 for k in knots)
