@@ -396,6 +396,45 @@ mfa_status mfa_encode_plan(const int32_t res[3], const double* const axis_u[3],
 mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctrl[3], const float* values,
                             double* ctrl, void* work, int64_t work_bytes, void* stream);
 
+/* Encoding with knot insertion (Fig. 1: fit, measure the error, add knots
+ * where it is too large, refit).  Starting from clamped uniform knots with
+ * n_init control points per axis, each pass makes the fixed-knot fit above
+ * on the device, reconstructs the spline at every sample (three more mode
+ * products with the B_a), and takes every sample's error relative to the
+ * data range, |f - F| / (max F - min F) (1 when the range is 0).  Per axis,
+ * a knot span [t_j, t_j+1) (span rule of mfa_model_create) gets the largest
+ * error over the samples whose axis-a parameter falls in it; a span whose
+ * error exceeds e_max is halved (a knot at its midpoint) when both halves
+ * hold a sample parameter.  When more spans qualify than max_ctrl[a] - n_a
+ * leaves room for, the ones of largest error are halved (ties: lower span
+ * first).  The loop ends after a pass that halves nothing or after
+ * max_fits passes; the result is the last pass's fit and knots.
+ *  res, axis_u, values, degree : as in mfa_encode_grid.
+ *  n_init   : starting control points per axis, degree + 1 <= n_init <= max_ctrl.
+ *  max_ctrl : largest control-point count per axis, max_ctrl[a] <= res[a];
+ *             sizes the workspace and ctrl.
+ *  e_max    : error bound, finite and > 0.  max_fits >= 1.
+ *  knots_out: host FP64 out, knots_out[a] with room for max_ctrl[a] + degree[a] + 1
+ *             values; n_out : host out, the final control-point counts.
+ *  ctrl     : device FP64 out, room for ctrl_capacity >= the product of
+ *             max_ctrl; holds [n_out0][n_out1][n_out2] (axis 2 fastest).
+ *  history  : host FP64 out (NULL to skip), max_fits rows of 4 values, per
+ *             pass n0, n1, n2 and the largest relative error of that fit;
+ *             n_fits : host out, the passes made.
+ *  work     : device scratch of mfa_encode_adaptive_workspace(res, max_ctrl)
+ *             bytes, caller-owned.
+ * res0 * res1 is at most 65535 * 512.  Errors: as mfa_encode_grid; every
+ * pass waits for its work on the stream (the knots are chosen on the host),
+ * so the call returns with ctrl final.                                     */
+mfa_status mfa_encode_adaptive_workspace(const int32_t res[3], const int32_t max_ctrl[3],
+                                         int64_t* bytes);
+mfa_status mfa_encode_adaptive(const int32_t res[3], const double* const axis_u[3],
+                               const float* values, const int32_t degree[3],
+                               const int32_t n_init[3], const int32_t max_ctrl[3], double e_max,
+                               int32_t max_fits, double* const knots_out[3], int32_t n_out[3],
+                               double* ctrl, int64_t ctrl_capacity, double* history,
+                               int32_t* n_fits, void* work, int64_t work_bytes, void* stream);
+
 /* Host-only helpers (no device work): the storage rounding and the default
  * knot vector the library uses, exported so they can be checked on a CPU.
  *  mfa_quantize : n FP64 values -> stored bits of dtype (MFA_F32: uint32

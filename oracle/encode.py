@@ -87,14 +87,20 @@ def span_errors(err: np.ndarray, axis_u, degree, knots):
     return out
 
 
-def fit_adaptive(F: np.ndarray, axis_u, degree, n_init, e_max: float, max_iter: int = 10):
+def fit_adaptive(F: np.ndarray, axis_u, degree, n_init, e_max: float, max_iter: int = 10,
+                 max_ctrl=None):
     """Fixed-knot fits with knot insertion (paper Fig. 1): starting from
     clamped uniform knots with n_init control points per axis, fit, measure
     the error of every sample relative to the data range, and halve every
     knot span (per axis) whose largest error exceeds e_max and whose two
     halves would each hold a sample parameter; refit; stop when no span is
     halved or after max_iter fits.  Returns (knots, P, history), history
-    holding per fit the control-point counts and the largest error."""
+    holding per fit the control-point counts and the largest error.
+
+    max_ctrl (a per-axis cap on the control-point count; the paper sets
+    none, a storage budget is an implementation's choice): when more spans
+    qualify than the cap leaves room for, the spans of largest error are
+    halved, ties going to the lower span."""
     F = np.asarray(F, dtype=np.float64)
     rng = float(F.max() - F.min()) or 1.0
     knots = []
@@ -120,7 +126,12 @@ def fit_adaptive(F: np.ndarray, axis_u, degree, n_init, e_max: float, max_iter: 
                 t0, t1 = T[p + j], T[p + j + 1]
                 mid = 0.5 * (t0 + t1)
                 if e > e_max and np.any((u >= t0) & (u < mid)) and np.any((u >= mid) & (u <= t1)):
-                    new.append(mid)
+                    new.append((e, mid))
+            if max_ctrl is not None:
+                room = int(max_ctrl[a]) - n_ctrl[a]
+                if len(new) > room:
+                    new = sorted(new, key=lambda c: -c[0])[:room]      # stable: ties keep span order
+            new = [m for _, m in new]
             if new:
                 knots[a] = np.sort(np.concatenate([T, new]))
                 grown = True

@@ -280,6 +280,56 @@ def encode_grid(values, axis_u: Sequence, degree: Sequence[int], n_ctrl: Sequenc
     return out
 
 
+def encode_adaptive_workspace_bytes(res: Sequence[int], max_ctrl: Sequence[int]) -> int:
+    """Device scratch bytes that encode_adaptive needs for these sizes."""
+    out = C.c_int64()
+    L.check(L.lib().mfa_encode_adaptive_workspace((C.c_int32 * 3)(*[int(v) for v in res]),
+                                                  (C.c_int32 * 3)(*[int(v) for v in max_ctrl]),
+                                                  C.byref(out)))
+    return int(out.value)
+
+
+def encode_adaptive(values, axis_u: Sequence, degree: Sequence[int], n_init: Sequence[int],
+                    e_max: float, max_ctrl: Optional[Sequence[int]] = None, max_fits: int = 10,
+                    work=None, stream=None):
+    """Encoding with knot insertion (mfa_encode_adaptive) of the CUDA float32
+    samples values (r0, r1, r2) at the host float64 parameter tables axis_u.
+    Returns (knots: three float64 arrays, ctrl: FP64 CUDA tensor (n0, n1,
+    n2), history: list of ((n0, n1, n2), largest relative error) per fit).
+    max_ctrl defaults to res."""
+    torch = _torch()
+    if values.dim() != 3 or len(axis_u) != 3 or len(degree) != 3 or len(n_init) != 3:
+        raise ValueError("values must be (r0, r1, r2), with three axes of parameters")
+    res = [int(v) for v in values.shape]
+    mc = [int(v) for v in (max_ctrl if max_ctrl is not None else res)]
+    tabs = [np.ascontiguousarray(np.asarray(u, dtype=np.float64)) for u in axis_u]
+    for a in range(3):
+        if tabs[a].shape != (res[a],):
+            raise ValueError(f"axis_u[{a}] must hold {res[a]} parameters")
+    pv = _dev_ptr(values, torch.float32, tuple(res), "values")
+    nb = encode_adaptive_workspace_bytes(res, mc)
+    if work is None:
+        work = torch.empty((nb,), dtype=torch.uint8, device=values.device)
+    pw = _dev_ptr(work, torch.uint8, name="work")
+    cap = mc[0] * mc[1] * mc[2]
+    ctrl = torch.empty((cap,), dtype=torch.float64, device=values.device)
+    kout = [np.zeros(mc[a] + int(degree[a]) + 1) for a in range(3)]
+    hist = np.zeros((max(int(max_fits), 1), 4))
+    n_out = (C.c_int32 * 3)()
+    n_fits = C.c_int32()
+    L.check(L.lib().mfa_encode_adaptive(
+        (C.c_int32 * 3)(*res), (C.c_void_p * 3)(*[t.ctypes.data for t in tabs]), pv,
+        (C.c_int32 * 3)(*[int(v) for v in degree]), (C.c_int32 * 3)(*[int(v) for v in n_init]),
+        (C.c_int32 * 3)(*mc), float(e_max), int(max_fits),
+        (C.c_void_p * 3)(*[k.ctypes.data for k in kout]), n_out,
+        C.c_void_p(ctrl.data_ptr()), cap, hist.ctypes.data, C.byref(n_fits), pw,
+        int(work.numel()), _stream_ptr(stream)))
+    n = [int(n_out[a]) for a in range(3)]
+    knots = [kout[a][:n[a] + int(degree[a]) + 1].copy() for a in range(3)]
+    history = [((int(h[0]), int(h[1]), int(h[2])), float(h[3])) for h in hist[:n_fits.value]]
+    return knots, ctrl[:n[0] * n[1] * n[2]].view(*n), history
+
+
 class EncodePlan:
     """mfa_encode_plan for one grid shape (res samples -> n_ctrl control
     points, degrees, knots, parameter tables), holding its CUDA workspace;

@@ -110,6 +110,14 @@ SIGNATURES = {
                                   C.c_void_p, C.c_int64, C.c_void_p]),
     "mfa_encode_apply": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mfa_encode_adaptive_workspace": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                                C.POINTER(C.c_int64)]),
+    "mfa_encode_adaptive": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_void_p), C.c_void_p,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.c_double, C.c_int32,
+                                      C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p,
+                                      C.c_int64, C.c_void_p]),
     "mfa_quantize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     "mfa_default_knots": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
     "mfa_last_error": (C.c_char_p, []),

@@ -169,3 +169,44 @@ def test_encode_rejects_bad_arguments_before_device_work():
     k[0] = k[0][::-1].copy()                                            # decreasing knots
     assert call(knots=k)[0] == L.MFA_E_ARG
     assert lib.mfa_encode_grid(None, None, None, None, None, None, None, None, 0, None) == L.MFA_E_ARG
+
+
+def test_encode_adaptive_workspace_size_and_rejections():
+    lib = L.lib()
+    nb = C.c_int64()
+    (N0, N1, N2), (m0, m1, m2) = (10, 12, 700), (5, 6, 7)
+    assert lib.mfa_encode_adaptive_workspace(_i3(N0, N1, N2), _i3(m0, m1, m2),
+                                             C.byref(nb)) == L.MFA_OK
+    al = lambda v: (v + 255) // 256 * 256
+    want = 2 * sum(al(8 * n * r) for n, r in ((m0, N0), (m1, N1), (m2, N2)))
+    want += al(8 * m0 * N1 * N2) + al(8 * N2 * m0 * m1) + al(8 * N0 * m1 * m2) \
+        + al(8 * m2 * N0 * N1) + al(8 * N0 * N1 * N2) + al(8 * N0 * N1) \
+        + al(8 * ((N0 * N1 + 511) // 512) * N2) + al(8 * 1024)
+    assert nb.value == want
+    assert lib.mfa_encode_adaptive_workspace(_i3(4, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_E_ARG
+
+    res, tabs = (10, 9, 8), [np.linspace(0.0, 1.0, r) for r in (10, 9, 8)]
+    fake = C.c_void_p(0x1000)
+    kout = [np.zeros(20) for _ in range(3)]
+
+    def call(degree=(3, 3, 3), n_init=(4, 4, 5), max_ctrl=(8, 8, 8), e_max=1e-3, max_fits=5,
+             cap=512, work_bytes=1 << 30, tabs=tabs):
+        st = lib.mfa_encode_adaptive(
+            _i3(*res), (C.c_void_p * 3)(*[t.ctypes.data for t in tabs]), fake, _i3(*degree),
+            _i3(*n_init), _i3(*max_ctrl), e_max, max_fits,
+            (C.c_void_p * 3)(*[k.ctypes.data for k in kout]), (C.c_int32 * 3)(), fake, cap, None,
+            C.byref(C.c_int32()), fake, work_bytes, None)
+        return st, lib.mfa_last_error().decode()
+
+    assert call(n_init=(3, 4, 5))[0] == L.MFA_E_ARG                     # n_init < p + 1
+    assert call(max_ctrl=(8, 8, 9))[0] == L.MFA_E_ARG                   # max_ctrl > res
+    assert call(n_init=(4, 9, 5), max_ctrl=(8, 8, 8))[0] == L.MFA_E_ARG  # n_init > max_ctrl
+    assert call(e_max=0.0)[0] == L.MFA_E_ARG
+    assert call(e_max=float("nan"))[0] == L.MFA_E_ARG
+    assert call(max_fits=0)[0] == L.MFA_E_ARG
+    assert call(cap=511)[0] == L.MFA_E_ARG
+    assert call(work_bytes=16)[0] == L.MFA_E_ARG
+    bad = [t.copy() for t in tabs]
+    bad[0][2] = -0.25
+    st, msg = call(tabs=bad)
+    assert st == L.MFA_E_ARG and "outside [0, 1]" in msg

@@ -123,3 +123,68 @@ def test_encode_plan_serves_several_blocks(mfa, dev):
     for b, o in zip(blocks, outs):
         ref = oe.fit_grid(b.astype(np.float64), axis_u, (3, 3, 3), kn, n_ctrl)
         assert np.abs(o.cpu().numpy() - ref).max() <= REL_ENC * np.abs(b).max()
+
+
+# ---------------------------------------------------------------- knot insertion (Fig. 1)
+def oracle_adaptive_with_margin(F64, axis_u, degree, n_init, e_max, max_iter, max_ctrl, margin=1e-6):
+    """The oracle's adaptive fit, checking that no span error of any pass
+    lies within a relative margin of e_max (there the two sides' FP64
+    rounding could take different split decisions)."""
+    ref = oe.fit_adaptive(F64, axis_u, degree, n_init, e_max, max_iter=max_iter, max_ctrl=max_ctrl)
+    rng = float(F64.max() - F64.min()) or 1.0
+    for k in range(1, len(ref[2]) + 1):
+        kn, P, _ = oe.fit_adaptive(F64, axis_u, degree, n_init, e_max, max_iter=k, max_ctrl=max_ctrl)
+        err = np.abs(oe.reconstruct_grid(P, axis_u, degree, kn) - F64) / rng
+        for e in oe.span_errors(err, axis_u, degree, kn):
+            assert np.all(np.abs(e - e_max) > margin * e_max), "span error at the bound"
+    return ref
+
+
+def run_adaptive(mfa, dev, F32, axis_u, degree, n_init, e_max, max_fits, max_ctrl=None):
+    import torch
+    F64 = F32.astype(np.float64)
+    knots, P, hist = mfa.encode_adaptive(torch.as_tensor(F32).to(dev), axis_u, degree, n_init,
+                                         e_max, max_ctrl=max_ctrl, max_fits=max_fits)
+    rk, rP, rh = oracle_adaptive_with_margin(F64, axis_u, degree, n_init, e_max, max_fits, max_ctrl)
+    for a in range(3):
+        np.testing.assert_array_equal(knots[a], rk[a])                  # same split decisions
+    assert [h[0] for h in hist] == [tuple(h[0]) for h in rh]
+    for (_, e), (_, re) in zip(hist, rh):
+        assert abs(e - re) <= 1e-9 * max(re, 1e-12)
+    got = P.cpu().numpy()
+    assert got.shape == rP.shape
+    assert np.abs(got - rP).max() <= REL_ENC * np.abs(F32).max()
+    return knots, hist
+
+
+def test_encode_adaptive_gaussian_field_reaches_the_bound(mfa, dev):
+    field = synth.field_c1(1)
+    xs = np.arange(48, dtype=np.float64) / 47
+    F = field.value_separable(xs, xs, xs).astype(np.float32)
+    announce("adaptive encode 48^3 e_max=2e-3")
+    knots, hist = run_adaptive(mfa, dev, F, [xs] * 3, (3, 3, 3), (6, 6, 6), 2e-3, 10)
+    assert len(hist) >= 2 and hist[-1][1] <= 2e-3
+
+
+def test_encode_adaptive_ragged_unsorted_mixed_degrees_with_cap(mfa, dev):
+    rng = np.random.default_rng(90)
+    res, degree = (45, 38, 53), (2, 3, 4)
+    x = [np.linspace(0.0, 1.0, r) for r in res]
+    g = np.meshgrid(*x, indexing="ij")
+    F = (np.abs(g[0] - 0.37) ** 2.5 + np.sin(6.0 * g[1]) * g[2] + 0.3 * np.exp(-40 * (g[2] - 0.6) ** 2))
+    perm = [rng.permutation(r) for r in res]
+    F = F[np.ix_(*perm)].astype(np.float32)                          # samples in shuffled order
+    axis_u = [x[a][perm[a]] for a in range(3)]
+    announce("adaptive encode ragged 45x38x53, capped")
+    knots, hist = run_adaptive(mfa, dev, F, axis_u, degree, (4, 5, 6), 5e-4, 6, max_ctrl=(12, 15, 11))
+    assert max(h[0][0] for h in hist) <= 12 and max(h[0][2] for h in hist) <= 11
+
+
+def test_encode_adaptive_loose_bound_is_one_fixed_knot_fit(mfa, dev):
+    rng = np.random.default_rng(91)
+    res = (20, 24, 28)
+    axis_u = [np.linspace(0.0, 1.0, r) for r in res]
+    F = rng.standard_normal(res).astype(np.float32)
+    announce("adaptive encode, loose bound")
+    knots, hist = run_adaptive(mfa, dev, F, axis_u, (3, 3, 3), (7, 8, 9), 10.0, 4)
+    assert len(hist) == 1 and hist[0][0] == (7, 8, 9)

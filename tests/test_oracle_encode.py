@@ -199,3 +199,31 @@ def test_adaptive_residual_never_grows_and_loose_bound_keeps_initial_knots():
     assert rss[-1] < 0.05 * rss[0]
     knots, P, hist = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 10.0)
     assert len(hist) == 1 and all(len(k) == 5 + 4 for k in knots)
+
+
+def test_adaptive_cap_keeps_the_largest_errors():
+    """With a cap on the control points, the spans that are halved are the
+    ones of largest error; a cap never reached changes nothing."""
+    F, axis_u = _c1_samples(32)
+    free, Pf, hf = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 1e-4, max_iter=2)
+    big, Pb, hb = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 1e-4, max_iter=2, max_ctrl=[32] * 3)
+    for a in range(3):
+        np.testing.assert_array_equal(free[a], big[a])
+    k1, _, h1 = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 1e-4, max_iter=1)
+    capped, _, hc = oe.fit_adaptive(F, axis_u, [3] * 3, [5] * 3, 1e-4, max_iter=2, max_ctrl=[6, 7, 5])
+    assert [len(capped[a]) - 4 for a in range(3)] == [6, 7, 5]
+    # which spans: recompute the span errors of the first fit by a scalar scan
+    n1 = [len(k1[a]) - 4 for a in range(3)]
+    P1 = oe.fit_grid(F, axis_u, [3] * 3, k1, n1)
+    err = np.abs(oe.reconstruct_grid(P1, axis_u, [3] * 3, k1) - F) / (F.max() - F.min())
+    for a, extra in ((0, 1), (1, 2)):
+        other = tuple(b for b in range(3) if b != a)
+        marg = err.max(axis=other)
+        span_err = {}
+        for i, u in enumerate(axis_u[a]):
+            j = min(int(np.searchsorted(k1[a], u, side="right")) - 1, n1[a] - 1) - 3
+            span_err[j] = max(span_err.get(j, 0.0), marg[i])
+        order = sorted(span_err, key=lambda j: (-span_err[j], j))[:extra]
+        want = sorted([0.5 * (k1[a][3 + j] + k1[a][4 + j]) for j in order])
+        added = sorted(set(np.round(capped[a], 14)) - set(np.round(k1[a], 14)))
+        np.testing.assert_allclose(added, want, atol=1e-14)
