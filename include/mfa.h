@@ -400,8 +400,9 @@ mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctrl[3], const
  * where it is too large, refit).  Starting from clamped uniform knots with
  * n_init control points per axis, each pass makes the fixed-knot fit above
  * on the device, reconstructs the spline at every sample (three more mode
- * products with the B_a), and takes every sample's error relative to the
- * data range, |f - F| / (max F - min F) (1 when the range is 0).  Per axis,
+ * products with the B_a, the last one taking the errors in its epilogue
+ * instead of storing the values), and takes every sample's error relative
+ * to the data range, |f - F| / (max F - min F) (range 1 when it is 0).  Per axis,
  * a knot span [t_j, t_j+1) (span rule of mfa_model_create) gets the largest
  * error over the samples whose axis-a parameter falls in it; a span whose
  * error exceeds e_max is halved (a knot at its midpoint) when both halves
@@ -423,7 +424,8 @@ mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctrl[3], const
  *             n_fits : host out, the passes made.
  *  work     : device scratch of mfa_encode_adaptive_workspace(res, max_ctrl)
  *             bytes, caller-owned.
- * res0 * res1 is at most 65535 * 512.  Errors: as mfa_encode_grid; every
+ * res0 * res1 is at most 65535 * 2048.  Errors: as mfa_encode_grid (also
+ * from a later pass whose knots leave a basis function without samples); every
  * pass waits for its work on the stream (the knots are chosen on the host),
  * so the call returns with ctrl final.                                     */
 mfa_status mfa_encode_adaptive_workspace(const int32_t res[3], const int32_t max_ctrl[3],

@@ -15,6 +15,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "mfa_model.h"
@@ -45,7 +48,8 @@ constexpr int kGemmBlock = 256;   // 4 waves, each computing its own C tile
 constexpr int kGemmTile = 32;     // C tile per wave: 2 x 2 MFMA blocks of 16 x 16
 
 // One wave per 32 x 32 tile of C; tiles are numbered with the M tile
-// fastest, so the waves of a workgroup share the columns of B they read.
+// fastest, so the waves of a workgroup share the columns of B they read
+// (with ERR below, N fastest: there the waves share rows of A).
 // Per step of 4 along K each lane supplies A(m0 + 16t + lane % 16, k) and
 // B(k, n0 + 16u + lane % 16) with k = k0 + lane / 16, and the MFMA leaves
 // element (i, j) of a 16 x 16 block in lane j + 16 * (i % 4), register
@@ -55,17 +59,40 @@ constexpr int kGemmTile = 32;     // C tile per wave: 2 x 2 MFMA blocks of 16 x 
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T*;   // global-memory pointer
 
+// With ERR the GEMM is the last product of a reconstruction: instead of
+// storing C it takes every element's relative error against the samples,
+// |C(m, n) - F(m, n)| * inv_range (F(m, n) at f[m * ldf + n]), and stores
+// per tile the largest error of each of its rows, rowpart[jn * M + m], and
+// of each of its columns, colpart[im * N + n] (jn, im: the tile's column
+// and row index); out-of-range elements count as 0.
+struct ErrOut {
+  const float* f;
+  int64_t ldf;
+  double inv_range;
+  double* rowpart;
+  double* colpart;
+};
+
 constexpr int kGemmUnroll = 4;    // K steps whose loads are issued together
 
-template <typename TB, bool TRANS_A>
+template <typename TB, bool TRANS_A, bool ERR>
 __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restrict__ gA,
                                                          const TB* __restrict__ gB,
-                                                         double* __restrict__ gC, GemmArgs g) {
+                                                         double* __restrict__ gC, GemmArgs g,
+                                                         ErrOut eo) {
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * (kGemmBlock / 64) + (threadIdx.x >> 6);
+  // Workgroups are dealt to the 8 XCDs in turn (physical block x to XCD
+  // x % 8); renumber them so that each XCD runs a contiguous range of
+  // logical blocks, whose tiles share operand strips in that XCD's L2.
+  const int64_t nb = gridDim.x, xq = nb / 8, xr = nb % 8, xcd = blockIdx.x % 8, xi = blockIdx.x / 8;
+  const int64_t lb = xcd < xr ? xcd * (xq + 1) + xi : xr * (xq + 1) + (xcd - xr) * xq + xi;
+  const int64_t w = lb * (kGemmBlock / 64) + (threadIdx.x >> 6);
   const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + kGemmTile - 1) / kGemmTile;
   if (w >= tm * tn * g.batch) return;                  // whole wave
-  const int64_t im = w % tm, rest = w / tm, jn = rest % tn, b = rest / tn;
+  // tiles numbered with M fastest (the waves of a run share B columns), or
+  // N fastest for the error product (few, narrow B columns; tall A)
+  const int64_t im = ERR ? (w / tn) % tm : w % tm, jn = ERR ? w % tn : (w / tm) % tn;
+  const int64_t b = w / (tm * tn);
   const int c16 = lane & 15, q = lane >> 4;
   const int64_t m0 = im * kGemmTile, n0 = jn * kGemmTile;
   const double* A0 = gA + b * g.sA;
@@ -135,27 +162,67 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
     }
     mma(a, bv);
   }
-  double* __restrict__ C = gC + b * g.sC;
+  if constexpr (ERR) {
+    gptr<float> F = (gptr<float>)eo.f;
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
+          acc[t][u][r] = (m < g.M && n < g.N)
+                             ? fabs(acc[t][u][r] - (double)F[m * eo.ldf + n]) * eo.inv_range
+                             : 0.0;
+        }
+    // rows: the 16 lanes of one q hold a row's 32 columns (two per lane)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
-        if (m < g.M && n < g.N) C[g.c_trans ? n * g.ldc + m : m * g.ldc + n] = acc[t][u][r];
+        double v = fmax(acc[t][0][r], acc[t][1][r]);
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+        const int64_t m = m0 + 16 * t + q + 4 * r;
+        if (c16 == 0 && m < g.M) eo.rowpart[jn * g.M + m] = v;
       }
+    // columns: a lane holds 8 rows of a column, the four q groups the rest
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v = fmax(v, acc[t][u][r]);
+      v = fmax(v, __shfl_xor(v, 16));
+      v = fmax(v, __shfl_xor(v, 32));
+      const int64_t n = n0 + 16 * u + c16;
+      if (q == 0 && n < g.N) eo.colpart[im * g.N + n] = v;
+    }
+  } else {
+    double* __restrict__ C = gC + b * g.sC;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
+          if (m < g.M && n < g.N) C[g.c_trans ? n * g.ldc + m : m * g.ldc + n] = acc[t][u][r];
+        }
+  }
 }
 
-template <typename TB, bool TRANS_A>
-hipError_t gemm(const GemmArgs& g, hipStream_t st) {
+template <typename TB, bool TRANS_A, bool ERR = false>
+hipError_t gemm(const GemmArgs& g, hipStream_t st, const ErrOut& eo = ErrOut{}) {
   const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + kGemmTile - 1) / kGemmTile) *
                         g.batch;
   const int64_t blocks = (tiles + kGemmBlock / 64 - 1) / (kGemmBlock / 64);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st, g.A,
-                     static_cast<const TB*>(g.B), g.C, g);
+  if (ERR && g.batch != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A, ERR>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st,
+                     g.A, static_cast<const TB*>(g.B), g.C, g, eo);
   return hipGetLastError();
 }
 
@@ -187,8 +254,10 @@ void basis_values(const double* T, int p, int s, double u, double* N) {
 }
 
 // Q = (B^T B)^-1 B^T, stored transposed (N x n row-major), for the collocation matrix B of one
-// axis: the Gram matrix is banded (bandwidth p), factorised as L L^T, and
-// each column B^T e_i (non-zero on rows s_i - p .. s_i) is solved for.
+// axis: the Gram matrix G = B^T B is banded (bandwidth p) and factorised as
+// L L^T; its inverse Z is formed column by column (two banded triangular
+// solves per unit vector), and row i of Q is the combination of the p + 1
+// rows of Z picked by the non-zeros of row i of B (Z is symmetric).
 mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N, int axis,
                           std::vector<double>& Q, std::vector<double>* Bt = nullptr) {
   const int w = p + 1;
@@ -228,14 +297,13 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
         L[(size_t)j * w] = std::sqrt(v);
       }
     }
-  Q.assign((size_t)n * N, 0.0);
+  std::vector<double> Z((size_t)n * n);
   std::vector<double> y(n);
-  for (int i = 0; i < N; ++i) {
-    const int j0 = s[i] - p;
+  for (int c = 0; c < n; ++c) {
     std::fill(y.begin(), y.end(), 0.0);
-    for (int j = j0; j < n; ++j) {                       // L y = B^T e_i
-      double v = (j <= s[i]) ? Bv[(size_t)i * w + (j - j0)] : 0.0;
-      for (int m = std::max(j0, j - p); m < j; ++m) v -= L[(size_t)j * w + (j - m)] * y[m];
+    for (int j = c; j < n; ++j) {                        // L y = e_c (y[j] = 0 for j < c)
+      double v = j == c ? 1.0 : 0.0;
+      for (int m = std::max(c, j - p); m < j; ++m) v -= L[(size_t)j * w + (j - m)] * y[m];
       y[j] = v / L[(size_t)j * w];
     }
     for (int j = n - 1; j >= 0; --j) {                   // L^T x = y (in place)
@@ -243,7 +311,16 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
       for (int m = j + 1; m <= std::min(n - 1, j + p); ++m) v -= L[(size_t)m * w + (m - j)] * y[m];
       y[j] = v / L[(size_t)j * w];
     }
-    for (int j = 0; j < n; ++j) Q[(size_t)i * n + j] = y[j];
+    std::copy(y.begin(), y.end(), Z.begin() + (size_t)c * n);
+  }
+  Q.assign((size_t)n * N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double* q = &Q[(size_t)i * n];
+    for (int r = 0; r <= p; ++r) {
+      const double b = Bv[(size_t)i * w + r];
+      const double* z = &Z[(size_t)(s[i] - p + r) * n];
+      for (int j = 0; j < n; ++j) q[j] += b * z[j];
+    }
   }
   return MFA_OK;
 }
@@ -269,52 +346,66 @@ hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, 
 
 // The spline on the sample grid, Fh = P x_0 B0 x_1 B1 x_2 B2, with the
 // collocation tables bt[a] transposed (n_a x N_a); R1 is written transposed
-// ([n2][N0 * N1]) for the same reason as Y1 above.
-hipError_t run_recon(const int64_t N[3], const int64_t n[3], const double* ctrl,
-                     const double* const bt[3], double* r0, double* r1, double* fh, hipStream_t hs) {
+// ([n2][N0 * N1]) for the same reason as Y1 above.  Fh itself is never
+// stored: the last product leaves the per-tile row and column maxima of the
+// relative error (ErrOut), with rows m = i0 * N1 + i1 and columns i2.
+hipError_t run_recon_err(const int64_t N[3], const int64_t n[3], const double* ctrl,
+                         const double* const bt[3], double* r0, double* r1, const ErrOut& eo,
+                         hipStream_t hs) {
   GemmArgs g0{N[0], n[1] * n[2], n[0], 1, bt[0], N[0], 0, ctrl, n[1] * n[2], 0, r0, n[1] * n[2], 0, 0};
   GemmArgs g1{N[1], n[2], n[1], N[0], bt[1], N[1], 0, r0, n[2], n[1] * n[2], r1, N[0] * N[1], N[1], 1};
-  GemmArgs g2{N[0] * N[1], N[2], n[2], 1, r1, N[0] * N[1], 0, bt[2], N[2], 0, fh, N[2], 0, 0};
+  GemmArgs g2{N[0] * N[1], N[2], n[2], 1, r1, N[0] * N[1], 0, bt[2], N[2], 0, nullptr, N[2], 0, 0};
   hipError_t e = gemm<double, true>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
-  if (e == hipSuccess) e = gemm<double, true>(g2, hs);
+  if (e == hipSuccess) e = gemm<double, true, true>(g2, hs, eo);
   return e;
 }
 
 // ------------------------------------------------------------------ errors of a fit
-constexpr int kErrRows = 512;     // rows per chunk of the column pass
-constexpr int kMinMaxBlocks = 1024;
+constexpr int kRedRows = 64;        // rows per workgroup of max_lead_k
+constexpr int kMinMaxBlocks = 2048;
 
-// Largest relative error |Fh - F| * inv_range of each grid row (i0, i1):
-// one wave per row, lanes striding along axis 2.
-__global__ __launch_bounds__(256) void err_rows_k(const double* __restrict__ fh,
-                                                  const float* __restrict__ f, int64_t rows,
-                                                  int64_t n2, double inv_range,
-                                                  double* __restrict__ rowmax) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
-  const int lane = threadIdx.x & 63;
+// dst[y * C + c] = max over rows [y * kRedRows, (y + 1) * kRedRows) of
+// src[r * C + c] (values >= 0): one thread per column, coalesced.
+__global__ __launch_bounds__(256) void max_lead_k(const double* __restrict__ src, int64_t R,
+                                                  int64_t C, double* __restrict__ dst) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= C) return;
+  const int64_t r0 = (int64_t)blockIdx.y * kRedRows, r1 = min(r0 + (int64_t)kRedRows, R);
   double m = 0.0;
-  for (int64_t c = lane; c < n2; c += 64)
-    m = fmax(m, fabs(fh[row * n2 + c] - (double)f[row * n2 + c]) * inv_range);
-#pragma unroll
-  for (int o = 32; o; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  if (lane == 0) rowmax[row] = m;
+#pragma unroll 16
+  for (int64_t r = r0; r < r1; ++r) m = fmax(m, src[r * C + c]);   // loads issued 16 at a time
+  dst[blockIdx.y * C + c] = m;
 }
 
-// Largest relative error of each column i2 over chunks of kErrRows rows:
-// colpart[chunk * n2 + c]; one thread per column of a chunk.
-__global__ __launch_bounds__(256) void err_cols_k(const double* __restrict__ fh,
-                                                  const float* __restrict__ f, int64_t rows,
-                                                  int64_t n2, double inv_range,
-                                                  double* __restrict__ colpart) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= n2) return;
-  const int64_t r0 = (int64_t)blockIdx.y * kErrRows, r1 = min(r0 + (int64_t)kErrRows, rows);
+// dst[r] = max over c of src[r * C + c]: one wave per row.
+__global__ __launch_bounds__(256) void max_row_k(const double* __restrict__ src, int64_t R, int64_t C,
+                                                 double* __restrict__ dst) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const int lane = threadIdx.x & 63;
   double m = 0.0;
-  for (int64_t r = r0; r < r1; ++r)
-    m = fmax(m, fabs(fh[r * n2 + c] - (double)f[r * n2 + c]) * inv_range);
-  colpart[blockIdx.y * n2 + c] = m;
+  for (int64_t c = lane; c < C; c += 64) m = fmax(m, src[row * C + c]);
+#pragma unroll
+  for (int o = 32; o; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) dst[row] = m;
+}
+
+// dst[c] = max over the R rows of src (R x C), by rounds of max_lead_k that
+// shrink R by kRedRows through the scratch buffers t0 / t1 (each of
+// ceil(R / kRedRows) * C values).
+hipError_t max_lead(const double* src, int64_t R, int64_t C, double* t0, double* t1, double* dst,
+                    hipStream_t hs) {
+  const unsigned gx = (unsigned)((C + 255) / 256);
+  for (int round = 0;; ++round) {
+    const int64_t Ry = (R + kRedRows - 1) / kRedRows;
+    double* out = Ry == 1 ? dst : (round % 2 ? t1 : t0);
+    hipLaunchKernelGGL(max_lead_k, dim3(gx, (unsigned)Ry), dim3(256), 0, hs, src, R, C, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || Ry == 1) return e;
+    src = out;
+    R = Ry;
+  }
 }
 
 // Per-workgroup (min, max) of the samples, for the data range.
@@ -322,7 +413,21 @@ __global__ __launch_bounds__(256) void minmax_k(const float* __restrict__ f, int
                                                 float2* __restrict__ part) {
   __shared__ float lo[256], hi[256];
   float a = __builtin_inff(), b = -__builtin_inff();
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+  // up to 3 leading values before a 16-byte boundary, then float4 loads, then the tail
+  const int64_t h = min(n, (int64_t)(((16 - ((uintptr_t)f & 15)) & 15) >> 2));
+  const int64_t n4 = (n - h) / 4, stride = (int64_t)gridDim.x * 256;
+  const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float4* f4 = reinterpret_cast<const float4*>(f + h);
+  for (int64_t i = tid; i < n4; i += stride) {
+    const float4 v = f4[i];
+    a = fminf(a, fminf(fminf(v.x, v.y), fminf(v.z, v.w)));
+    b = fmaxf(b, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+  }
+  if (tid < h) {
+    a = fminf(a, f[tid]);
+    b = fmaxf(b, f[tid]);
+  }
+  for (int64_t i = h + 4 * n4 + tid; i < n; i += stride) {
     a = fminf(a, f[i]);
     b = fmaxf(b, f[i]);
   }
@@ -472,14 +577,20 @@ extern "C" mfa_status mfa_encode_grid(const int32_t res[3], const double* const 
 namespace mfa {
 namespace {
 
-// Workspace of the adaptive loop, sized for max_ctrl control points per axis.
+// Workspace of the adaptive loop, sized for max_ctrl control points per
+// axis: the tables, the intermediates of a fit and of a reconstruction, the
+// per-tile error maxima (rows m = i0 * N1 + i1 of the last reconstruction
+// product, columns i2), their reduction scratch and the three marginals.
 struct AdaptLayout {
-  size_t qt[3], bt[3], y0, y1, r0, r1, fh, rowmax, colpart, mm, total;
+  size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, total;
 };
 
 AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   AdaptLayout L{};
   const size_t N0 = res[0], N1 = res[1], N2 = res[2], m0 = nm[0], m1 = nm[1], m2 = nm[2];
+  const size_t M = N0 * N1, tm = (M + kGemmTile - 1) / kGemmTile, tn = (N2 + kGemmTile - 1) / kGemmTile;
+  auto up = [](size_t v) { return (v + kRedRows - 1) / kRedRows; };
+  const size_t red = std::max({up(tm) * N2, tn > (size_t)kRedRows ? up(tn) * M : 0, up(N0) * N1});
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -491,10 +602,13 @@ AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   L.y0 = take(8 * m0 * N1 * N2);
   L.y1 = take(8 * N2 * m0 * m1);
   L.r0 = take(8 * N0 * m1 * m2);
-  L.r1 = take(8 * m2 * N0 * N1);
-  L.fh = take(8 * N0 * N1 * N2);
-  L.rowmax = take(8 * N0 * N1);
-  L.colpart = take(8 * ((N0 * N1 + kErrRows - 1) / kErrRows) * N2);
+  L.r1 = take(8 * m2 * M);
+  L.rowpart = take(8 * tn * M);
+  L.colpart = take(8 * tm * N2);
+  L.rowmax = take(8 * M);
+  L.red0 = take(8 * red);
+  L.red1 = take(8 * red);
+  L.marg = take(8 * (N0 + N1 + N2));
   L.mm = take(sizeof(float2) * kMinMaxBlocks);
   L.total = o;
   return L;
@@ -559,8 +673,10 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
   uint8_t* wb = static_cast<uint8_t*>(work);
   auto at = [&](size_t off) { return reinterpret_cast<double*>(wb + off); };
   const int64_t N[3] = {res[0], res[1], res[2]};
-  const int64_t rows = N[0] * N[1], nchunk = (rows + kErrRows - 1) / kErrRows;
-  if (nchunk > 65535) return fail(MFA_E_ARG, "res0 * res1 above %lld", 65535LL * kErrRows);
+  const int64_t rows = N[0] * N[1];
+  const int64_t tm = (rows + kGemmTile - 1) / kGemmTile, tn = (N[2] + kGemmTile - 1) / kGemmTile;
+  if ((tm + kRedRows - 1) / kRedRows > 65535)
+    return fail(MFA_E_ARG, "res0 * res1 above %lld", 65535LL * kRedRows * kGemmTile);
   // data range
   float2* mm = reinterpret_cast<float2*>(wb + lay.mm);
   hipLaunchKernelGGL(minmax_k, dim3(kMinMaxBlocks), dim3(256), 0, hs, values, rows * N[2], mm);
@@ -581,14 +697,32 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     T[a].resize(n_init[a] + degree[a] + 1);
     default_knots(n_init[a], degree[a], T[a].data());
   }
-  std::vector<double> Q[3], Bt[3], rowmax(rows), colpart((size_t)nchunk * N[2]);
+  std::vector<double> Q[3], Bt[3], marg(N[0] + N[1] + N[2]);
+  double* dmarg = at(lay.marg);
+  const ErrOut eo{values, N[2], inv_range, at(lay.rowpart), at(lay.colpart)};
   int fits = 0;
   for (;;) {
     int64_t n[3];
     for (int a = 0; a < 3; ++a) n[a] = (int64_t)T[a].size() - degree[a] - 1;
+    // the three axes' tables are independent: two of them on helper threads
+    mfa_status sts[3] = {MFA_OK, MFA_OK, MFA_OK};
+    std::string msg[3];
+    auto tables = [&](int a) {
+      sts[a] = pseudo_inverse(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Q[a], &Bt[a]);
+      if (sts[a] != MFA_OK) msg[a] = mfa_last_error();     // the message is per thread
+    };
+    std::thread th[2];
+    int started = 0;                                  // axes 1..started run on threads
+    try {
+      for (; started < 2; ++started) th[started] = std::thread(tables, started + 1);
+    } catch (const std::system_error&) {
+    }
+    for (int a = 0; a < 3; ++a)
+      if (a == 0 || a > started) tables(a);
+    for (int k = 0; k < started; ++k) th[k].join();
+    for (int a = 0; a < 3; ++a)
+      if (sts[a] != MFA_OK) return fail(sts[a], "%s", msg[a].c_str());
     for (int a = 0; a < 3; ++a) {
-      st = pseudo_inverse(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Q[a], &Bt[a]);
-      if (st != MFA_OK) return st;
       e = hipMemcpyAsync(at(lay.qt[a]), Q[a].data(), Q[a].size() * 8, hipMemcpyHostToDevice, hs);
       if (e == hipSuccess)
         e = hipMemcpyAsync(at(lay.bt[a]), Bt[a].data(), Bt[a].size() * 8, hipMemcpyHostToDevice, hs);
@@ -597,33 +731,26 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     const double* qt[3] = {at(lay.qt[0]), at(lay.qt[1]), at(lay.qt[2])};
     const double* bt[3] = {at(lay.bt[0]), at(lay.bt[1]), at(lay.bt[2])};
     e = run_fit(N, n, values, ctrl, qt, at(lay.y0), at(lay.y1), hs);
-    if (e == hipSuccess) e = run_recon(N, n, ctrl, bt, at(lay.r0), at(lay.r1), at(lay.fh), hs);
+    if (e == hipSuccess) e = run_recon_err(N, n, ctrl, bt, at(lay.r0), at(lay.r1), eo, hs);
+    // marginals: m0[i0], m1[i1] from the row maxima over i2, m2[i2] over all rows
+    if (e == hipSuccess) e = max_lead(eo.rowpart, tn, rows, at(lay.red0), at(lay.red1), at(lay.rowmax), hs);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(err_rows_k, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, hs, at(lay.fh),
-                         values, rows, N[2], inv_range, at(lay.rowmax));
-      hipLaunchKernelGGL(err_cols_k, dim3((unsigned)((N[2] + 255) / 256), (unsigned)nchunk), dim3(256),
-                         0, hs, at(lay.fh), values, rows, N[2], inv_range, at(lay.colpart));
+      hipLaunchKernelGGL(max_row_k, dim3((unsigned)((N[0] + 3) / 4)), dim3(256), 0, hs, at(lay.rowmax),
+                         N[0], N[1], dmarg);
       e = hipGetLastError();
     }
     if (e == hipSuccess)
-      e = hipMemcpyAsync(rowmax.data(), at(lay.rowmax), rows * 8, hipMemcpyDeviceToHost, hs);
+      e = max_lead(at(lay.rowmax), N[0], N[1], at(lay.red0), at(lay.red1), dmarg + N[0], hs);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(colpart.data(), at(lay.colpart), colpart.size() * 8, hipMemcpyDeviceToHost, hs);
+      e = max_lead(eo.colpart, tm, N[2], at(lay.red0), at(lay.red1), dmarg + N[0] + N[1], hs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(marg.data(), dmarg, marg.size() * 8, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_fail(e, "encode: adaptive fit");
     // largest error per sample index of each axis
-    std::vector<double> m[3];
-    m[0].assign(N[0], 0.0);
-    m[1].assign(N[1], 0.0);
-    m[2].assign(N[2], 0.0);
-    for (int64_t r = 0; r < rows; ++r) {
-      m[0][r / N[1]] = std::max(m[0][r / N[1]], rowmax[r]);
-      m[1][r % N[1]] = std::max(m[1][r % N[1]], rowmax[r]);
-    }
-    for (int64_t q = 0; q < nchunk; ++q)
-      for (int64_t c = 0; c < N[2]; ++c) m[2][c] = std::max(m[2][c], colpart[q * N[2] + c]);
+    const double* m[3] = {marg.data(), marg.data() + N[0], marg.data() + N[0] + N[1]};
     double emax = 0.0;
-    for (double v : m[0]) emax = std::max(emax, v);
+    for (int64_t i = 0; i < N[0]; ++i) emax = std::max(emax, m[0][i]);
     if (history) {
       history[4 * fits + 0] = (double)n[0];
       history[4 * fits + 1] = (double)n[1];
