@@ -151,13 +151,14 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single128",
                     choices=["single128", "multiblock", "serving", "points", "encode", "encode_adaptive",
-                             "composite"],
+                             "composite", "iso"],
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
                          "serving: open-loop request trace over three resident models; "
                          "points: point decode alone, input order vs block/tile-sorted order; "
                          "encode: least-squares fit of a 512^3 sample grid to 192^3 control points; "
                          "encode_adaptive: the 512^3 grid fitted with knot insertion to 1e-4; "
+                         "iso: first-hit isosurface of the 128^3 model's 1024^2 frame; "
                          "composite: 8 octant partial renders of the 8x8x8-block frame + over")
     ap.add_argument("--points-model", default="single128", choices=["single128", "multiblock"],
                     help="points: the 128^3 model with 1e7 points or the 8x8x8-block model with 1e8")
@@ -185,6 +186,8 @@ def main(argv=None):
         return run_encode_adaptive(args)
     if args.workload == "composite":
         return run_composite(args)
+    if args.workload == "iso":
+        return run_iso(args)
     if args.steps is None:
         args.steps = 20
     return run_single128(args)
@@ -670,6 +673,94 @@ def run_encode(args):
                      "frac": tf / 78.6, "traffic": None,
                      "kernel": "gemm_f64_k (the three mode products of one apply)",
                      "flop_per_launch": flop},
+        "cpu_baseline": cpu}), flush=True)
+    return 0
+
+
+# ------------------------------------------------------------------ isosurface workload
+ISO_FRAC = 0.3          # level: 30 % of the control-point range
+
+
+def flop_per_value(p: int) -> int:
+    """Value-only sample: basis values (Horner, p FMAs per function and axis)
+    and the sum-factorised contraction (q^3 + q^2 + q FMAs)."""
+    q = p + 1
+    return 2 * (q ** 3 + q ** 2 + q) + 2 * 3 * q * p
+
+
+def _iso_cpu_baseline(spec, cam, params, iso, rgb):
+    """The FP64 oracle on the central 64 x 64 pixels of the frame."""
+    from oracle import render as orr
+    c0 = FRAME // 2 - 32
+    jj, ii = np.meshgrid(np.arange(c0, c0 + 64), np.arange(c0, c0 + 64), indexing="ij")
+    pix = np.stack([jj.reshape(-1), ii.reshape(-1)], axis=1)
+    t0 = time.perf_counter()
+    r = orr.render_iso(orr.model_field(spec), spec.lo, spec.hi, cam, params, FRAME, FRAME, iso, rgb,
+                       pixels=pix)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": len(pix) / dt / FRAME ** 2, "unit": "frames/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, central 64x64 pixels of the frame ({int((r['hit'] >= 0).sum())} "
+                      f"hits) in {dt:.1f} s, scaled to the 1024^2 frame", "cpu_model": _cpu_model()}
+
+
+def run_iso(args):
+    """First-hit isosurface of the 128^3 model's 1024^2 perspective frame at
+    30 % of the value range: one launch of iso_k per step."""
+    steps = 20 if args.steps is None else args.steps
+    spec = synth.model_c2()
+    p = spec.blocks[0].degree[0]
+    cam = synth.perspective_camera(FRAME, FRAME)
+    params = synth.render_params(spec)
+    lo, hi = spec.ctrl_min_max()
+    iso = float(np.float32(lo + ISO_FRAC * (hi - lo)))
+    rgb = (0.9, 0.7, 0.4)
+    cpu = None if args.no_cpu_baseline else _iso_cpu_baseline(spec, cam, params, iso, rgb)
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    model = mfa.Model(spec, args.storage)
+    rgba = torch.empty((FRAME, FRAME, 4), dtype=torch.float32, device=dev)
+    depth = torch.empty((FRAME, FRAME), dtype=torch.float64, device=dev)
+    _, _, ns, ne = mfa.render_iso(model, cam, params, FRAME, FRAME, iso, rgb, debug=True, device=dev)
+    torch.cuda.synchronize()
+    hits = int((ns[..., 1] >= 0).sum().item())
+    n_eval = int(ne.sum().item())
+    examined = int(torch.where(ns[..., 1] >= 0, ns[..., 1] + 1, ns[..., 0]).sum().item())
+    del ns, ne
+    for _ in range(args.warmup):
+        mfa.render_iso(model, cam, params, FRAME, FRAME, iso, rgb, out=rgba, depth=depth, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        mfa.render_iso(model, cam, params, FRAME, FRAME, iso, rgb, out=rgba, depth=depth, device=dev)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0) / steps
+    ms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+    # value-only work for every evaluation but the one full value + gradient
+    # evaluation and shading (30 flop) per hit
+    flop = (n_eval - hits) * flop_per_value(p) + hits * (flop_per_sample(p) + 30)
+    tf = flop / (ms * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "isosurface frames/s (1024^2, first hit)", "value": 1e3 / wall_ms,
+        "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": wall_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"f32 ({args.storage} storage)", "data": "synthetic",
+        "config": {"workload": f"128^3 model (64-Gaussian field, p = {p}), 1024^2 perspective frame, "
+                               f"isosurface at {ISO_FRAC:.0%} of the value range",
+                   "kernel_ms": ms, "hits": hits, "samples_examined": examined,
+                   "values_evaluated": n_eval, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / PEAK_FP32_TFLOPS, "traffic": None,
+                     "peak_unpacked_fp32": PEAK_FP32_ISSUABLE_TFLOPS,
+                     "frac_unpacked_fp32": tf / PEAK_FP32_ISSUABLE_TFLOPS,
+                     "kernel": "iso_k", "flop_per_launch": flop},
         "cpu_baseline": cpu}), flush=True)
     return 0
 

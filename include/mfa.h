@@ -243,6 +243,30 @@ mfa_status mfa_render_frame(mfa_model model, const mfa_camera* camera, const mfa
                             int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
                             void* stream);
 
+/* First-hit isosurface of level iso, from the same value and gradient
+ * queries as the volume render (the paper names isosurface rendering as
+ * another product of its ray-casting step, Sec. IV-A4, without a method).
+ * The rays, their box entry and samples t_k = t_near + (k + 1/2) step are
+ * those of mfa_render_frame; a sample is on side 1 where f >= iso; the hit
+ * lies between the first two consecutive samples k-1, k of different sides
+ * (either direction), at w = (iso - f_{k-1}) / (f_k - f_{k-1}) between them:
+ * t* = t_near + (k - 1/2 + w) step.  The pixel is the headlight Phong colour
+ * of rgb with the gradient at x* = o + t* d (params ka, kd, ks, g0,
+ * shininess), opacity 1; without a hit (0, 0, 0, 0).  params' transfer
+ * function, vmin / vmax and ert_alpha are not used (tf_rgba may be NULL).
+ *  rgba  : device FP32 [h][w][4].
+ *  depth : NULL or device FP64 [h][w]: t* (+inf without a hit), which can
+ *          key the image in mfa_composite_over.
+ *  dbg   : NULL or nsamp = (K, hit sample k or -1) and neval = values
+ *          evaluated; alpha must be NULL.
+ * Samples in a macro cell whose value bounds lie wholly on one side of iso
+ * are not evaluated: the bounds contain every evaluation in the cell, so
+ * the sides, and the image, are those of evaluating every sample.
+ * Errors: as mfa_render_frame, and MFA_E_ARG for a non-finite iso or rgb. */
+mfa_status mfa_render_iso(mfa_model model, const mfa_camera* camera, const mfa_render_params* params,
+                          float iso, const float rgb[3], int32_t w, int32_t h, float* rgba,
+                          double* depth, const mfa_render_debug* dbg, void* stream);
+
 /* Object-space split (Sec. IV-A4: each node ray-casts the blocks it holds
  * into a partially rendered image; Sec. IV-A5: the partial images are
  * combined by "over" in depth order).

@@ -215,6 +215,35 @@ def render_partial(model: Model, cam: dict, params: dict, w: int, h: int, block_
     return (out, key, ns) if nsamp else (out, key)
 
 
+def render_iso(model: Model, cam: dict, params: dict, w: int, h: int, iso: float, rgb,
+               out=None, depth=None, debug: bool = False, stream=None, device=None):
+    """First-hit isosurface of level iso (surface colour rgb).  Returns rgba
+    (h, w, 4) float32 and the hit depths (h, w) float64 (+inf: no hit), plus
+    int32 (h, w, 2) (K, hit sample or -1) and int32 (h, w) evaluated-value
+    counts if debug."""
+    torch = _torch()
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    cobj = make_camera(cam)
+    pobj = make_params(params, None)
+    if out is None:
+        out = torch.empty((h, w, 4), dtype=torch.float32, device=dev)
+    if depth is None:
+        depth = torch.empty((h, w), dtype=torch.float64, device=dev)
+    po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
+    pd = _dev_ptr(depth, torch.float64, (h, w), "depth")
+    dbg = None
+    if debug:
+        dbg = L.RenderDebug()
+        ns = torch.zeros((h, w, 2), dtype=torch.int32, device=dev)
+        ne = torch.zeros((h, w), dtype=torch.int32, device=dev)
+        dbg.nsamp = ns.data_ptr()
+        dbg.neval = ne.data_ptr()
+    L.check(L.lib().mfa_render_iso(model.handle, C.byref(cobj), C.byref(pobj), float(iso),
+                                   (C.c_float * 3)(*[float(v) for v in rgb]), int(w), int(h), po, pd,
+                                   C.byref(dbg) if dbg is not None else None, _stream_ptr(stream)))
+    return (out, depth, ns, ne) if debug else (out, depth)
+
+
 def composite_over(images: Sequence, keys: Sequence, out=None, stream=None):
     """Depth-ordered "over" of partial images (CUDA float32 (h, w, 4) each)
     by their keys (CUDA float64 (h, w) each)."""
@@ -385,14 +414,15 @@ def make_camera(cam: dict) -> L.Camera:
 
 
 def make_params(params: dict, tf_dev) -> L.RenderParams:
+    """tf_dev None: no transfer function (isosurface renders)."""
     torch = _torch()
     p = L.RenderParams()
-    p.tf_rgba = _dev_ptr(tf_dev, torch.float32, (256, 4), "tf").value
-    p.vmin = float(params["vmin"])
-    p.vmax = float(params["vmax"])
+    p.tf_rgba = None if tf_dev is None else _dev_ptr(tf_dev, torch.float32, (256, 4), "tf").value
+    p.vmin = float(params.get("vmin", 0.0))
+    p.vmax = float(params.get("vmax", 1.0))
     p.step = float(params["step"])
     p.max_samples = int(params["max_samples"])
-    p.ert_alpha = float(params["ert_alpha"])
+    p.ert_alpha = float(params.get("ert_alpha", 2.0))
     p.ka, p.kd, p.ks = float(params["ka"]), float(params["kd"]), float(params["ks"])
     p.g0 = float(params["g0"])
     p.shininess = int(params["shininess"])

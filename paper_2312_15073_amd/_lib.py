@@ -91,6 +91,9 @@ SIGNATURES = {
     "mfa_render_partial": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p, C.POINTER(RenderDebug), C.c_void_p]),
+    "mfa_render_iso": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams), C.c_float,
+                                 C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.POINTER(RenderDebug), C.c_void_p]),
     "mfa_composite_over": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "mfa_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),

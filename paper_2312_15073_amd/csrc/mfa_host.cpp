@@ -26,6 +26,8 @@ hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
 hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
                          hipStream_t st);
 hipError_t launch_composite(const CompositeArgs& c, hipStream_t st);
+hipError_t launch_iso(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+                      hipStream_t st);
 }  // namespace mfa
 
 using namespace mfa;
@@ -770,7 +772,7 @@ extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3]
 // ------------------------------------------------------------------ render
 mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
                             int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
-                            RenderArgs* out) {
+                            RenderArgs* out, bool need_tf) {
   if (!m || !cam || !rp || !rgba) return fail(MFA_E_ARG, "null argument");
   if (w < 1 || h < 1 || w > 16384 || h > 16384) return fail(MFA_E_ARG, "image %dx%d out of range", w, h);
   if (cam->kind != MFA_ORTHO && cam->kind != MFA_PERSPECTIVE) return fail(MFA_E_ARG, "camera kind");
@@ -778,8 +780,8 @@ mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render
     if (!is_fin(cam->eye[a]) || !is_fin(cam->forward[a]) || !is_fin(cam->right[a]) || !is_fin(cam->up[a]))
       return fail(MFA_E_ARG, "camera vectors must be finite");
   if (!is_fin(cam->sx) || !is_fin(cam->sy)) return fail(MFA_E_ARG, "camera scales must be finite");
-  if (!rp->tf_rgba) return fail(MFA_E_ARG, "tf_rgba is null");
-  if (!(rp->vmin < rp->vmax) || !std::isfinite(rp->vmin) || !std::isfinite(rp->vmax))
+  if (need_tf && !rp->tf_rgba) return fail(MFA_E_ARG, "tf_rgba is null");
+  if (need_tf && (!(rp->vmin < rp->vmax) || !std::isfinite(rp->vmin) || !std::isfinite(rp->vmax)))
     return fail(MFA_E_ARG, "need finite vmin < vmax");
   const double step = rp->step == 0.0 ? 0.5 * m->voxel : rp->step;
   if (!(step > 0.0) || !is_fin(step)) return fail(MFA_E_ARG, "step must be > 0");
@@ -804,7 +806,7 @@ mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render
   r.max_samples = rp->max_samples;
   r.shininess = rp->shininess;
   r.vmin = rp->vmin;
-  r.inv_range = (float)(1.0 / ((double)rp->vmax - (double)rp->vmin));
+  r.inv_range = need_tf ? (float)(1.0 / ((double)rp->vmax - (double)rp->vmin)) : 0.f;
   r.ert_alpha = rp->ert_alpha;
   r.ka = rp->ka;
   r.kd = rp->kd;
@@ -862,6 +864,30 @@ extern "C" mfa_status mfa_render_partial(mfa_model m, const mfa_camera* cam,
   if (st != MFA_OK) return st;
   hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "partial render launch");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_render_iso(mfa_model m, const mfa_camera* cam,
+                                     const mfa_render_params* rp, float iso, const float rgb[3],
+                                     int32_t w, int32_t h, float* rgba, double* depth,
+                                     const mfa_render_debug* dbg, void* stream) {
+  RenderArgs r;
+  mfa_status st = make_render_args(m, cam, rp, w, h, rgba, dbg, &r, false);
+  if (st != MFA_OK) return st;
+  if (!std::isfinite(iso)) return fail(MFA_E_ARG, "iso must be finite");
+  if (!rgb) return fail(MFA_E_ARG, "null rgb");
+  for (int c = 0; c < 3; ++c) {
+    if (!std::isfinite(rgb[c])) return fail(MFA_E_ARG, "rgb must be finite");
+    r.iso_rgb[c] = rgb[c];
+  }
+  if (dbg && dbg->alpha) return fail(MFA_E_ARG, "the isosurface render has no alpha output");
+  r.iso = iso;
+  r.key = depth;
+  r.tf = nullptr;
+  st = check_device(m);
+  if (st != MFA_OK) return st;
+  hipError_t e = launch_iso(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "isosurface render launch");
   return MFA_OK;
 }
 

@@ -219,6 +219,10 @@ struct RenderArgs {
   int32_t reg_lo[3], reg_hi[3];
   double reg_box_lo[3], reg_box_hi[3];
   double* key;
+  // isosurface render: level and surface colour; key[pixel] = hit
+  // parameter t* (+inf without a hit), nsamp = (K, hit sample or -1)
+  float iso;
+  float iso_rgb[3];
 };
 
 // Depth-ordered compositing of up to kMaxPartials partial images.

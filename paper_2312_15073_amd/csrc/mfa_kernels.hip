@@ -1298,6 +1298,145 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   render_tile<P, S, MULTI, PARTIAL>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
 }
 
+// ------------------------------------------------------------------ K8: isosurface
+// First-hit isosurface on the volume renderer's ray schedule: a sample is on
+// side 1 when f >= iso; the surface lies between the first two consecutive
+// samples whose sides differ, at the linear interpolation of f between
+// them; the hit is shaded with the volume renderer's headlight Phong
+// (surface colour iso_rgb, opacity 1).  The value bounds of a macro cell
+// (its control points' range, widened beyond the FP32 evaluation error and
+// rounded outwards to FP16) contain every evaluation in the cell, so a cell
+// whose lower bound is >= iso puts all its samples on side 1, one whose
+// upper bound is < iso on side 0: the sides an evaluation would give.  The
+// value of such a sample is evaluated only if it brackets the hit.
+__device__ __forceinline__ int iso_side(uint32_t bh, float iso) {
+  const float blo = __half2float(__ushort_as_half((unsigned short)(bh & 0xFFFFu)));
+  const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
+  return iso <= blo ? 1 : (iso > bhi ? 0 : -1);
+}
+
+template <int P, Storage S, bool MULTI>
+__device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r, int tile,
+                                         const SpanRec* __restrict__ R,
+                                         const float* __restrict__ MT) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int tx = (r.w + kTile - 1) / kTile;
+  const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool pix = i < r.w && j < r.h;
+  Ray ray;
+  ray.K = 0;
+  if (pix) ray = make_ray(m, r, i, j);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const int64_t pid = (int64_t)j * r.w + i;
+  int hit = -1, nev = 0, side_prev = -1, last_mc = -1, cell_side = -1;
+  float fprev = 0.f, fa = 0.f, fb = 0.f;
+  bool known = false;                    // fprev holds the value of sample k - 1
+  for (int k = 0;; ++k) {
+    const bool act = pix && hit < 0 && k < ray.K;
+    if (__ballot(act) == 0) break;       // whole wave finished
+    if (!act) continue;
+    double x[3];
+    sample_point(ray, r.step, k, x);
+    Probe q = probe<MULTI>(m, R, x);
+    const int mcg = macro_cell(m, q.B, q.j);
+    uint32_t bh = 0;
+    if (mcg != last_mc) bh = m.mcb[mcg];
+    const Loc Lc = finish(m, R, q);
+    if (Lc.mc != last_mc) {
+      if (Lc.mc != mcg) bh = m.mcb[Lc.mc];
+      cell_side = iso_side(bh, r.iso);
+      last_mc = Lc.mc;
+    }
+    int side = cell_side;
+    float f = 0.f;
+    bool have = false;
+    if (side < 0) {
+      f = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x;
+      ++nev;
+      side = f >= r.iso ? 1 : 0;
+      have = true;
+    }
+    if (k > 0 && side != side_prev) {
+      if (!have) {
+        f = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x;
+        ++nev;
+      }
+      if (!known) {
+        double xp[3];
+        sample_point(ray, r.step, k - 1, xp);
+        const Loc Lp = locate<P, MULTI>(m, R, xp);
+        fprev = evaluate<P, S, !MULTI>(Lp, rs, MT, m.mat_stride, m.imat).x;
+        ++nev;
+      }
+      hit = k;
+      fa = fprev;
+      fb = f;
+    }
+    side_prev = side;
+    fprev = f;
+    known = have;
+  }
+  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+  double depth = __builtin_inf();
+  if (pix && hit > 0) {
+    // fa and fb lie on different sides of iso, so w is in [0, 1]
+    const float w = (r.iso - fa) / (fb - fa);
+    double xs[3];
+    {
+#pragma clang fp contract(off)
+      depth = ray.t_near + (((double)(hit - 1) + 0.5) + (double)w) * r.step;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xs[a] = ray.o[a] + depth * ray.d[a];
+    }
+    const Loc Ls = locate<P, MULTI>(m, R, xs);
+    const float4 e = evaluate<P, S, !MULTI>(Ls, rs, MT, m.mat_stride, m.imat);
+    ++nev;
+    const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
+    float L[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L[a] = (float)(-ray.d[a] / dn);
+    const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
+    const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
+    const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
+    float spec = 1.f, bse = diff;
+    for (int ex = r.shininess; ex; ex >>= 1) {
+      if (ex & 1) spec *= bse;
+      bse *= bse;
+    }
+    const float shade = fmaf(r.kd, diff, r.ka);
+    const float ks = r.ks * spec;
+    out = make_float4(fmaf(r.iso_rgb[0], shade, ks), fmaf(r.iso_rgb[1], shade, ks),
+                      fmaf(r.iso_rgb[2], shade, ks), 1.f);
+  }
+  if (pix) {
+    reinterpret_cast<float4*>(r.rgba)[pid] = out;
+    if (r.key) r.key[pid] = depth;
+    if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, hit);
+    if (r.neval) r.neval[pid] = nev;
+  }
+}
+
+template <int P, Storage S, bool MULTI, bool LDSREC>
+__global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
+  extern __shared__ float4 dyn[];
+  const SpanRec* R = m.rec;
+  const float* MT = m.mats;
+  if constexpr (LDSREC) {
+    SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
+    float* lm = reinterpret_cast<float*>(lr + m.n_rec);
+    for (int q = threadIdx.x; q < m.n_rec * 2; q += kBlock)
+      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
+    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    R = lr;
+    MT = lm;
+    __syncthreads();
+  }
+  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+  iso_tile<P, S, MULTI>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
+}
+
 // ------------------------------------------------------------------ K6: persistent serving
 // Each workgroup takes work items from an atomic cursor until the batch is
 // exhausted (every wave reaches the exit once the cursor passes n_items).
@@ -1453,6 +1592,19 @@ static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, h
   return hipGetLastError();
 }
 
+template <int P, Storage S>
+static hipError_t iso_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
+  const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
+  if (multi)
+    hipLaunchKernelGGL((iso_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else if (lds <= (size_t)kLdsRecBytes)
+    hipLaunchKernelGGL((iso_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
+  else
+    hipLaunchKernelGGL((iso_k<P, S, false, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  return hipGetLastError();
+}
+
 #define MFA_DISPATCH(FN, ...)                                                        \
   switch (p) {                                                                       \
     case 1: return s == Storage::F32 ? FN<1, Storage::F32>(__VA_ARGS__)              \
@@ -1496,6 +1648,11 @@ hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArg
 hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
                          hipStream_t st) {
   MFA_DISPATCH(render_p, m, multi, r, st)
+}
+
+hipError_t launch_iso(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+                      hipStream_t st) {
+  MFA_DISPATCH(iso_p, m, multi, r, st)
 }
 
 // ------------------------------------------------------------------ K7: compositing

@@ -49,7 +49,8 @@ mfa_status check_knots(const double* T, int n, int p, int blk, int axis);
 void default_knots(int n, int p, double* T);
 mfa_status check_device(mfa_model m);
 // Validated kernel arguments of a render of model m (shared by the direct
-// entry point and the server).
+// entry point and the server); need_tf = false for the isosurface render,
+// which uses neither the transfer function nor its value range.
 mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
                             int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
-                            mfa::RenderArgs* out);
+                            mfa::RenderArgs* out, bool need_tf = true);
