@@ -1308,7 +1308,9 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
 // rounded outwards to FP16) contain every evaluation in the cell, so a cell
 // whose lower bound is >= iso puts all its samples on side 1, one whose
 // upper bound is < iso on side 0: the sides an evaluation would give.  The
-// value of such a sample is evaluated only if it brackets the hit.
+// value of such a sample is evaluated only if it brackets the hit.  The
+// same test on the coarse and fine super cells lets a ray leap across a
+// super cell wholly on one side.
 __device__ __forceinline__ int iso_side(uint32_t bh, float iso) {
   const float blo = __half2float(__ushort_as_half((unsigned short)(bh & 0xFFFFu)));
   const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
@@ -1329,53 +1331,114 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
   if (pix) ray = make_ray(m, r, i, j);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const int64_t pid = (int64_t)j * r.w + i;
-  int hit = -1, nev = 0, side_prev = -1, last_mc = -1, cell_side = -1;
+  int hit = -1, nev = 0, side_prev = -1;
   float fprev = 0.f, fa = 0.f, fb = 0.f;
   bool known = false;                    // fprev holds the value of sample k - 1
-  for (int k = 0;; ++k) {
+  bool back = false;                     // this step evaluates sample k - 1 (hit found at k)
+  // cached sides of the last coarse, fine and macro cell (-1: undecided)
+  int last_c[3] = {-1, -1, -1}, side_c[3] = {-1, -1, -1};
+  // leap state: origin sample, level and cell of a pending leap; the cell
+  // (2 * cell + level) where a leap failed and is not tried again
+  int k = 0, from = -1, lvl = 0, cell = -1, noleap = -1;
+  // One located sample and at most one value query per lane and step, so
+  // that the lanes needing a value share one evaluation.
+  for (;;) {
     const bool act = pix && hit < 0 && k < ray.K;
     if (__ballot(act) == 0) break;       // whole wave finished
     if (!act) continue;
     double x[3];
-    sample_point(ray, r.step, k, x);
-    Probe q = probe<MULTI>(m, R, x);
-    const int mcg = macro_cell(m, q.B, q.j);
-    uint32_t bh = 0;
-    if (mcg != last_mc) bh = m.mcb[mcg];
-    const Loc Lc = finish(m, R, q);
-    if (Lc.mc != last_mc) {
-      if (Lc.mc != mcg) bh = m.mcb[Lc.mc];
-      cell_side = iso_side(bh, r.iso);
-      last_mc = Lc.mc;
+    sample_point(ray, r.step, back ? k - 1 : k, x);
+    const Loc Lc = locate<P, MULTI>(m, R, x);
+    const DevBlock* __restrict__ B = MULTI ? m.blocks + Lc.block : &m.b0;
+    int c[3];
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const int sh = m.sc_shift[l];
+      c[l] = B->sc_off[l] + (((Lc.j[0] >> sh) * B->sc[l][1] + (Lc.j[1] >> sh)) * B->sc[l][2] +
+                             (Lc.j[2] >> sh));
     }
-    int side = cell_side;
+    c[2] = Lc.mc;
+    int lv = 3;
+    if (!back && from < 0) {
+      uint32_t bh[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        if (c[l] != last_c[l]) bh[l] = l < 2 ? m.scb[l][c[l]] : m.mcb[c[l]];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        if (c[l] != last_c[l]) {
+          side_c[l] = iso_side(bh[l], r.iso);
+          last_c[l] = c[l];
+        }
+      lv = side_c[0] >= 0 ? 0 : (side_c[1] >= 0 ? 1 : (side_c[2] >= 0 ? 2 : 3));
+    }
+    const int sdec = lv < 3 ? side_c[lv] : -1;
+    const bool need = back || (from < 0 && (sdec < 0 || (k > 0 && sdec != side_prev)));
     float f = 0.f;
-    bool have = false;
-    if (side < 0) {
+    if (need) {
       f = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x;
       ++nev;
-      side = f >= r.iso ? 1 : 0;
-      have = true;
     }
-    if (k > 0 && side != side_prev) {
-      if (!have) {
-        f = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x;
-        ++nev;
-      }
-      if (!known) {
-        double xp[3];
-        sample_point(ray, r.step, k - 1, xp);
-        const Loc Lp = locate<P, MULTI>(m, R, xp);
-        fprev = evaluate<P, S, !MULTI>(Lp, rs, MT, m.mat_stride, m.imat).x;
-        ++nev;
-      }
+    if (back) {                          // the value before the hit
+      fa = f;
       hit = k;
-      fa = fprev;
+      continue;
+    }
+    if (from >= 0) {                     // landing sample of a leap at level lvl
+      if (c[lvl] != cell) {              // left the cell: undo, step from the origin
+        noleap = 2 * cell + lvl;
+        k = from + 1;
+      } else {                           // every sample up to here had the origin's side
+        known = false;
+        ++k;
+      }
+      from = -1;
+      continue;
+    }
+    const int side = sdec >= 0 ? sdec : (f >= r.iso ? 1 : 0);
+    if (k > 0 && side != side_prev) {
       fb = f;
+      if (known) {
+        fa = fprev;
+        hit = k;
+      } else {
+        back = true;
+      }
+      continue;
     }
     side_prev = side;
     fprev = f;
-    known = have;
+    known = need;
+    // A super cell on one side of the level: leap to the estimated last
+    // sample inside it (FP32 exit through the uniform-knot position of the
+    // cell faces, less one step), located next by the exact rules.  If that
+    // sample lies in the same cell, so does every sample between (the span
+    // index per axis is monotone along the ray), which all have this side;
+    // otherwise the leap is undone.
+    int kl = k;
+    if (lv < 2 && 2 * c[lv] + lv != noleap) {
+      const int sh = m.sc_shift[lv];
+      float te = __builtin_inff();
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (ray.d[a] == 0.0) continue;
+        const int cc = Lc.j[a] >> sh;
+        const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
+        const float xb =
+            fmaf(__fdividef((float)jb, (float)B->nsp[a]), (float)B->ext[a], (float)B->lo[a]);
+        te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
+      }
+      kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
+                      (float)(ray.K - 1));
+    }
+    if (kl > k + 1) {
+      from = k;
+      lvl = lv;
+      cell = c[lv];
+      k = kl;
+    } else {
+      ++k;
+    }
   }
   float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
   double depth = __builtin_inf();
