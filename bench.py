@@ -151,13 +151,14 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single128",
                     choices=["single128", "multiblock", "serving", "points", "encode", "encode_adaptive",
-                             "composite", "iso"],
+                             "composite", "iso", "graded"],
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
                          "serving: open-loop request trace over three resident models; "
                          "points: point decode alone, input order vs block/tile-sorted order; "
                          "encode: least-squares fit of a 512^3 sample grid to 192^3 control points; "
                          "encode_adaptive: the 512^3 grid fitted with knot insertion to 1e-4; "
+                         "graded: the default step on the 128^3 model with graded knots; "
                          "iso: first-hit isosurface of the 128^3 model's 1024^2 frame; "
                          "composite: 8 octant partial renders of the 8x8x8-block frame + over")
     ap.add_argument("--points-model", default="single128", choices=["single128", "multiblock"],
@@ -188,13 +189,17 @@ def main(argv=None):
         return run_composite(args)
     if args.workload == "iso":
         return run_iso(args)
+    if args.workload == "graded":
+        if args.steps is None:
+            args.steps = 20
+        return run_single128(args, graded=True)
     if args.steps is None:
         args.steps = 20
     return run_single128(args)
 
 
-def run_single128(args):
-    spec = synth.model_c2()
+def run_single128(args, graded: bool = False):
+    spec = synth.model_c2_graded() if graded else synth.model_c2()
     p = spec.blocks[0].degree[0]
     pts = synth.random_points(N_POINTS, seed=12)
     cam = synth.perspective_camera(FRAME, FRAME)
@@ -298,7 +303,8 @@ def run_single128(args):
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "f32" else f"f32 ({args.storage} storage)",
         "data": "synthetic",
-        "config": {"workload": (f"single block, {spec.blocks[0].ctrl.shape[0]}^3 control points, "
+        "config": {"workload": (f"single block, {spec.blocks[0].ctrl.shape[0]}^3 control points"
+                                f"{' on graded knots (span widths 7x apart)' if graded else ''}, "
                                 f"degree {p}, {args.storage} storage; decode {GRID_N}^3 grid + "
                                 f"{N_POINTS} random points + {FRAME}x{FRAME} perspective frame "
                                 f"(max 1024 samples/ray)"),

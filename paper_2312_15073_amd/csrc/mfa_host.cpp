@@ -17,16 +17,16 @@
 #include "mfa_model.h"
 
 namespace mfa {
-hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, const float* xyz,
                                 int64_t n, float* out, int32_t* dbg, hipStream_t st);
 hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
                               hipStream_t st);
-hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st);
-hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                          hipStream_t st);
 hipError_t launch_composite(const CompositeArgs& c, hipStream_t st);
-hipError_t launch_iso(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+hipError_t launch_iso(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                       hipStream_t st);
 }  // namespace mfa
 
@@ -200,7 +200,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_ws};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -367,6 +367,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   const int es = elem_size(storage);
   std::vector<DevBlock> dblk(nb);
   std::vector<SpanRec> recs;
+  std::vector<int32_t> gtab;
   std::vector<float> mats;
   std::map<std::vector<float>, int> mat_ids;
   const std::vector<float> canon = uniform_table(p);
@@ -428,8 +429,33 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
         }
         recs.push_back(r);
       }
+      // Span guess table of a non-uniform axis: bins of width at most half
+      // the shortest span hold at most one knot each, so the span of the
+      // bin's left edge is the exact span or the one before it.
+      const int nsp = n - p;
+      bool uniform = true;
+      double hmin = INFINITY;
+      for (int j = 0; j < nsp; ++j) {
+        uniform &= T[p + j] == (double)j / (double)nsp;
+        if (T[p + j + 1] > T[p + j]) hmin = std::fmin(hmin, T[p + j + 1] - T[p + j]);
+      }
+      D.gtab_off[a] = -1;
+      D.gtab_n[a] = 0;
+      if (!uniform) {
+        const int64_t G = std::min<int64_t>(std::max<int64_t>((int64_t)std::ceil(2.0 / hmin), nsp),
+                                            std::min<int64_t>(64ll * nsp, 1ll << 20));
+        D.gtab_off[a] = (int32_t)gtab.size();
+        D.gtab_n[a] = (int32_t)G;
+        for (int64_t g = 0; g < G; ++g) {
+          const double u = (double)g / (double)G;
+          const int s = (int)(std::upper_bound(T.data() + p, T.data() + n, u) - T.data()) - 1;
+          gtab.push_back(std::min(std::max(s, p), n - 1) - p);
+        }
+      }
     }
   }
+  if (gtab.size() > (size_t)INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "span tables too large"); }
+  m->nonuniform = !gtab.empty();
   if (recs.size() > (size_t)INT32_MAX) { free_model(m); return fail(MFA_E_UNSUPPORTED, "too many spans"); }
   // Finest macro cells whose bounds (4 bytes each) take no more memory than
   // the larger of the stored control points and 16 MiB.
@@ -590,7 +616,9 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_scb[0], scb16[0].data(), scb16[0].size() * 4, m, "bounds upload")) != MFA_OK ||
       (st = upload(&m->d_scb[1], scb16[1].data(), scb16[1].size() * 4, m, "bounds upload")) != MFA_OK ||
       (!bwin.empty() &&
-       (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK)) {
+       (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK) ||
+      (!gtab.empty() &&
+       (st = upload(&m->d_gtab, gtab.data(), gtab.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK)) {
     free_model(m);
     return st;
   }
@@ -623,6 +651,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     dm.sc_shift[l] = sc_shift[l];
   }
   dm.bwin = m->d_bwin;
+  dm.gtab = m->d_gtab;
   dm.win_max = win_max;
   dm.b0 = dblk[0];
   *out = m;
@@ -732,12 +761,12 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
     sa.nb = (int32_t)nbk;
     sa.tmp = two ? (float4*)(w + o_tmp) : nullptr;
     sa.ccursor = two ? (uint32_t*)(w + o_ccur) : nullptr;
-    hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), m->nblocks > 1, sa, out, dbg,
+    hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), sa, out, dbg,
                                         (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sorted decode launch");
     return MFA_OK;
   }
-  hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), m->nblocks > 1, xyz, n, out,
+  hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), kernel_kind(m), xyz, n, out,
                                       dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_points launch");
   return MFA_OK;
@@ -834,7 +863,7 @@ extern "C" mfa_status mfa_render_frame(mfa_model m, const mfa_camera* cam, const
   if (st != MFA_OK) return st;
   st = check_device(m);
   if (st != MFA_OK) return st;
-  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), kernel_kind(m), r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   return MFA_OK;
 }
@@ -862,7 +891,7 @@ extern "C" mfa_status mfa_render_partial(mfa_model m, const mfa_camera* cam,
   r.key = key;
   st = check_device(m);
   if (st != MFA_OK) return st;
-  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  hipError_t e = launch_render(m->dm, m->degree, storage_of(m), kernel_kind(m), r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "partial render launch");
   return MFA_OK;
 }
@@ -886,7 +915,7 @@ extern "C" mfa_status mfa_render_iso(mfa_model m, const mfa_camera* cam,
   r.tf = nullptr;
   st = check_device(m);
   if (st != MFA_OK) return st;
-  hipError_t e = launch_iso(m->dm, m->degree, storage_of(m), m->nblocks > 1, r, (hipStream_t)stream);
+  hipError_t e = launch_iso(m->dm, m->degree, storage_of(m), kernel_kind(m), r, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "isosurface render launch");
   return MFA_OK;
 }

@@ -44,9 +44,13 @@ struct DevBlock {
   int32_t tile_off;     // first sort bucket of the block
   int32_t sc_off[2];    // per super-cell level: the block's first cell in that level's pool
   int32_t sc[2][3];     // per level: cells per axis = ceil(nsp / 2^sc_shift[level])
-  int32_t pad;
+  // span guess of a non-uniform knot axis: gtab[gtab_off + floor(u * gtab_n)]
+  // is the span (record index) holding u = g / gtab_n, with bins narrower
+  // than the shortest span; gtab_off = -1 for uniform knots (guess floor(u * nsp))
+  int32_t gtab_off[3];
+  int32_t gtab_n[3];
 };
-static_assert(sizeof(DevBlock) == 176, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 200, "DevBlock layout");
 
 // Points sorted for decode are grouped by (block, tile); a tile spans
 // 2^sort_shift knot spans per axis, the shift chosen per model so that there
@@ -88,6 +92,10 @@ constexpr int kMaxMacroShift = 2;
 // first visible cell in a few leaps.
 constexpr int kSuperShift[2] = {3, 2};
 
+// Kernel family of a model: single block with uniform knots, single block
+// with a non-uniform axis (span guess tables), several blocks.
+constexpr int kKindPlain = 0, kKindGraded = 1, kKindMulti = 2;
+
 struct DevModel {
   const void* ctrl;
   const SpanRec* rec;
@@ -110,6 +118,7 @@ struct DevModel {
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
   const uint32_t* scb[2];  // the same bounds per super cell, coarse level first
+  const int32_t* gtab;     // span guess tables of the non-uniform knot axes
   int32_t sc_shift[2];     // log2 of the spans per super cell and axis, per level
   double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
   double box_lo[3];

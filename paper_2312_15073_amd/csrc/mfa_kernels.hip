@@ -147,6 +147,22 @@ __device__ __forceinline__ int guess_span(int nsp, double u) {
   return j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
 }
 
+// The guess of a point's span on axis a of block B: floor(u * nsp) for
+// uniform knots, else the span of u's bin in the axis's guess table (the
+// exact span or the one before it).  GT: the kernel may see guess tables
+// (multi-block kernels, and the single-block kernels built for models with
+// a non-uniform axis); without it the plain guess is compiled alone.
+template <bool GT>
+__device__ __forceinline__ int guess_span(const int32_t* __restrict__ gtab,
+                                          const DevBlock* __restrict__ B, int a, double u) {
+  if constexpr (!GT) return guess_span(B->nsp[a], u);
+  const int off = B->gtab_off[a];
+  if (off < 0) return guess_span(B->nsp[a], u);
+  const int G = B->gtab_n[a];
+  const int g = (int)(u * (double)G);
+  return gtab[off + (g < 0 ? 0 : (g > G - 1 ? G - 1 : g))];
+}
+
 __device__ __forceinline__ bool span_ok(int nsp, double u, int j, const SpanRec& rec) {
   return !(j < nsp - 1 && rec.t_next <= u) & !(j > 0 && rec.t > u);
 }
@@ -342,7 +358,7 @@ __device__ __forceinline__ int macro_cell(const DevModel& m, const DevBlock* __r
 }
 
 // R: span records (global pool or its LDS copy).
-template <bool MULTI>
+template <bool MULTI, bool GT = MULTI>
 __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restrict__ R,
                                        const double (&x)[3]) {
   Probe q;
@@ -381,7 +397,7 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    q.j[a] = guess_span(q.B->nsp[a], q.u[a]);
+    q.j[a] = guess_span<GT>(m.gtab, q.B, a, q.u[a]);
     q.rec[a] = R[q.B->rec_off[a] + q.j[a]];
   }
   return q;
@@ -415,10 +431,10 @@ __device__ __forceinline__ Loc finish(const DevModel& m, const SpanRec* __restri
   return L;
 }
 
-template <int P, bool MULTI>
+template <int P, bool MULTI, bool GT = MULTI>
 __device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
                                       const double (&x)[3]) {
-  Probe q = probe<MULTI>(m, R, x);
+  Probe q = probe<MULTI, GT>(m, R, x);
   return finish(m, R, q);
 }
 
@@ -444,7 +460,7 @@ __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t 
 }
 
 // ------------------------------------------------------------------ K1: points
-template <int P, Storage S, bool MULTI>
+template <int P, Storage S, bool MULTI, bool GT = MULTI>
 __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
                                                           int64_t n, float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -452,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const floa
   if (i >= n) return;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const double x[3] = {(double)xyz[i], (double)xyz[n + i], (double)xyz[2 * n + i]};
-  const Loc L = locate<P, MULTI>(m, m.rec, x);
+  const Loc L = locate<P, MULTI, GT>(m, m.rec, x);
   reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
@@ -521,7 +537,7 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int nsp = B->nsp[a];
-    const int j = min((int)(u[a] * (double)nsp), nsp - 1);
+    const int j = guess_span<true>(m.gtab, B, a, u[a]);   // the exact span or the one before
     t[a] = j >> sh;
     td[a] = (nsp + (1 << sh) - 1) >> sh;
   }
@@ -702,7 +718,7 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
 // for non-uniform knots) reads its rows from global memory.  Both paths sum
 // in the same order.  LDSREC: the span records and basis tables of a
 // single-block model are staged too, ahead of the window.
-template <int P, Storage S, bool MULTI, bool LDSREC>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = MULTI>
 __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
                                                          float* __restrict__ out,
                                                          int32_t* __restrict__ dbg) {
@@ -777,7 +793,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   for (; t < s1; t += kBlock) {
     const float4 qn = sa.rec[min(t + kBlock, s1 - 1)];   // next record in flight
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
-    const Loc L = locate<P, MULTI>(m, R, x);
+    const Loc L = locate<P, MULTI, GT>(m, R, x);
     const uint32_t i = __float_as_uint(q.w);
     q = qn;
     if ((int64_t)i >= sa.n) continue;
@@ -802,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
 // Sorted decode for models whose bucket windows exceed the LDS budget: one
 // point per thread over the sorted records (workgroup ranges dealt to XCDs
 // in contiguous bands), rows from global memory.
-template <int P, Storage S, bool MULTI>
+template <int P, Storage S, bool MULTI, bool GT = MULTI>
 __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
                                                           float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -812,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs s
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const float4 q = sa.rec[t];
   const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
-  const Loc L = locate<P, MULTI>(m, m.rec, x);
+  const Loc L = locate<P, MULTI, GT>(m, m.rec, x);
   const uint32_t i = __float_as_uint(q.w);
   if ((int64_t)i >= sa.n) return;
   reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
@@ -1030,6 +1046,16 @@ __device__ __forceinline__ void region_range(const RenderArgs& r, const Ray& ray
   if (k_lo > k_hi) k_lo = k_hi;
 }
 
+// Knot at the start of span jb of axis a, in FP32: the parameter of a cell
+// face for the leap estimates; jb / nsp for uniform knots, else from the
+// span records (1 past the last span: the end knot 1).
+template <bool GT>
+__device__ __forceinline__ float face_knot(const SpanRec* __restrict__ R,
+                                           const DevBlock* __restrict__ B, int a, int jb) {
+  if (!GT || B->gtab_off[a] < 0) return __fdividef((float)jb, (float)B->nsp[a]);
+  return jb < B->nsp[a] ? (float)R[B->rec_off[a] + jb].t : 1.f;
+}
+
 // Transfer-function coordinate s in [0, 255] of a value (shared by the
 // lookup and by the transparency test so both round identically).
 __device__ __forceinline__ float tf_coord(float f, float vmin, float inv_range) {
@@ -1072,8 +1098,8 @@ __device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, co
 // lane: returns the first sample the per-sample loop has to look at (K if
 // none).  A sample in a transparent coarse super cell (else in a
 // transparent fine one) leaps to the estimated last sample inside that cell
-// (FP32 exit from the uniform-knot position of the cell faces, less one
-// step), which is then located by the exact rules.  If the landing sample
+// (FP32 exit through the cell faces at their stored knots, less one step),
+// which is then located by the exact rules.  If the landing sample
 // lies in the same cell, so does every sample between: the span index per
 // axis is monotone along the ray (each rounding step of the position and of
 // the parameter map is monotone), so the cell coordinates of a sample in
@@ -1082,7 +1108,7 @@ __device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, co
 // that cell is crossed sample by sample.  The search stops at the first
 // sample whose fine super cell is not transparent; compositing from there
 // gives the same pixel as compositing from sample 0.
-template <int P, bool MULTI>
+template <int P, bool MULTI, bool GT = MULTI>
 __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs& r,
                                              const SpanRec* __restrict__ R, const Ray& ray,
                                              const int* zpre, int k_lo, int k_hi) {
@@ -1091,7 +1117,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
   while (k < k_hi) {
     double x[3];
     sample_point(ray, r.step, k, x);
-    const Loc Lc = locate<P, MULTI>(m, R, x);
+    const Loc Lc = locate<P, MULTI, GT>(m, R, x);
     const DevBlock* __restrict__ B = MULTI ? m.blocks + Lc.block : &m.b0;
     int c[2];
 #pragma unroll
@@ -1129,8 +1155,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
         if (ray.d[a] == 0.0) continue;
         const int cc = Lc.j[a] >> sh;
         const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
-        const float xb =
-            fmaf(__fdividef((float)jb, (float)B->nsp[a]), (float)B->ext[a], (float)B->lo[a]);
+        const float xb = fmaf(face_knot<GT>(R, B, a, jb), (float)B->ext[a], (float)B->lo[a]);
         te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
       }
       kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
@@ -1148,7 +1173,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
 
 // One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
 // and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
-template <int P, Storage S, bool MULTI, bool PARTIAL = false>
+template <int P, Storage S, bool MULTI, bool PARTIAL = false, bool GT = MULTI>
 __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs& r, int tile,
                                             const SpanRec* __restrict__ R,
                                             const float* __restrict__ MT, const float4* tf,
@@ -1175,7 +1200,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   if constexpr (PARTIAL) {
     if (pix) region_range(r, ray, k_lo, k_hi, t_in);
   }
-  const int k0 = pix ? first_visible<P, MULTI>(m, r, R, ray, zpre, k_lo, k_hi) : 0;
+  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, k_lo, k_hi) : 0;
   if (r.alpha)
     for (int q = 0; q < k0; ++q) r.alpha[pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
@@ -1188,7 +1213,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, k, x);
-    Probe q = probe<MULTI>(m, R, x);
+    Probe q = probe<MULTI, GT>(m, R, x);
     // Skip the evaluation where the transfer function is zero over the
     // value bounds of the macro cell: such a sample has alpha = 0 exactly
     // and leaves C and A unchanged.  The verdict is kept while the ray
@@ -1275,7 +1300,7 @@ __device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
 
 // LDSREC: single-block model whose span records and basis tables are copied
 // into LDS once per workgroup.
-template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool GT = MULTI>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   __shared__ float4 tf[256];
@@ -1295,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   }
   stage_tf(r.tf, tf, zpre, wtot);
   const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-  render_tile<P, S, MULTI, PARTIAL>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
+  render_tile<P, S, MULTI, PARTIAL, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
 }
 
 // ------------------------------------------------------------------ K8: isosurface
@@ -1317,7 +1342,7 @@ __device__ __forceinline__ int iso_side(uint32_t bh, float iso) {
   return iso <= blo ? 1 : (iso > bhi ? 0 : -1);
 }
 
-template <int P, Storage S, bool MULTI>
+template <int P, Storage S, bool MULTI, bool GT = MULTI>
 __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r, int tile,
                                          const SpanRec* __restrict__ R,
                                          const float* __restrict__ MT) {
@@ -1348,7 +1373,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, back ? k - 1 : k, x);
-    const Loc Lc = locate<P, MULTI>(m, R, x);
+    const Loc Lc = locate<P, MULTI, GT>(m, R, x);
     const DevBlock* __restrict__ B = MULTI ? m.blocks + Lc.block : &m.b0;
     int c[3];
 #pragma unroll
@@ -1410,8 +1435,8 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
     fprev = f;
     known = need;
     // A super cell on one side of the level: leap to the estimated last
-    // sample inside it (FP32 exit through the uniform-knot position of the
-    // cell faces, less one step), located next by the exact rules.  If that
+    // sample inside it (FP32 exit through the cell faces at their stored
+    // knots, less one step), located next by the exact rules.  If that
     // sample lies in the same cell, so does every sample between (the span
     // index per axis is monotone along the ray), which all have this side;
     // otherwise the leap is undone.
@@ -1424,8 +1449,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
         if (ray.d[a] == 0.0) continue;
         const int cc = Lc.j[a] >> sh;
         const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
-        const float xb =
-            fmaf(__fdividef((float)jb, (float)B->nsp[a]), (float)B->ext[a], (float)B->lo[a]);
+        const float xb = fmaf(face_knot<GT>(R, B, a, jb), (float)B->ext[a], (float)B->lo[a]);
         te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
       }
       kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
@@ -1452,7 +1476,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
 #pragma unroll
       for (int a = 0; a < 3; ++a) xs[a] = ray.o[a] + depth * ray.d[a];
     }
-    const Loc Ls = locate<P, MULTI>(m, R, xs);
+    const Loc Ls = locate<P, MULTI, GT>(m, R, xs);
     const float4 e = evaluate<P, S, !MULTI>(Ls, rs, MT, m.mat_stride, m.imat);
     ++nev;
     const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
@@ -1480,7 +1504,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
   }
 }
 
-template <int P, Storage S, bool MULTI, bool LDSREC>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = MULTI>
 __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   const SpanRec* R = m.rec;
@@ -1497,7 +1521,7 @@ __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
     __syncthreads();
   }
   const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-  iso_tile<P, S, MULTI>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
+  iso_tile<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
 }
 
 // ------------------------------------------------------------------ K6: persistent serving
@@ -1544,16 +1568,22 @@ __global__ __launch_bounds__(kBlock) void serve_k(const DevModel* __restrict__ m
 }
 
 // ------------------------------------------------------------------ launchers
-// Span records and tables go to LDS when they fit this budget.
-constexpr int kLdsRecBytes = 40 * 1024;
+// Span records and tables go to LDS when they fit this budget (non-uniform
+// knots give every span its own basis table: 128 spans per axis take about
+// 54 KB); with the decode window (at most 32 KB) a workgroup stays within
+// the 160 KB of LDS of a CU.
+constexpr int kLdsRecBytes = 64 * 1024;
 
 template <int P, Storage S>
-static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int64_t n, float* out,
+static hipError_t points_p(const DevModel& m, int kind, const float* xyz, int64_t n, float* out,
                            int32_t* dbg, hipStream_t st) {
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  if (multi)
+  if (kind == kKindMulti)
     hipLaunchKernelGGL((decode_points_k<P, S, true>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
                        out, dbg);
+  else if (kind == kKindGraded)
+    hipLaunchKernelGGL((decode_points_k<P, S, false, true>), dim3(grid), dim3(kBlock), 0, st, m, xyz,
+                       n, out, dbg);
   else
     hipLaunchKernelGGL((decode_points_k<P, S, false>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
                        out, dbg);
@@ -1561,8 +1591,9 @@ static hipError_t points_p(const DevModel& m, bool multi, const float* xyz, int6
 }
 
 template <int P, Storage S>
-static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, float* out,
+static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
+  const bool multi = kind == kKindMulti;
   const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
   const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
@@ -1593,7 +1624,7 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
   }
   if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
     const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
-    if (multi)
+    if (kind != kKindPlain)
       hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
     else
       hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out,
@@ -1605,9 +1636,12 @@ static hipError_t sorted_p(const DevModel& m, bool multi, const SortArgs& sa, fl
   const int cap = m.win_max;
   const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   const size_t wb = (size_t)cap * 4;
-  if (multi)
+  if (kind == kKindMulti || (kind == kKindGraded && tabs > (size_t)kLdsRecBytes))
     hipLaunchKernelGGL((decode_tiles_k<P, S, true, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
                        cap, out, dbg);
+  else if (kind == kKindGraded)
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true, true>), dim3(gi), dim3(kBlock), tabs + wb,
+                       st, m, sa, cap, out, dbg);
   else if (tabs <= (size_t)kLdsRecBytes)
     hipLaunchKernelGGL((decode_tiles_k<P, S, false, true>), dim3(gi), dim3(kBlock), tabs + wb, st,
                        m, sa, cap, out, dbg);
@@ -1638,9 +1672,12 @@ static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
 }
 
 template <int P, Storage S>
-static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
+static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
+  // a single block with a non-uniform axis: its own kernel when the tables
+  // fit in LDS, else the multi-block kernels
+  const bool multi = kind == kKindMulti || (kind == kKindGraded && lds > (size_t)kLdsRecBytes);
   // a partial render of a single-block model holds every sample (its
   // region is the model box): it is the full render, whose key is the
   // entry parameter of the model box
@@ -1648,6 +1685,9 @@ static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, h
     hipLaunchKernelGGL((render_k<P, S, true, false, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   else if (multi)
     hipLaunchKernelGGL((render_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else if (kind == kKindGraded)
+    hipLaunchKernelGGL((render_k<P, S, false, true, false, true>), dim3(tiles), dim3(kBlock), lds, st,
+                       m, r);
   else if (lds <= (size_t)kLdsRecBytes)
     hipLaunchKernelGGL((render_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else
@@ -1656,11 +1696,13 @@ static hipError_t render_p(const DevModel& m, bool multi, const RenderArgs& r, h
 }
 
 template <int P, Storage S>
-static hipError_t iso_p(const DevModel& m, bool multi, const RenderArgs& r, hipStream_t st) {
+static hipError_t iso_p(const DevModel& m, int kind, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
-  if (multi)
+  if (kind == kKindMulti || (kind == kKindGraded && lds > (size_t)kLdsRecBytes))
     hipLaunchKernelGGL((iso_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
+  else if (kind == kKindGraded)
+    hipLaunchKernelGGL((iso_k<P, S, false, true, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else if (lds <= (size_t)kLdsRecBytes)
     hipLaunchKernelGGL((iso_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else
@@ -1688,14 +1730,14 @@ static hipError_t iso_p(const DevModel& m, bool multi, const RenderArgs& r, hipS
     default: return hipErrorInvalidValue;                                            \
   }
 
-hipError_t launch_decode_points(const DevModel& m, int p, Storage s, bool multi, const float* xyz,
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, const float* xyz,
                                 int64_t n, float* out, int32_t* dbg, hipStream_t st) {
-  MFA_DISPATCH(points_p, m, multi, xyz, n, out, dbg, st)
+  MFA_DISPATCH(points_p, m, kind, xyz, n, out, dbg, st)
 }
 
-hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, bool multi,
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st) {
-  MFA_DISPATCH(sorted_p, m, multi, sa, out, dbg, st)
+  MFA_DISPATCH(sorted_p, m, kind, sa, out, dbg, st)
 }
 
 hipError_t launch_serve(int p, Storage s, bool multi, const DevModel* models, const ServeReq* reqs,
@@ -1708,14 +1750,14 @@ hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArg
   MFA_DISPATCH(grid_p, m, ga, st)
 }
 
-hipError_t launch_render(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                          hipStream_t st) {
-  MFA_DISPATCH(render_p, m, multi, r, st)
+  MFA_DISPATCH(render_p, m, kind, r, st)
 }
 
-hipError_t launch_iso(const DevModel& m, int p, Storage s, bool multi, const RenderArgs& r,
+hipError_t launch_iso(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                       hipStream_t st) {
-  MFA_DISPATCH(iso_p, m, multi, r, st)
+  MFA_DISPATCH(iso_p, m, kind, r, st)
 }
 
 // ------------------------------------------------------------------ K7: compositing

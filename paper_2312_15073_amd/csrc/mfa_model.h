@@ -31,6 +31,8 @@ struct mfa_model_s {
   uint32_t* d_mcb = nullptr;
   uint32_t* d_scb[2] = {nullptr, nullptr};
   mfa::BucketWin* d_bwin = nullptr;
+  int32_t* d_gtab = nullptr;
+  bool nonuniform = false;   // some axis has non-uniform knots (span guess tables)
   int64_t device_bytes = 0;
   int64_t n_buckets = 0;        // sort buckets (block, tile)
   void* d_ws = nullptr;         // scratch of sorted decodes, grown on demand
@@ -48,6 +50,13 @@ mfa::Storage storage_of(mfa_model m);
 mfa_status check_knots(const double* T, int n, int p, int blk, int axis);
 void default_knots(int n, int p, double* T);
 mfa_status check_device(mfa_model m);
+// Kernel family of a model (kKindPlain / kKindGraded / kKindMulti); the
+// serving kernel has no single-block variant with span guess tables, so a
+// model with a non-uniform axis is served by the multi-block one.
+inline int kernel_kind(mfa_model m) {
+  return m->nblocks > 1 ? mfa::kKindMulti : (m->nonuniform ? mfa::kKindGraded : mfa::kKindPlain);
+}
+inline bool serve_multi(mfa_model m) { return m->nblocks > 1 || m->nonuniform; }
 // Validated kernel arguments of a render of model m (shared by the direct
 // entry point and the server); need_tf = false for the isosurface render,
 // which uses neither the transfer function nor its value range.

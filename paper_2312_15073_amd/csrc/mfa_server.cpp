@@ -119,7 +119,7 @@ struct mfa_server_s {
 
 static Variant variant_of(mfa_model m) {
   if (!m) return Variant{3, Storage::F32, false};
-  return Variant{m->degree, storage_of(m), m->nblocks > 1};
+  return Variant{m->degree, storage_of(m), serve_multi(m)};
 }
 
 // Places the next items of the queued requests, first come first served,

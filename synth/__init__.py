@@ -234,6 +234,27 @@ def model_c2(n: int = 128, p: int = 3, seed: int = 2) -> ModelSpec:
     return single_block_model(ctrl, deg, knots, voxel=1.0 / 511.0)
 
 
+def graded_knot_vector(n: int, p: int, amp: float = 0.75, waves: int = 3) -> np.ndarray:
+    """Clamped knots T[p+j] = phi(j / (n-p)) with the monotone map
+    phi(t) = t - amp sin(2 pi waves t) / (2 pi waves): span widths vary by
+    (1 + amp) / (1 - amp) (7x at amp = 0.75), the shape of knot vectors
+    refined where a field varies most."""
+    t = np.arange(1, n - p, dtype=np.float64) / (n - p)
+    inner = t - amp * np.sin(2 * np.pi * waves * t) / (2 * np.pi * waves)
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def model_c2_graded(n: int = 128, p: int = 3, seed: int = 2) -> ModelSpec:
+    """The 128^3 model of the 64-Gaussian field on graded (non-uniform)
+    knots, a different phase per axis; control points at the Greville
+    abscissae."""
+    field = field_c2(seed)
+    deg = [p, p, p]
+    knots = [graded_knot_vector(n, p, waves=3 + a) for a in range(3)]
+    ctrl = _ctrl_from_field(field, knots, deg, np.zeros(3), np.ones(3), 0.0, None)
+    return single_block_model(ctrl, deg, knots, voxel=1.0 / 511.0)
+
+
 def model_c3_fit48(n_ctrl: int = 48, n_in: int = 128, p: int = 3,
                    seed: int = 1) -> ModelSpec:
     """Compressed model: c1 field sampled on n_in^3 (+1 % noise), fixed-knot

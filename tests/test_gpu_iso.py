@@ -130,6 +130,26 @@ def test_iso_multiblock(mfa, dev, kind):
     assert r["hits"] > 50
 
 
+def test_iso_strongly_graded_knots(mfa, dev):
+    """A single block with strongly graded knots runs the general kernels
+    (span guess tables, leaps through the stored knots)."""
+    from tests.test_gpu_parity import graded_knots
+    p, ns = 3, (33, 27, 30)
+    knots = [graded_knots(n, p, 4, phase=a) for a, n in enumerate(ns)]
+    F = synth.field_c1()
+    g = [synth.greville(T, p, n) for T, n in zip(knots, ns)]
+    X = np.stack(np.meshgrid(*g, indexing="ij"), -1).reshape(-1, 3)
+    model = synth.single_block_model(F.value(X).reshape(ns), [p] * 3, knots, voxel=1.0 / 63)
+    W, H = 56, 44
+    cam = synth.perspective_camera(W, H, az_deg=150, el_deg=20)
+    params = synth.render_params(model)
+    iso = iso_level(model, 0.3)
+    announce("iso strongly graded knots")
+    got, ref = run(mfa, dev, model, cam, params, W, H, iso)
+    r = check_iso(model, cam, params, W, H, iso, got, ref)
+    assert r["hits"] > 100
+
+
 def test_iso_outside_the_value_range_evaluates_nothing(mfa, dev):
     """Every macro cell's bounds lie below (above) the level: no sample is
     evaluated, no surface is hit."""

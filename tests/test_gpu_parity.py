@@ -108,6 +108,38 @@ def test_decode_points_nonunit_box_and_nonuniform_knots(mfa, dev):
     assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)))
 
 
+def graded_knots(n, p, ratio_log2, phase=0):
+    """Clamped knots whose span widths cycle through 2^0 .. 2^-ratio_log2,
+    so that floor(u * nsp) can miss the span by many spans."""
+    w = 2.0 ** -((np.arange(n - p) + phase) % (ratio_log2 + 1))
+    inner = np.cumsum(w)[:-1] / w.sum()
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_decode_points_strongly_graded_knots(mfa, dev, storage):
+    rng = np.random.default_rng(17)
+    p, ns = 3, (41, 37, 29)
+    knots = [graded_knots(n, p, 5, phase=a) for a, n in enumerate(ns)]
+    P = rng.standard_normal(ns)
+    model = synth.single_block_model(P, [p] * 3, knots)
+    pts = rng.random((3, 50000)).astype(np.float32)
+    for a in range(3):                       # points on knots and one ulp off
+        T = knots[a][p + 1:ns[a]].astype(np.float32)
+        pts[a, :len(T)] = T
+        pts[a, len(T):2 * len(T)] = np.nextafter(T, np.float32(0))
+    announce(f"decode_points strongly graded knots {storage}")
+    with mfa.Model(model, storage) as M:
+        out, dbg = mfa.decode_points(M, to_dev(pts, dev), dbg=True)
+        srt = mfa.decode_points(M, to_dev(pts, dev), sorted_order=True)
+        out, dbg, srt = out.cpu().numpy(), dbg.cpu().numpy(), srt.cpu().numpy()
+    qP = quant.stored_values(P, storage) if storage != "f32" else P
+    ref = oracle_points(synth.single_block_model(qP, [p] * 3, knots), pts.T)
+    np.testing.assert_array_equal(dbg[:, :3], ref["spans"])
+    assert_values_close(out, ref["f"], ref["grad"], np.max(np.abs(P)))
+    np.testing.assert_array_equal(srt, out)                          # same sums in both orders
+
+
 # ------------------------------------------------------------------ grid
 def test_decode_grid_c1_full(mfa, dev, c1):
     ax = [synth.grid_axis(64)] * 3
@@ -197,10 +229,9 @@ def test_render_c1_axis_aligned_rays(mfa, dev, c1):
 
 
 def test_render_graded_knots(mfa, dev):
-    # Knots crowded towards 0: the leap targets over transparent super
-    # cells, estimated from uniform knot positions, miss for many rays, so
-    # leaps are undone and cells crossed sample by sample; the image, the
-    # sample counts and the FP32 replay must still match.
+    # Knots crowded towards 0: the model runs the general kernels (span
+    # guess tables; leap targets through the stored knots of the cell
+    # faces); the image, the sample counts and the FP32 replay must match.
     p = 3
     ns = (20, 26, 17)
     knots = [np.concatenate([np.zeros(p + 1), np.linspace(0, 1, n - p + 1)[1:-1] ** 2,
