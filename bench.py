@@ -151,13 +151,14 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single128",
                     choices=["single128", "multiblock", "serving", "points", "encode", "encode_adaptive",
-                             "composite", "iso", "graded"],
+                             "composite", "iso", "graded", "quality"],
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
                          "serving: open-loop request trace over three resident models; "
                          "points: point decode alone, input order vs block/tile-sorted order; "
                          "encode: least-squares fit of a 512^3 sample grid to 192^3 control points; "
                          "encode_adaptive: the 512^3 grid fitted with knot insertion to 1e-4; "
+                         "quality: Marschner-Lobb frames, MFA vs local filters, PSNR vs analytic; "
                          "graded: the default step on the 128^3 model with graded knots; "
                          "iso: first-hit isosurface of the 128^3 model's 1024^2 frame; "
                          "composite: 8 octant partial renders of the 8x8x8-block frame + over")
@@ -189,6 +190,8 @@ def main(argv=None):
         return run_composite(args)
     if args.workload == "iso":
         return run_iso(args)
+    if args.workload == "quality":
+        return run_quality(args)
     if args.workload == "graded":
         if args.steps is None:
             args.steps = 20
@@ -768,6 +771,104 @@ def run_iso(args):
                      "frac_unpacked_fp32": tf / PEAK_FP32_ISSUABLE_TFLOPS,
                      "kernel": "iso_k", "flop_per_launch": flop},
         "cpu_baseline": cpu}), flush=True)
+    return 0
+
+
+# ------------------------------------------------------------------ quality study workload
+QUALITY_N, QUALITY_FRAME = 256, 768
+
+
+def _psnr8(img, ref):
+    """PSNR (dB) of two premultiplied RGBA frames over black, as 8-bit RGB
+    levels: 10 log10(255^2 / MSE)."""
+    a = np.rint(np.clip(img[..., :3], 0.0, 1.0) * 255.0)
+    b = np.rint(np.clip(ref[..., :3], 0.0, 1.0) * 255.0)
+    m = float(np.mean((a - b) ** 2))
+    return (float("inf") if m == 0.0 else 10.0 * np.log10(255.0 ** 2 / m)), m
+
+
+def run_quality(args):
+    """Rendering quality and speed on the Marschner-Lobb function (the
+    paper's Sec. V-A1 and Table II setting): 256^3 FP32 samples on [0, 7]^3;
+    768^2 perspective frames of the analytic field (ground truth), of the
+    samples through the trilinear, Catmull-Rom and cubic B-spline filters,
+    and of MFA models (degree 2) fitted to the samples with 256^3 and 128^3
+    control points; PSNR of each against the ground truth, ms per frame."""
+    steps = 5 if args.steps is None else args.steps
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    N, S = QUALITY_N, QUALITY_FRAME
+    lo, hi = (0.0, 0.0, 0.0), (7.0, 7.0, 7.0)
+    vol = torch.as_tensor(synth.marschner_lobb_samples(N)).to(dev)
+    cam = synth.perspective_camera(S, S, az_deg=30.0, el_deg=35.0, dist=15.0, centre=(3.5, 3.5, 3.5))
+    params = dict(tf=synth.tf_table_A(), vmin=np.float32(0.0), vmax=np.float32(1.0),
+                  step=0.5 * 7.0 / (N - 1), max_samples=2048, ert_alpha=np.float32(0.99),
+                  ka=np.float32(0.3), kd=np.float32(0.6), ks=np.float32(0.3),
+                  g0=np.float32(0.01), shininess=16)
+    tf = torch.as_tensor(params["tf"], device=dev)
+    out = torch.empty((S, S, 4), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+
+    def vol_fn(kind, v):
+        return lambda: mfa.render_volume(v, kind, lo, hi, cam, params, S, S, dims=(N, N, N),
+                                         tf_dev=tf, out=out, device=dev)
+
+    results = {}
+    ms = timed(vol_fn("marschner_lobb", None))
+    gt = out.cpu().numpy().copy()
+    results["ground truth (analytic, FP32)"] = dict(ms=ms)
+    for kind in ("trilinear", "catmull_rom", "cubic_bspline"):
+        ms = timed(vol_fn(kind, vol))
+        ps, m = _psnr8(out.cpu().numpy(), gt)
+        results[f"{kind} on {N}^3 samples"] = dict(ms=ms, psnr=ps, mse=m, bytes=4 * N ** 3)
+    axis = np.arange(N, dtype=np.float64) / (N - 1)
+    mfa_rows = {}
+    for n in (N, N // 2):
+        P = mfa.encode_grid(vol, [axis] * 3, (2, 2, 2), (n, n, n)).cpu().numpy()
+        spec = synth.single_block_model(P, [2, 2, 2], None, lo=lo, hi=hi, voxel=7.0 / (N - 1))
+        del P
+        with mfa.Model(spec, "f32") as M:
+            _, ns, ne = mfa.render_frame(M, cam, params, S, S, tf_dev=tf, nsamp=True, neval=True,
+                                         device=dev)
+            s_eval = int(ne.sum().item())
+            ms = timed(lambda: mfa.render_frame(M, cam, params, S, S, tf_dev=tf, out=out, device=dev))
+            ps, m = _psnr8(out.cpu().numpy(), gt)
+            info = M.info()
+        key = f"MFA p=2, {n}^3 control points (compression {(N / n) ** 3:.0f})"
+        results[key] = dict(ms=ms, psnr=ps, mse=m, bytes=info["device_bytes"], evaluated=s_eval)
+        mfa_rows[n] = key
+        del spec
+    comp = results[mfa_rows[N // 2]]
+    fl = (flop_per_sample(2) + 54) * comp["evaluated"]
+    tfl = fl / (comp["ms"] * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "PSNR (dB) of a 768^2 Marschner-Lobb frame against the analytic field",
+        "value": comp["psnr"], "unit": "dB", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": comp["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Marschner-Lobb (f_M = 6, alpha = 0.25) on [0, 7]^3 sampled at {N}^3 "
+                               f"FP32, {S}^2 perspective frames; value: MFA with {N // 2}^3 control "
+                               f"points", "methods": results, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": tfl, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tfl / PEAK_FP32_TFLOPS, "traffic": None,
+                     "peak_unpacked_fp32": PEAK_FP32_ISSUABLE_TFLOPS,
+                     "frac_unpacked_fp32": tfl / PEAK_FP32_ISSUABLE_TFLOPS,
+                     "kernel": "render_k (MFA model, 128^3 control points)", "flop_per_launch": fl},
+        "cpu_baseline": None}), flush=True)
     return 0
 
 

@@ -267,6 +267,43 @@ mfa_status mfa_render_iso(mfa_model model, const mfa_camera* camera, const mfa_r
                           float iso, const float rgb[3], int32_t w, int32_t h, float* rgba,
                           double* depth, const mfa_render_debug* dbg, void* stream);
 
+/* Local-filter baselines (the reconstruction filters the paper compares MFA
+ * queries with, Sec. I and Sec. V) and the analytic Marschner-Lobb field
+ * (Sec. V-A1, the ground truth of its quality study), rendered by the same
+ * ray caster: rays, schedule, transfer function, shading, compositing and
+ * termination are those of mfa_render_frame, with the box [lo, hi] in place
+ * of the model box and value + gradient from the volume below.
+ *  samples : device FP32 [dims0][dims1][dims2] (axis 2 fastest), sample
+ *            (i0, i1, i2) at lo + i * h, h = (hi - lo) / (dims - 1); NULL for
+ *            MFA_FIELD_MARSCHNER_LOBB.
+ *  kind    : MFA_FILTER_TRILINEAR (cell c = min(floor(g), dims - 2) of the
+ *            grid coordinate g = clamp((x - lo) / h, 0, dims - 1), weights
+ *            1 - t, t), MFA_FILTER_CATMULL_ROM (cubic interpolation with
+ *            tangents (v[c+1] - v[c-1]) / 2, samples c-1 .. c+2),
+ *            MFA_FILTER_CUBIC_BSPLINE (the uniform cubic B-spline filter on
+ *            the samples, approximating, same stencil), stencil indices
+ *            outside the grid repeating the edge sample; gradients are the
+ *            analytic derivatives of the filter's polynomial (1 / h per
+ *            axis).  MFA_FIELD_MARSCHNER_LOBB: F = (1 - sin(pi z/2) +
+ *            a (1 + cos(2 pi f cos(pi r/2)))) / (2 (1 + a)), r = |(x, y)|,
+ *            f = 6, a = 0.25, and its analytic gradient, in FP32.
+ *  dims    : >= 2 per axis (also for the analytic field: they set the
+ *            default step, half the smallest spacing h).
+ * The debug outputs are those of mfa_render_frame (every sample up to the
+ * termination is evaluated).  Errors: MFA_E_ARG for a bad kind, box or
+ * dims, null samples, and as mfa_render_frame.                             */
+enum { MFA_FILTER_TRILINEAR = 0, MFA_FILTER_CATMULL_ROM = 1, MFA_FILTER_CUBIC_BSPLINE = 2,
+       MFA_FIELD_MARSCHNER_LOBB = 3 };
+typedef struct {
+  const float* samples;
+  int32_t dims[3];
+  double lo[3], hi[3];
+  int32_t kind;
+} mfa_volume_desc;
+mfa_status mfa_render_volume(const mfa_volume_desc* volume, const mfa_camera* camera,
+                             const mfa_render_params* params, int32_t w, int32_t h, float* rgba,
+                             const mfa_render_debug* dbg, void* stream);
+
 /* Object-space split (Sec. IV-A4: each node ray-casts the blocks it holds
  * into a partially rendered image; Sec. IV-A5: the partial images are
  * combined by "over" in depth order).

@@ -470,6 +470,59 @@ def render_frame(model: Model, cam: dict, params: dict, w: int, h: int, tf_dev=N
     return (out, *extra) if extra else out
 
 
+FILTERS = {"trilinear": L.FILTER_TRILINEAR, "catmull_rom": L.FILTER_CATMULL_ROM,
+           "cubic_bspline": L.FILTER_CUBIC_BSPLINE, "marschner_lobb": L.FIELD_MARSCHNER_LOBB}
+
+
+def render_volume(samples, kind: str, lo, hi, cam: dict, params: dict, w: int, h: int, dims=None,
+                  tf_dev=None, out=None, nsamp: bool = False, alpha: bool = False, stream=None,
+                  device=None):
+    """Ray-casts a volume of samples (CUDA float32 (N0, N1, N2) on the grid
+    lo + i (hi - lo) / (N - 1)) through the local filter kind ("trilinear",
+    "catmull_rom", "cubic_bspline"), or the analytic Marschner-Lobb field
+    ("marschner_lobb", samples None, dims giving the default step).  Returns
+    rgba (h, w, 4) and optional int32 (h, w, 2) sample counts and float32
+    (h, w, max_samples) opacities, as render_frame."""
+    torch = _torch()
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    d = L.VolumeDesc()
+    d.kind = FILTERS[kind]
+    if samples is not None:
+        dims = tuple(int(v) for v in samples.shape)
+        d.samples = _dev_ptr(samples, torch.float32, dims, "samples").value
+    else:
+        d.samples = None
+    for a in range(3):
+        d.dims[a] = int(dims[a])
+        d.lo[a] = float(lo[a])
+        d.hi[a] = float(hi[a])
+    if tf_dev is None:
+        tf_dev = torch.as_tensor(np.ascontiguousarray(params["tf"], dtype=np.float32), device=dev)
+    cobj = make_camera(cam)
+    pobj = make_params(params, tf_dev)
+    if out is None:
+        out = torch.empty((h, w, 4), dtype=torch.float32, device=dev)
+    po = _dev_ptr(out, torch.float32, (h, w, 4), "out")
+    dbg = None
+    extra = []
+    if nsamp or alpha:
+        dbg = L.RenderDebug()
+        if nsamp:
+            ns = torch.zeros((h, w, 2), dtype=torch.int32, device=dev)
+            dbg.nsamp = ns.data_ptr()
+            extra.append(ns)
+        if alpha:
+            ms = int(params["max_samples"])
+            al = torch.zeros((h, w, ms), dtype=torch.float32, device=dev)
+            dbg.alpha = al.data_ptr()
+            dbg.alpha_stride = ms
+            extra.append(al)
+    L.check(L.lib().mfa_render_volume(C.byref(d), C.byref(cobj), C.byref(pobj), int(w), int(h), po,
+                                      C.byref(dbg) if dbg is not None else None,
+                                      _stream_ptr(stream)))
+    return (out, *extra) if extra else out
+
+
 class Server:
     """Request loop over resident models (mfa_server_*).
 

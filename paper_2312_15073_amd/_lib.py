@@ -55,6 +55,14 @@ class RenderDebug(C.Structure):
                 ("alpha_stride", C.c_int32)]
 
 
+class VolumeDesc(C.Structure):
+    _fields_ = [("samples", C.c_void_p), ("dims", C.c_int32 * 3), ("lo", D3), ("hi", D3),
+                ("kind", C.c_int32)]
+
+
+FILTER_TRILINEAR, FILTER_CATMULL_ROM, FILTER_CUBIC_BSPLINE, FIELD_MARSCHNER_LOBB = 0, 1, 2, 3
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("queue_cap", C.c_int32),
                 ("max_batch_items", C.c_int32), ("flags", C.c_uint32), ("fake_item_us", C.c_double)]
@@ -94,6 +102,9 @@ SIGNATURES = {
     "mfa_render_iso": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams), C.c_float,
                                  C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                  C.POINTER(RenderDebug), C.c_void_p]),
+    "mfa_render_volume": (C.c_int, [C.POINTER(VolumeDesc), C.POINTER(Camera), C.POINTER(RenderParams),
+                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(RenderDebug),
+                                    C.c_void_p]),
     "mfa_composite_over": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "mfa_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),

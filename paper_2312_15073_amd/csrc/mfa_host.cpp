@@ -28,6 +28,7 @@ hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const Re
 hipError_t launch_composite(const CompositeArgs& c, hipStream_t st);
 hipError_t launch_iso(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                       hipStream_t st);
+hipError_t launch_volume(const VolArgs& v, int kind, const RenderArgs& r, hipStream_t st);
 }  // namespace mfa
 
 using namespace mfa;
@@ -799,10 +800,11 @@ extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3]
 }
 
 // ------------------------------------------------------------------ render
-mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
-                            int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
-                            RenderArgs* out, bool need_tf) {
-  if (!m || !cam || !rp || !rgba) return fail(MFA_E_ARG, "null argument");
+// Validated kernel arguments of a render; voxel: the default step is half of it.
+static mfa_status render_args_core(double voxel, const mfa_camera* cam, const mfa_render_params* rp,
+                                   int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                                   RenderArgs* out, bool need_tf) {
+  if (!cam || !rp || !rgba) return fail(MFA_E_ARG, "null argument");
   if (w < 1 || h < 1 || w > 16384 || h > 16384) return fail(MFA_E_ARG, "image %dx%d out of range", w, h);
   if (cam->kind != MFA_ORTHO && cam->kind != MFA_PERSPECTIVE) return fail(MFA_E_ARG, "camera kind");
   for (int a = 0; a < 3; ++a)
@@ -812,7 +814,7 @@ mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render
   if (need_tf && !rp->tf_rgba) return fail(MFA_E_ARG, "tf_rgba is null");
   if (need_tf && (!(rp->vmin < rp->vmax) || !std::isfinite(rp->vmin) || !std::isfinite(rp->vmax)))
     return fail(MFA_E_ARG, "need finite vmin < vmax");
-  const double step = rp->step == 0.0 ? 0.5 * m->voxel : rp->step;
+  const double step = rp->step == 0.0 ? 0.5 * voxel : rp->step;
   if (!(step > 0.0) || !is_fin(step)) return fail(MFA_E_ARG, "step must be > 0");
   if (rp->max_samples < 1) return fail(MFA_E_ARG, "max_samples must be >= 1");
   if (!(rp->g0 > 0.f) || !std::isfinite(rp->g0)) return fail(MFA_E_ARG, "g0 must be > 0");
@@ -852,6 +854,44 @@ mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render
   r.step = step;
   r.inv_step = 1.0 / step;
   *out = r;
+  return MFA_OK;
+}
+
+mfa_status make_render_args(mfa_model m, const mfa_camera* cam, const mfa_render_params* rp,
+                            int32_t w, int32_t h, float* rgba, const mfa_render_debug* dbg,
+                            RenderArgs* out, bool need_tf) {
+  if (!m) return fail(MFA_E_ARG, "null argument");
+  return render_args_core(m->voxel, cam, rp, w, h, rgba, dbg, out, need_tf);
+}
+
+extern "C" mfa_status mfa_render_volume(const mfa_volume_desc* vol, const mfa_camera* cam,
+                                        const mfa_render_params* rp, int32_t w, int32_t h,
+                                        float* rgba, const mfa_render_debug* dbg, void* stream) {
+  if (!vol) return fail(MFA_E_ARG, "null volume");
+  if (vol->kind < MFA_FILTER_TRILINEAR || vol->kind > MFA_FIELD_MARSCHNER_LOBB)
+    return fail(MFA_E_ARG, "unknown volume kind %d", vol->kind);
+  VolArgs v{};
+  double hmin = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (!is_fin(vol->lo[a]) || !is_fin(vol->hi[a]) || !(vol->lo[a] < vol->hi[a]))
+      return fail(MFA_E_ARG, "axis %d: need finite lo < hi", a);
+    if (vol->dims[a] < 2 || vol->dims[a] > (1 << 16))
+      return fail(MFA_E_ARG, "axis %d: %d samples outside [2, 65536]", a, vol->dims[a]);
+    v.n[a] = vol->dims[a];
+    v.lo[a] = vol->lo[a];
+    v.hi[a] = vol->hi[a];
+    v.h[a] = (vol->hi[a] - vol->lo[a]) / (double)(vol->dims[a] - 1);
+    v.inv_h[a] = (float)(1.0 / v.h[a]);
+    hmin = std::fmin(hmin, v.h[a]);
+  }
+  if (vol->kind != MFA_FIELD_MARSCHNER_LOBB && !vol->samples)
+    return fail(MFA_E_ARG, "null samples");
+  v.v = vol->samples;
+  RenderArgs r;
+  mfa_status st = render_args_core(hmin, cam, rp, w, h, rgba, dbg, &r, true);
+  if (st != MFA_OK) return st;
+  hipError_t e = launch_volume(v, vol->kind, r, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "volume render launch");
   return MFA_OK;
 }
 

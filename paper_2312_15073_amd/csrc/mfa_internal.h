@@ -234,6 +234,16 @@ struct RenderArgs {
   float iso_rgb[3];
 };
 
+// Volume of samples on a uniform grid rendered through a local filter:
+// sample (i0, i1, i2) at lo + i * h, h = (hi - lo) / (n - 1) (FP64 on the
+// host); v = nullptr for the analytic Marschner-Lobb field.
+struct VolArgs {
+  const float* v;
+  int32_t n[3];
+  double lo[3], hi[3], h[3];
+  float inv_h[3];
+};
+
 // Depth-ordered compositing of up to kMaxPartials partial images.
 constexpr int kMaxPartials = 16;
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include "mfa.h"
 #include "mfa_internal.h"
 
 namespace mfa {
@@ -965,7 +966,8 @@ struct Ray {
   int K;
 };
 
-__device__ __forceinline__ Ray make_ray(const DevModel& m, const RenderArgs& r, int i, int j) {
+__device__ __forceinline__ Ray make_ray_box(const double (&blo)[3], const double (&bhi)[3],
+                                            const RenderArgs& r, int i, int j) {
 #pragma clang fp contract(off)
   Ray ray;
   const double px = (double)(2 * i + 1 - r.w) * r.sx;
@@ -985,11 +987,11 @@ __device__ __forceinline__ Ray make_ray(const DevModel& m, const RenderArgs& r, 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (ray.d[a] == 0.0) {
-      miss |= (ray.o[a] < m.box_lo[a]) || (ray.o[a] > m.box_hi[a]);
+      miss |= (ray.o[a] < blo[a]) || (ray.o[a] > bhi[a]);
     } else {
       const double inv = 1.0 / ray.d[a];
-      const double t1 = (m.box_lo[a] - ray.o[a]) * inv;
-      const double t2 = (m.box_hi[a] - ray.o[a]) * inv;
+      const double t1 = (blo[a] - ray.o[a]) * inv;
+      const double t2 = (bhi[a] - ray.o[a]) * inv;
       tn = fmax(tn, fmin(t1, t2));
       tf = fmin(tf, fmax(t1, t2));
     }
@@ -1002,6 +1004,10 @@ __device__ __forceinline__ Ray make_ray(const DevModel& m, const RenderArgs& r, 
     ray.K = (int)fmin(q, (double)r.max_samples);
   }
   return ray;
+}
+
+__device__ __forceinline__ Ray make_ray(const DevModel& m, const RenderArgs& r, int i, int j) {
+  return make_ray_box(m.box_lo, m.box_hi, r, i, j);
 }
 
 __device__ __forceinline__ void sample_point(const Ray& ray, double step, int k, double (&x)[3]) {
@@ -1092,6 +1098,42 @@ __device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, co
   const float bhi = __half2float(__ushort_as_half((unsigned short)(bh >> 16)));
   return zpre[tf_entry(tf_coord(bhi, r.vmin, r.inv_range)) + 2] ==
          zpre[tf_entry(tf_coord(blo, r.vmin, r.inv_range))];
+}
+
+// Transfer function, headlight Phong and one front-to-back "over" step of a
+// sample with value and world gradient e (f, df/dx, df/dy, df/dz); returns
+// the sample's opacity.
+__device__ __forceinline__ float shade_over(const float4 e, const float (&L)[3], const float4* tf,
+                                            const RenderArgs& r, float& C0, float& C1, float& C2,
+                                            float& A) {
+  const float s = tf_coord(e.x, r.vmin, r.inv_range);
+  const int i0 = tf_entry(s);
+  const float w = s - (float)i0;
+  const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+  const float cr = fmaf(w, c1.x - c0.x, c0.x);
+  const float cg = fmaf(w, c1.y - c0.y, c0.y);
+  const float cb = fmaf(w, c1.z - c0.z, c0.z);
+  const float alpha = fmaf(w, c1.w - c0.w, c0.w);
+  // headlight Phong, two-sided; 1 / max(|g|, g0) as one hardware
+  // reciprocal square root of max(|g|^2, g0^2)
+  const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
+  const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
+  const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
+  float spec = 1.f, bse = diff;
+  for (int ex = r.shininess; ex; ex >>= 1) {
+    if (ex & 1) spec *= bse;
+    bse *= bse;
+  }
+  const float shade = fmaf(r.kd, diff, r.ka);
+  const float ks = r.ks * spec;
+  // front-to-back over; the opacity update rounds each operation
+  const float om = __fsub_rn(1.f, A);
+  const float ta = __fmul_rn(om, alpha);
+  C0 = fmaf(ta, fmaf(cr, shade, ks), C0);
+  C1 = fmaf(ta, fmaf(cg, shade, ks), C1);
+  C2 = fmaf(ta, fmaf(cb, shade, ks), C2);
+  A = __fadd_rn(A, ta);
+  return alpha;
 }
 
 // Transparent stretch in front of a ray's first visible super cell, lane by
@@ -1240,33 +1282,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     if (!empty) {
       const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat);
       ++nev;
-      const float s = tf_coord(e.x, r.vmin, r.inv_range);
-      const int i0 = tf_entry(s);
-      const float w = s - (float)i0;
-      const float4 c0 = tf[i0], c1 = tf[i0 + 1];
-      const float cr = fmaf(w, c1.x - c0.x, c0.x);
-      const float cg = fmaf(w, c1.y - c0.y, c0.y);
-      const float cb = fmaf(w, c1.z - c0.z, c0.z);
-      alpha = fmaf(w, c1.w - c0.w, c0.w);
-      // headlight Phong, two-sided; 1 / max(|g|, g0) as one hardware
-      // reciprocal square root of max(|g|^2, g0^2)
-      const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
-      const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
-      const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
-      float spec = 1.f, bse = diff;
-      for (int ex = r.shininess; ex; ex >>= 1) {
-        if (ex & 1) spec *= bse;
-        bse *= bse;
-      }
-      const float shade = fmaf(r.kd, diff, r.ka);
-      const float ks = r.ks * spec;
-      // front-to-back over; the opacity update rounds each operation
-      const float om = __fsub_rn(1.f, A);
-      const float ta = __fmul_rn(om, alpha);
-      C0 = fmaf(ta, fmaf(cr, shade, ks), C0);
-      C1 = fmaf(ta, fmaf(cg, shade, ks), C1);
-      C2 = fmaf(ta, fmaf(cb, shade, ks), C2);
-      A = __fadd_rn(A, ta);
+      alpha = shade_over(e, L, tf, r, C0, C1, C2, A);
     }
     used = k + 1;
     if (r.alpha) r.alpha[pid * r.alpha_stride + k] = alpha;
@@ -1524,6 +1540,137 @@ __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
   iso_tile<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
 }
 
+// ------------------------------------------------------------------ K9: local-filter volumes
+// The same ray caster over a volume of samples reconstructed by a local
+// filter (the baselines the paper compares MFA queries with), or over the
+// analytic Marschner-Lobb field (its quality study's ground truth).  Every
+// sample up to the termination is evaluated (no empty-space skipping).
+template <int KIND, int K>
+__device__ __forceinline__ void filter_weights(float t, float (&w)[K], float (&dw)[K]) {
+  if constexpr (KIND == MFA_FILTER_TRILINEAR) {
+    w[0] = 1.f - t;
+    w[1] = t;
+    dw[0] = -1.f;
+    dw[1] = 1.f;
+  } else if constexpr (KIND == MFA_FILTER_CATMULL_ROM) {
+    const float t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5f * (-t3 + 2.f * t2 - t);
+    w[1] = 0.5f * (3.f * t3 - 5.f * t2 + 2.f);
+    w[2] = 0.5f * (-3.f * t3 + 4.f * t2 + t);
+    w[3] = 0.5f * (t3 - t2);
+    dw[0] = 0.5f * (-3.f * t2 + 4.f * t - 1.f);
+    dw[1] = 0.5f * (9.f * t2 - 10.f * t);
+    dw[2] = 0.5f * (-9.f * t2 + 8.f * t + 1.f);
+    dw[3] = 0.5f * (3.f * t2 - 2.f * t);
+  } else {
+    const float t2 = t * t, t3 = t2 * t, s = 1.f - t;
+    constexpr float sixth = 1.f / 6.f;
+    w[0] = s * s * s * sixth;
+    w[1] = (3.f * t3 - 6.f * t2 + 4.f) * sixth;
+    w[2] = (-3.f * t3 + 3.f * t2 + 3.f * t + 1.f) * sixth;
+    w[3] = t3 * sixth;
+    dw[0] = -0.5f * s * s;
+    dw[1] = (9.f * t2 - 12.f * t) * sixth;
+    dw[2] = (-9.f * t2 + 6.f * t + 3.f) * sixth;
+    dw[3] = 0.5f * t2;
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ float4 volume_field(const VolArgs& v, const double (&x)[3]) {
+  if constexpr (KIND == MFA_FIELD_MARSCHNER_LOBB) {
+    constexpr float kPi = 3.14159265358979f, kFm = 6.f, kAlpha = 0.25f;
+    constexpr float kDen = 2.f * (1.f + kAlpha);
+    const float X = (float)x[0], Y = (float)x[1], Z = (float)x[2];
+    const float rr = sqrtf(X * X + Y * Y);
+    const float inner = 2.f * kPi * kFm * cosf(0.5f * kPi * rr);
+    const float f = (1.f - sinf(0.5f * kPi * Z) + kAlpha * (1.f + cosf(inner))) / kDen;
+    const float drho = sinf(inner) * (2.f * kPi * kFm) * sinf(0.5f * kPi * rr) * (0.5f * kPi);
+    const float q = rr > 0.f ? kAlpha * drho / (rr * kDen) : 0.f;
+    return make_float4(f, q * X, q * Y, -0.5f * kPi * cosf(0.5f * kPi * Z) / kDen);
+  } else {
+    constexpr int K = KIND == MFA_FILTER_TRILINEAR ? 2 : 4;
+    constexpr int OFF = KIND == MFA_FILTER_TRILINEAR ? 0 : -1;
+    int idx[3][K];
+    float w[3][K], dw[3][K];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double g = clampd((x[a] - v.lo[a]) / v.h[a], 0.0, (double)(v.n[a] - 1));
+      const int c = min((int)floor(g), v.n[a] - 2);
+      filter_weights<KIND, K>((float)(g - (double)c), w[a], dw[a]);
+#pragma unroll
+      for (int q = 0; q < K; ++q) idx[a][q] = min(max(c + OFF + q, 0), v.n[a] - 1);
+    }
+    float f = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      float y = 0.f, yy = 0.f, yz = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float* row = v.v + ((int64_t)idx[0][i] * v.n[1] + idx[1][j]) * (int64_t)v.n[2];
+        float z = 0.f, zd = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float sv = row[idx[2][k]];
+          z = fmaf(w[2][k], sv, z);
+          zd = fmaf(dw[2][k], sv, zd);
+        }
+        y = fmaf(w[1][j], z, y);
+        yy = fmaf(dw[1][j], z, yy);
+        yz = fmaf(w[1][j], zd, yz);
+      }
+      f = fmaf(w[0][i], y, f);
+      fx = fmaf(dw[0][i], y, fx);
+      fy = fmaf(w[0][i], yy, fy);
+      fz = fmaf(w[0][i], yz, fz);
+    }
+    return make_float4(f, fx * v.inv_h[0], fy * v.inv_h[1], fz * v.inv_h[2]);
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void volume_k(VolArgs v, RenderArgs r) {
+  __shared__ float4 tf[256];
+  __shared__ int zpre[257];
+  __shared__ int wtot[kBlock / kWave];
+  stage_tf(r.tf, tf, zpre, wtot);
+  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+  const int tile = frame_tile(blockIdx.x, tx, ty);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
+  const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool pix = i < r.w && j < r.h;
+  Ray ray;
+  ray.K = 0;
+  if (pix) ray = make_ray_box(v.lo, v.hi, r, i, j);
+  float L[3] = {0.f, 0.f, 0.f};
+  if (pix) {
+    const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L[a] = (float)(-ray.d[a] / dn);
+  }
+  const int64_t pid = (int64_t)j * r.w + i;
+  float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
+  int used = 0;
+  bool done = false;
+  for (int k = 0;; ++k) {
+    const bool act = pix && !done && k < ray.K;
+    if (__ballot(act) == 0) break;                 // whole wave finished
+    if (!act) continue;
+    double x[3];
+    sample_point(ray, r.step, k, x);
+    const float alpha = shade_over(volume_field<KIND>(v, x), L, tf, r, C0, C1, C2, A);
+    used = k + 1;
+    if (r.alpha) r.alpha[pid * r.alpha_stride + k] = alpha;
+    done = A >= r.ert_alpha;
+  }
+  if (pix) {
+    reinterpret_cast<float4*>(r.rgba)[pid] = make_float4(C0, C1, C2, A);
+    if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, used);
+    if (r.neval) r.neval[pid] = used;
+  }
+}
+
 // ------------------------------------------------------------------ K6: persistent serving
 // Each workgroup takes work items from an atomic cursor until the batch is
 // exhausted (every wave reaches the exit once the cursor passes n_items).
@@ -1758,6 +1905,27 @@ hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const Re
 hipError_t launch_iso(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                       hipStream_t st) {
   MFA_DISPATCH(iso_p, m, kind, r, st)
+}
+
+hipError_t launch_volume(const VolArgs& v, int kind, const RenderArgs& r, hipStream_t st) {
+  const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  switch (kind) {
+    case MFA_FILTER_TRILINEAR:
+      hipLaunchKernelGGL(volume_k<MFA_FILTER_TRILINEAR>, dim3(tiles), dim3(kBlock), 0, st, v, r);
+      break;
+    case MFA_FILTER_CATMULL_ROM:
+      hipLaunchKernelGGL(volume_k<MFA_FILTER_CATMULL_ROM>, dim3(tiles), dim3(kBlock), 0, st, v, r);
+      break;
+    case MFA_FILTER_CUBIC_BSPLINE:
+      hipLaunchKernelGGL(volume_k<MFA_FILTER_CUBIC_BSPLINE>, dim3(tiles), dim3(kBlock), 0, st, v, r);
+      break;
+    case MFA_FIELD_MARSCHNER_LOBB:
+      hipLaunchKernelGGL(volume_k<MFA_FIELD_MARSCHNER_LOBB>, dim3(tiles), dim3(kBlock), 0, st, v, r);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ K7: compositing

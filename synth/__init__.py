@@ -234,6 +234,19 @@ def model_c2(n: int = 128, p: int = 3, seed: int = 2) -> ModelSpec:
     return single_block_model(ctrl, deg, knots, voxel=1.0 / 511.0)
 
 
+def marschner_lobb_samples(N: int, lo=(0.0, 0.0, 0.0), hi=(7.0, 7.0, 7.0), fm: float = 6.0,
+                           alpha: float = 0.25) -> np.ndarray:
+    """FP32 samples (N, N, N) of the Marschner-Lobb test function (the
+    paper's Sec. V-A1 definition, f_M = 6, alpha = 0.25, on its printed
+    domain [0, 7]^3) at x_i = lo + i (hi - lo) / (N - 1), axis 2 fastest."""
+    ax = [lo[a] + np.arange(N, dtype=np.float64) * ((hi[a] - lo[a]) / (N - 1)) for a in range(3)]
+    r = np.sqrt(ax[0][:, None] ** 2 + ax[1][None, :] ** 2)                  # (N, N)
+    rho = np.cos(2.0 * np.pi * fm * np.cos(0.5 * np.pi * r))
+    zpart = 1.0 - np.sin(0.5 * np.pi * ax[2])                               # (N,)
+    F = (zpart[None, None, :] + alpha * (1.0 + rho)[:, :, None]) / (2.0 * (1.0 + alpha))
+    return F.astype(np.float32)
+
+
 def graded_knot_vector(n: int, p: int, amp: float = 0.75, waves: int = 3) -> np.ndarray:
     """Clamped knots T[p+j] = phi(j / (n-p)) with the monotone map
     phi(t) = t - amp sin(2 pi waves t) / (2 pi waves): span widths vary by

@@ -213,3 +213,34 @@ def test_encode_adaptive_workspace_size_and_rejections():
     bad[0][2] = -0.25
     st, msg = call(tabs=bad)
     assert st == L.MFA_E_ARG and "outside [0, 1]" in msg
+
+
+def test_render_volume_rejects_bad_arguments_before_device_work():
+    lib = L.lib()
+    cam = L.Camera()
+    cam.kind = 1
+    for a in range(3):
+        cam.eye[a], cam.forward[a], cam.right[a], cam.up[a] = 0.5, float(a == 2), float(a == 0), float(a == 1)
+    cam.sx = cam.sy = 0.01
+    rp = L.RenderParams()
+    rp.tf_rgba = 0x1000
+    rp.vmin, rp.vmax, rp.step, rp.max_samples, rp.ert_alpha = 0.0, 1.0, 0.01, 64, 0.99
+    rp.ka, rp.kd, rp.ks, rp.g0, rp.shininess = 0.3, 0.6, 0.3, 0.01, 16
+
+    def call(kind=0, dims=(8, 8, 8), lo=(0, 0, 0), hi=(1, 1, 1), samples=0x1000, w=8):
+        d = L.VolumeDesc()
+        d.samples, d.kind = samples, kind
+        for a in range(3):
+            d.dims[a], d.lo[a], d.hi[a] = dims[a], lo[a], hi[a]
+        return lib.mfa_render_volume(C.byref(d), C.byref(cam), C.byref(rp), w, 8, C.c_void_p(0x1000),
+                                     None, None)
+
+    assert call(kind=4) == L.MFA_E_ARG
+    assert call(kind=-1) == L.MFA_E_ARG
+    assert call(dims=(8, 1, 8)) == L.MFA_E_ARG
+    assert call(lo=(0, 1, 0)) == L.MFA_E_ARG                       # lo >= hi on axis 1
+    assert call(hi=(1, float("inf"), 1)) == L.MFA_E_ARG
+    assert call(samples=None) == L.MFA_E_ARG                       # a filter needs samples
+    assert call(w=0) == L.MFA_E_ARG
+    assert lib.mfa_render_volume(None, C.byref(cam), C.byref(rp), 8, 8, C.c_void_p(0x1000), None,
+                                 None) == L.MFA_E_ARG

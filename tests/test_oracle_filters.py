@@ -157,3 +157,10 @@ def test_support_and_convex_hull(kind):
         assert f1[0] == pytest.approx(f0[q], abs=1e-12)
         if kind != of.CATMULL_ROM:
             assert V[sl].min() - 1e-12 <= f0[q] <= V[sl].max() + 1e-12
+
+
+def test_input_generator_samples_equal_the_oracle_function():
+    import synth
+    for N in (5, 16):
+        np.testing.assert_array_equal(synth.marschner_lobb_samples(N),
+                                      of.ml_samples(N).astype(np.float32))
