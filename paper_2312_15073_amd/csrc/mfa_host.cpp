@@ -201,7 +201,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 
 static void free_model(mfa_model m) {
   if (!m) return;
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_ws};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -368,7 +368,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   const int es = elem_size(storage);
   std::vector<DevBlock> dblk(nb);
   std::vector<SpanRec> recs;
-  std::vector<int32_t> gtab;
+  std::vector<int32_t> gtab, gmeta(6 * nb, 0);
   std::vector<float> mats;
   std::map<std::vector<float>, int> mat_ids;
   const std::vector<float> canon = uniform_table(p);
@@ -440,13 +440,12 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
         uniform &= T[p + j] == (double)j / (double)nsp;
         if (T[p + j + 1] > T[p + j]) hmin = std::fmin(hmin, T[p + j + 1] - T[p + j]);
       }
-      D.gtab_off[a] = -1;
-      D.gtab_n[a] = 0;
+      gmeta[6 * b + a] = -1;
       if (!uniform) {
         const int64_t G = std::min<int64_t>(std::max<int64_t>((int64_t)std::ceil(2.0 / hmin), nsp),
                                             std::min<int64_t>(64ll * nsp, 1ll << 20));
-        D.gtab_off[a] = (int32_t)gtab.size();
-        D.gtab_n[a] = (int32_t)G;
+        gmeta[6 * b + a] = (int32_t)gtab.size();
+        gmeta[6 * b + 3 + a] = (int32_t)G;
         for (int64_t g = 0; g < G; ++g) {
           const double u = (double)g / (double)G;
           const int s = (int)(std::upper_bound(T.data() + p, T.data() + n, u) - T.data()) - 1;
@@ -619,7 +618,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (!bwin.empty() &&
        (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK) ||
       (!gtab.empty() &&
-       (st = upload(&m->d_gtab, gtab.data(), gtab.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK)) {
+       ((st = upload(&m->d_gtab, gtab.data(), gtab.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK ||
+        (st = upload(&m->d_gmeta, gmeta.data(), gmeta.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK))) {
     free_model(m);
     return st;
   }
@@ -653,6 +653,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   }
   dm.bwin = m->d_bwin;
   dm.gtab = m->d_gtab;
+  dm.gmeta = m->d_gmeta;
   dm.win_max = win_max;
   dm.b0 = dblk[0];
   *out = m;

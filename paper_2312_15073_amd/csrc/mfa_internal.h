@@ -44,13 +44,9 @@ struct DevBlock {
   int32_t tile_off;     // first sort bucket of the block
   int32_t sc_off[2];    // per super-cell level: the block's first cell in that level's pool
   int32_t sc[2][3];     // per level: cells per axis = ceil(nsp / 2^sc_shift[level])
-  // span guess of a non-uniform knot axis: gtab[gtab_off + floor(u * gtab_n)]
-  // is the span (record index) holding u = g / gtab_n, with bins narrower
-  // than the shortest span; gtab_off = -1 for uniform knots (guess floor(u * nsp))
-  int32_t gtab_off[3];
-  int32_t gtab_n[3];
+  int32_t pad;
 };
-static_assert(sizeof(DevBlock) == 200, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 176, "DevBlock layout");
 
 // Points sorted for decode are grouped by (block, tile); a tile spans
 // 2^sort_shift knot spans per axis, the shift chosen per model so that there
@@ -118,7 +114,13 @@ struct DevModel {
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
   const uint32_t* scb[2];  // the same bounds per super cell, coarse level first
-  const int32_t* gtab;     // span guess tables of the non-uniform knot axes
+  // span guess tables of the non-uniform knot axes (nullptr: none): for
+  // block b and axis a, gmeta[6 b + a] = offset of the axis's table in gtab
+  // (-1: uniform knots, guess floor(u * nsp)) and gmeta[6 b + 3 + a] = its
+  // bin count G; gtab[offset + floor(u * G)] is the span (record index)
+  // holding u = g / G, the bins being narrower than the shortest span
+  const int32_t* gtab;
+  const int32_t* gmeta;
   int32_t sc_shift[2];     // log2 of the spans per super cell and axis, per level
   double edge_scale[3];  // grid[a] / (E[G] - E[0]): block-owner guess only
   double box_lo[3];

@@ -150,18 +150,20 @@ __device__ __forceinline__ int guess_span(int nsp, double u) {
 
 // The guess of a point's span on axis a of block B: floor(u * nsp) for
 // uniform knots, else the span of u's bin in the axis's guess table (the
-// exact span or the one before it).  GT: the kernel may see guess tables
-// (multi-block kernels, and the single-block kernels built for models with
-// a non-uniform axis); without it the plain guess is compiled alone.
+// exact span or the one before it).  GT: the single-block kernels built for
+// models with a non-uniform axis; every other kernel compiles the plain
+// guess alone (the table path, even untaken, costs the multi-block kernels
+// about 10 %), and a non-uniform axis there is found by the walk.
 template <bool GT>
-__device__ __forceinline__ int guess_span(const int32_t* __restrict__ gtab,
-                                          const DevBlock* __restrict__ B, int a, double u) {
+__device__ __forceinline__ int guess_span(const DevModel& m, const DevBlock* __restrict__ B,
+                                          int block, int a, double u) {
   if constexpr (!GT) return guess_span(B->nsp[a], u);
-  const int off = B->gtab_off[a];
+  if (m.gtab == nullptr) return guess_span(B->nsp[a], u);   // no table in the model (scalar test)
+  const int off = m.gmeta[6 * block + a];
   if (off < 0) return guess_span(B->nsp[a], u);
-  const int G = B->gtab_n[a];
+  const int G = m.gmeta[6 * block + 3 + a];
   const int g = (int)(u * (double)G);
-  return gtab[off + (g < 0 ? 0 : (g > G - 1 ? G - 1 : g))];
+  return m.gtab[off + (g < 0 ? 0 : (g > G - 1 ? G - 1 : g))];
 }
 
 __device__ __forceinline__ bool span_ok(int nsp, double u, int j, const SpanRec& rec) {
@@ -359,7 +361,7 @@ __device__ __forceinline__ int macro_cell(const DevModel& m, const DevBlock* __r
 }
 
 // R: span records (global pool or its LDS copy).
-template <bool MULTI, bool GT = MULTI>
+template <bool MULTI, bool GT = false>
 __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restrict__ R,
                                        const double (&x)[3]) {
   Probe q;
@@ -398,7 +400,7 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    q.j[a] = guess_span<GT>(m.gtab, q.B, a, q.u[a]);
+    q.j[a] = guess_span<GT>(m, q.B, q.block, a, q.u[a]);
     q.rec[a] = R[q.B->rec_off[a] + q.j[a]];
   }
   return q;
@@ -432,7 +434,7 @@ __device__ __forceinline__ Loc finish(const DevModel& m, const SpanRec* __restri
   return L;
 }
 
-template <int P, bool MULTI, bool GT = MULTI>
+template <int P, bool MULTI, bool GT = false>
 __device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
                                       const double (&x)[3]) {
   Probe q = probe<MULTI, GT>(m, R, x);
@@ -461,7 +463,7 @@ __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t 
 }
 
 // ------------------------------------------------------------------ K1: points
-template <int P, Storage S, bool MULTI, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool GT = false>
 __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
                                                           int64_t n, float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -503,9 +505,10 @@ constexpr int kSortChunk = kBlock * kSortPer;  // points per workgroup
 // chunks keep more workgroups in flight
 constexpr int kSortPer2 = 8;
 
-template <bool MULTI>
+template <bool MULTI, bool GT>
 __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double (&x)[3]) {
   const DevBlock* __restrict__ B = &m.b0;
+  int block = 0;
   double u[3];
   if constexpr (MULTI) {
     int b[3];
@@ -525,7 +528,8 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
 #pragma unroll
       for (int a = 0; a < 3; ++a) fix_owner(m.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
     }
-    B = m.blocks + ((b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]);
+    block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
+    B = m.blocks + block;
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
   } else {
@@ -538,7 +542,7 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int nsp = B->nsp[a];
-    const int j = guess_span<true>(m.gtab, B, a, u[a]);   // the exact span or the one before
+    const int j = guess_span<GT>(m, B, block, a, u[a]);  // the exact span or the one before
     t[a] = j >> sh;
     td[a] = (nsp + (1 << sh) - 1) >> sh;
   }
@@ -550,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
   if (i < n) p[i] = 0u;
 }
 
-template <bool MULTI>
+template <bool MULTI, bool GT>
 __global__ __launch_bounds__(kBlock) void sort_hist_k(DevModel m, SortArgs sa) {
   __shared__ uint32_t h[kMaxBuckets];
   for (int b = threadIdx.x; b < sa.nb; b += kBlock) h[b] = 0u;
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void sort_hist_k(DevModel m, SortArgs sa) {
     const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
     if (i < sa.n) {
       const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
-      atomicAdd(h + sort_bucket<MULTI>(m, x), 1u);
+      atomicAdd(h + sort_bucket<MULTI, GT>(m, x), 1u);
     }
   }
   __syncthreads();
@@ -637,7 +641,7 @@ __device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
 // atomic, records written to run start + rank.  COARSE: key = bucket >>
 // kFineShift (the coarse pass, runs from sa.ccursor, records to sa.tmp);
 // otherwise key = bucket (runs from sa.cursor, records to sa.rec).
-template <bool MULTI, bool COARSE, bool FROM_TMP, int PER>
+template <bool MULTI, bool COARSE, bool FROM_TMP, int PER, bool GT>
 __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
   constexpr int kKeys = COARSE ? kCoarseBuckets : kMaxBuckets;
   __shared__ uint32_t h[kKeys];
@@ -654,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
     if (i < sa.n) {
       const float4 r = sort_input<FROM_TMP>(sa, i);
       const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
-      const uint32_t b = sort_bucket<MULTI>(m, x);
+      const uint32_t b = sort_bucket<MULTI, GT>(m, x);
       key[q] = COARSE ? b >> kFineShift : b;
       rank[q] = atomicAdd(h + key[q], 1u);
     }
@@ -719,7 +723,7 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
 // for non-uniform knots) reads its rows from global memory.  Both paths sum
 // in the same order.  LDSREC: the span records and basis tables of a
 // single-block model are staged too, ahead of the window.
-template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false>
 __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
                                                          float* __restrict__ out,
                                                          int32_t* __restrict__ dbg) {
@@ -819,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
 // Sorted decode for models whose bucket windows exceed the LDS budget: one
 // point per thread over the sorted records (workgroup ranges dealt to XCDs
 // in contiguous bands), rows from global memory.
-template <int P, Storage S, bool MULTI, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool GT = false>
 __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
                                                           float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -1056,9 +1060,11 @@ __device__ __forceinline__ void region_range(const RenderArgs& r, const Ray& ray
 // face for the leap estimates; jb / nsp for uniform knots, else from the
 // span records (1 past the last span: the end knot 1).
 template <bool GT>
-__device__ __forceinline__ float face_knot(const SpanRec* __restrict__ R,
-                                           const DevBlock* __restrict__ B, int a, int jb) {
-  if (!GT || B->gtab_off[a] < 0) return __fdividef((float)jb, (float)B->nsp[a]);
+__device__ __forceinline__ float face_knot(const DevModel& m, const SpanRec* __restrict__ R,
+                                           const DevBlock* __restrict__ B, int block, int a,
+                                           int jb) {
+  if (!GT || m.gtab == nullptr || m.gmeta[6 * block + a] < 0)
+    return __fdividef((float)jb, (float)B->nsp[a]);
   return jb < B->nsp[a] ? (float)R[B->rec_off[a] + jb].t : 1.f;
 }
 
@@ -1150,7 +1156,7 @@ __device__ __forceinline__ float shade_over(const float4 e, const float (&L)[3],
 // that cell is crossed sample by sample.  The search stops at the first
 // sample whose fine super cell is not transparent; compositing from there
 // gives the same pixel as compositing from sample 0.
-template <int P, bool MULTI, bool GT = MULTI>
+template <int P, bool MULTI, bool GT = false>
 __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs& r,
                                              const SpanRec* __restrict__ R, const Ray& ray,
                                              const int* zpre, int k_lo, int k_hi) {
@@ -1197,7 +1203,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
         if (ray.d[a] == 0.0) continue;
         const int cc = Lc.j[a] >> sh;
         const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
-        const float xb = fmaf(face_knot<GT>(R, B, a, jb), (float)B->ext[a], (float)B->lo[a]);
+        const float xb = fmaf(face_knot<GT>(m, R, B, Lc.block, a, jb), (float)B->ext[a], (float)B->lo[a]);
         te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
       }
       kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
@@ -1215,7 +1221,7 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
 
 // One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
 // and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
-template <int P, Storage S, bool MULTI, bool PARTIAL = false, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool PARTIAL = false, bool GT = false>
 __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs& r, int tile,
                                             const SpanRec* __restrict__ R,
                                             const float* __restrict__ MT, const float4* tf,
@@ -1316,7 +1322,7 @@ __device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
 
 // LDSREC: single-block model whose span records and basis tables are copied
 // into LDS once per workgroup.
-template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool GT = false>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   __shared__ float4 tf[256];
@@ -1358,7 +1364,7 @@ __device__ __forceinline__ int iso_side(uint32_t bh, float iso) {
   return iso <= blo ? 1 : (iso > bhi ? 0 : -1);
 }
 
-template <int P, Storage S, bool MULTI, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool GT = false>
 __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r, int tile,
                                          const SpanRec* __restrict__ R,
                                          const float* __restrict__ MT) {
@@ -1465,7 +1471,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
         if (ray.d[a] == 0.0) continue;
         const int cc = Lc.j[a] >> sh;
         const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
-        const float xb = fmaf(face_knot<GT>(R, B, a, jb), (float)B->ext[a], (float)B->lo[a]);
+        const float xb = fmaf(face_knot<GT>(m, R, B, Lc.block, a, jb), (float)B->ext[a], (float)B->lo[a]);
         te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
       }
       kl = (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
@@ -1520,7 +1526,7 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
   }
 }
 
-template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = MULTI>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false>
 __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   const SpanRec* R = m.rec;
@@ -1737,6 +1743,23 @@ static hipError_t points_p(const DevModel& m, int kind, const float* xyz, int64_
   return hipGetLastError();
 }
 
+// Histogram, scan and scatter of the (block, tile) sort.
+template <bool MULTI, bool GT>
+static void sort_launch(const DevModel& m, const SortArgs& sa, unsigned gc, hipStream_t st) {
+  hipLaunchKernelGGL((sort_hist_k<MULTI, GT>), dim3(gc), dim3(kBlock), 0, st, m, sa);
+  hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kBlock), 0, st, sa);
+  if (sa.tmp) {                        // two levels: coarse runs, then buckets
+    const unsigned g2 = (unsigned)((sa.n + kBlock * kSortPer2 - 1) / (kBlock * kSortPer2));
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, true, false, kSortPer2, GT>), dim3(g2), dim3(kBlock), 0,
+                       st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, false, true, kSortPer2, GT>), dim3(g2), dim3(kBlock), 0,
+                       st, m, sa);
+  } else {
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, false, false, kSortPer, GT>), dim3(gc), dim3(kBlock), 0,
+                       st, m, sa);
+  }
+}
+
 template <int P, Storage S>
 static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
@@ -1745,30 +1768,11 @@ static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, floa
   const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
   if (multi)
-    hipLaunchKernelGGL(sort_hist_k<true>, dim3(gc), dim3(kBlock), 0, st, m, sa);
+    sort_launch<true, false>(m, sa, gc, st);
+  else if (kind == kKindGraded)
+    sort_launch<false, true>(m, sa, gc, st);
   else
-    hipLaunchKernelGGL(sort_hist_k<false>, dim3(gc), dim3(kBlock), 0, st, m, sa);
-  hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kBlock), 0, st, sa);
-  if (sa.tmp) {                        // two levels: coarse runs, then buckets
-    const unsigned g2 = (unsigned)((sa.n + kBlock * kSortPer2 - 1) / (kBlock * kSortPer2));
-    if (multi) {
-      hipLaunchKernelGGL((sort_scatter_k<true, true, false, kSortPer2>), dim3(g2), dim3(kBlock), 0, st,
-                         m, sa);
-      hipLaunchKernelGGL((sort_scatter_k<true, false, true, kSortPer2>), dim3(g2), dim3(kBlock), 0, st,
-                         m, sa);
-    } else {
-      hipLaunchKernelGGL((sort_scatter_k<false, true, false, kSortPer2>), dim3(g2), dim3(kBlock), 0,
-                         st, m, sa);
-      hipLaunchKernelGGL((sort_scatter_k<false, false, true, kSortPer2>), dim3(g2), dim3(kBlock), 0,
-                         st, m, sa);
-    }
-  } else if (multi) {
-    hipLaunchKernelGGL((sort_scatter_k<true, false, false, kSortPer>), dim3(gc), dim3(kBlock), 0, st,
-                       m, sa);
-  } else {
-    hipLaunchKernelGGL((sort_scatter_k<false, false, false, kSortPer>), dim3(gc), dim3(kBlock), 0, st,
-                       m, sa);
-  }
+    sort_launch<false, false>(m, sa, gc, st);
   if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
     const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
     if (kind != kKindPlain)

@@ -32,6 +32,7 @@ struct mfa_model_s {
   uint32_t* d_scb[2] = {nullptr, nullptr};
   mfa::BucketWin* d_bwin = nullptr;
   int32_t* d_gtab = nullptr;
+  int32_t* d_gmeta = nullptr;
   bool nonuniform = false;   // some axis has non-uniform knots (span guess tables)
   int64_t device_bytes = 0;
   int64_t n_buckets = 0;        // sort buckets (block, tile)
@@ -50,9 +51,10 @@ mfa::Storage storage_of(mfa_model m);
 mfa_status check_knots(const double* T, int n, int p, int blk, int axis);
 void default_knots(int n, int p, double* T);
 mfa_status check_device(mfa_model m);
-// Kernel family of a model (kKindPlain / kKindGraded / kKindMulti); the
-// serving kernel has no single-block variant with span guess tables, so a
-// model with a non-uniform axis is served by the multi-block one.
+// Kernel family of a model (kKindPlain / kKindGraded / kKindMulti).  Only
+// the single-block kernels have a variant with span guess tables; the
+// serving kernel serves a model with a non-uniform axis through its
+// multi-block form, whose exact span walk finds those spans.
 inline int kernel_kind(mfa_model m) {
   return m->nblocks > 1 ? mfa::kKindMulti : (m->nonuniform ? mfa::kKindGraded : mfa::kKindPlain);
 }
