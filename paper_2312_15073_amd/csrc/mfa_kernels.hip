@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <atomic>
+
 #include "mfa.h"
 #include "mfa_internal.h"
 
@@ -1726,6 +1728,23 @@ __global__ __launch_bounds__(kBlock) void serve_k(const DevModel* __restrict__ m
 // 54 KB); with the decode window (at most 32 KB) a workgroup stays within
 // the 160 KB of LDS of a CU.
 constexpr int kLdsRecBytes = 64 * 1024;
+constexpr size_t kStaticLdsBytes = 8 * 1024;   // a kernel's own LDS arrays, at most
+
+// Whether dyn bytes of dynamic LDS (plus the kernel's own arrays) fit a
+// workgroup on the current device (its limit read once per device).
+static bool lds_fits(size_t dyn) {
+  static std::atomic<int> limit[64];     // zero-initialised: not read yet
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return dyn + kStaticLdsBytes <= 65536;
+  int v = limit[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+      v = 65536;
+    limit[dev].store(v, std::memory_order_relaxed);
+  }
+  return dyn + kStaticLdsBytes <= (size_t)v;
+}
 
 template <int P, Storage S>
 static hipError_t points_p(const DevModel& m, int kind, const float* xyz, int64_t n, float* out,
@@ -1787,13 +1806,14 @@ static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, floa
   const int cap = m.win_max;
   const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   const size_t wb = (size_t)cap * 4;
-  if (kind == kKindMulti || (kind == kKindGraded && tabs > (size_t)kLdsRecBytes))
+  const bool lds_tabs = tabs <= (size_t)kLdsRecBytes && lds_fits(tabs + wb);
+  if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
     hipLaunchKernelGGL((decode_tiles_k<P, S, true, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
                        cap, out, dbg);
   else if (kind == kKindGraded)
     hipLaunchKernelGGL((decode_tiles_k<P, S, false, true, true>), dim3(gi), dim3(kBlock), tabs + wb,
                        st, m, sa, cap, out, dbg);
-  else if (tabs <= (size_t)kLdsRecBytes)
+  else if (lds_tabs)
     hipLaunchKernelGGL((decode_tiles_k<P, S, false, true>), dim3(gi), dim3(kBlock), tabs + wb, st,
                        m, sa, cap, out, dbg);
   else
@@ -1828,7 +1848,8 @@ static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hip
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   // a single block with a non-uniform axis: its own kernel when the tables
   // fit in LDS, else the multi-block kernels
-  const bool multi = kind == kKindMulti || (kind == kKindGraded && lds > (size_t)kLdsRecBytes);
+  const bool lds_tabs = lds <= (size_t)kLdsRecBytes && lds_fits(lds);
+  const bool multi = kind == kKindMulti || (kind == kKindGraded && !lds_tabs);
   // a partial render of a single-block model holds every sample (its
   // region is the model box): it is the full render, whose key is the
   // entry parameter of the model box
@@ -1839,7 +1860,7 @@ static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hip
   else if (kind == kKindGraded)
     hipLaunchKernelGGL((render_k<P, S, false, true, false, true>), dim3(tiles), dim3(kBlock), lds, st,
                        m, r);
-  else if (lds <= (size_t)kLdsRecBytes)
+  else if (lds_tabs)
     hipLaunchKernelGGL((render_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else
     hipLaunchKernelGGL((render_k<P, S, false, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
@@ -1850,11 +1871,12 @@ template <int P, Storage S>
 static hipError_t iso_p(const DevModel& m, int kind, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
-  if (kind == kKindMulti || (kind == kKindGraded && lds > (size_t)kLdsRecBytes))
+  const bool lds_tabs = lds <= (size_t)kLdsRecBytes && lds_fits(lds);
+  if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
     hipLaunchKernelGGL((iso_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   else if (kind == kKindGraded)
     hipLaunchKernelGGL((iso_k<P, S, false, true, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
-  else if (lds <= (size_t)kLdsRecBytes)
+  else if (lds_tabs)
     hipLaunchKernelGGL((iso_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
   else
     hipLaunchKernelGGL((iso_k<P, S, false, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);

@@ -249,6 +249,19 @@ def test_render_graded_knots(mfa, dev):
     assert r["evaluated"] < r["samples"]
 
 
+def test_render_graded_128_tables_over_40kb(mfa, dev):
+    """128 graded spans per axis: every span has its own basis table, the
+    records and tables take about 54 KB of LDS in the graded single-block
+    kernel."""
+    model = synth.model_c2_graded()
+    W, H = 32, 24
+    cam = synth.perspective_camera(W, H, az_deg=70, el_deg=15)
+    params = synth.render_params(model)
+    announce("render graded 128^3 model, tables in LDS")
+    r = check_render(mfa, dev, model, cam, params, W, H)
+    assert r["evaluated"] > 1000
+
+
 def test_render_closed_form_constant_opacity(mfa, dev):
     T = synth.clamped_uniform_knots(8, 3)
     P = synth.linear_precision_ctrl([T] * 3, [3] * 3, (0.0, 1.0, 0.0, 0.0))
