@@ -47,7 +47,7 @@ struct GemmArgs {
 constexpr int kGemmBlock = 256;   // 4 waves, each computing its own C tile
 constexpr int kGemmTile = 32;     // C tile per wave: 2 x 2 MFMA blocks of 16 x 16
 
-// One wave per 32 x 32 tile of C; tiles are numbered with the M tile
+// One wave per 32 x 16 NT tile of C; tiles are numbered with the M tile
 // fastest, so the waves of a workgroup share the columns of B they read
 // (with ERR below, N fastest: there the waves share rows of A).
 // Per step of 4 along K each lane supplies A(m0 + 16t + lane % 16, k) and
@@ -75,7 +75,7 @@ struct ErrOut {
 
 constexpr int kGemmUnroll = 4;    // K steps whose loads are issued together
 
-template <typename TB, bool TRANS_A, bool ERR>
+template <typename TB, bool TRANS_A, bool ERR, int NT>
 __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restrict__ gA,
                                                          const TB* __restrict__ gB,
                                                          double* __restrict__ gC, GemmArgs g,
@@ -87,79 +87,88 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
   const int64_t nb = gridDim.x, xq = nb / 8, xr = nb % 8, xcd = blockIdx.x % 8, xi = blockIdx.x / 8;
   const int64_t lb = xcd < xr ? xcd * (xq + 1) + xi : xr * (xq + 1) + (xcd - xr) * xq + xi;
   const int64_t w = lb * (kGemmBlock / 64) + (threadIdx.x >> 6);
-  const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + kGemmTile - 1) / kGemmTile;
+  static_assert(!ERR || NT == 2, "the error epilogue works on 32 x 32 tiles");
+  constexpr int TN = 16 * NT;                          // tile width along N
+  const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + TN - 1) / TN;
   if (w >= tm * tn * g.batch) return;                  // whole wave
   // tiles numbered with M fastest (the waves of a run share B columns), or
   // N fastest for the error product (few, narrow B columns; tall A)
   const int64_t im = ERR ? (w / tn) % tm : w % tm, jn = ERR ? w % tn : (w / tm) % tn;
   const int64_t b = w / (tm * tn);
   const int c16 = lane & 15, q = lane >> 4;
-  const int64_t m0 = im * kGemmTile, n0 = jn * kGemmTile;
+  const int64_t m0 = im * kGemmTile, n0 = jn * TN;
   const double* A0 = gA + b * g.sA;
   const TB* B0 = gB + b * g.sB;
   gptr<double> pa[2];
-  gptr<TB> pb[2];
+  gptr<TB> pb[NT];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int64_t m = min(m0 + 16 * t + c16, g.M - 1), n = min(n0 + 16 * t + c16, g.N - 1);
+    const int64_t m = min(m0 + 16 * t + c16, g.M - 1);
     pa[t] = (gptr<double>)(TRANS_A ? A0 + (int64_t)q * g.lda + m : A0 + m * g.lda + q);
-    pb[t] = (gptr<TB>)(B0 + (int64_t)q * g.ldb + n);
+  }
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int64_t n = min(n0 + 16 * u + c16, g.N - 1);
+    pb[u] = (gptr<TB>)(B0 + (int64_t)q * g.ldb + n);
   }
   const int64_t step_a = TRANS_A ? 4 * g.lda : 4, step_b = 4 * g.ldb;
-  v4d acc[2][2];
+  v4d acc[2][NT];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) acc[t][u] = v4d{0.0, 0.0, 0.0, 0.0};
-  auto mma = [&](const double (&a)[2], const double (&bv)[2]) {
+    for (int u = 0; u < NT; ++u) acc[t][u] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](const double (&a)[2], const double (&bv)[NT]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < NT; ++u)
         acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[u], acc[t][u], 0, 0, 0);
   };
   const int64_t kfull = g.K & ~(int64_t)3;
   int64_t k0 = 0;
   for (; k0 + 4 * kGemmUnroll <= kfull; k0 += 4 * kGemmUnroll) {
     double a[kGemmUnroll][2];
-    TB bt[kGemmUnroll][2];
-#pragma unroll
-    for (int s = 0; s < kGemmUnroll; ++s)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[s][t] = pa[t][s * step_a];
-        bt[s][t] = pb[t][s * step_b];
-      }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      pa[t] += kGemmUnroll * step_a;
-      pb[t] += kGemmUnroll * step_b;
-    }
+    TB bt[kGemmUnroll][NT];
 #pragma unroll
     for (int s = 0; s < kGemmUnroll; ++s) {
-      const double bv[2] = {(double)bt[s][0], (double)bt[s][1]};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[s][t] = pa[t][s * step_a];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) bt[s][u] = pb[u][s * step_b];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) pa[t] += kGemmUnroll * step_a;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) pb[u] += kGemmUnroll * step_b;
+#pragma unroll
+    for (int s = 0; s < kGemmUnroll; ++s) {
+      double bv[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) bv[u] = (double)bt[s][u];
       mma(a[s], bv);
     }
   }
   for (; k0 < kfull; k0 += 4) {
-    double a[2], bv[2];
+    double a[2], bv[NT];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       a[t] = *pa[t];
-      bv[t] = (double)*pb[t];
       pa[t] += step_a;
-      pb[t] += step_b;
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      bv[u] = (double)*pb[u];
+      pb[u] += step_b;
     }
     mma(a, bv);
   }
   if (kfull < g.K) {
     const bool kin = kfull + q < g.K;
-    double a[2], bv[2];
+    double a[2], bv[NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = kin ? *pa[t] : 0.0;
-      bv[t] = kin ? (double)*pb[t] : 0.0;
-    }
+    for (int t = 0; t < 2; ++t) a[t] = kin ? *pa[t] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) bv[u] = kin ? (double)*pb[u] : 0.0;
     mma(a, bv);
   }
   if constexpr (ERR) {
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < NT; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
@@ -213,15 +222,15 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
   }
 }
 
-template <typename TB, bool TRANS_A, bool ERR = false>
+template <typename TB, bool TRANS_A, bool ERR = false, int NT = 2>
 hipError_t gemm(const GemmArgs& g, hipStream_t st, const ErrOut& eo = ErrOut{}) {
-  const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + kGemmTile - 1) / kGemmTile) *
+  const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + 16 * NT - 1) / (16 * NT)) *
                         g.batch;
   const int64_t blocks = (tiles + kGemmBlock / 64 - 1) / (kGemmBlock / 64);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (ERR && g.batch != 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A, ERR>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st,
+  hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A, ERR, NT>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st,
                      g.A, static_cast<const TB*>(g.B), g.C, g, eo);
   return hipGetLastError();
 }
@@ -328,7 +337,9 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // The three mode products of a fit, P = F x_0 B0+ x_1 B1+ x_2 B2+, with the
-// tables qt[a] = B_a+ transposed (N_a x n_a).  Y1 is written transposed,
+// tables qt[a] = B_a+ transposed (N_a x n_a).  The first, by far the
+// largest (N = N1 N2 columns), runs 32 x 64 tiles per wave (fewer operand
+// loads per MFMA); the other two keep 32 x 32 (measured faster there).  Y1 is written transposed,
 // [N2][n0 * n1], so that the third product reads its A operand along rows
 // of 16 consecutive values.
 hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, double* ctrl,
@@ -338,7 +349,7 @@ hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, 
   GemmArgs g1{n[1], N[2], N[1], n[0], qt[1], n[1], 0, y0, N[2], N[1] * N[2], y1, n[0] * n[1],
               n[1], 1};
   GemmArgs g2{n[0] * n[1], n[2], N[2], 1, y1, n[0] * n[1], 0, qt[2], n[2], 0, ctrl, n[2], 0, 0};
-  hipError_t e = gemm<float, true>(g0, hs);
+  hipError_t e = gemm<float, true, false, 4>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
   if (e == hipSuccess) e = gemm<double, true>(g2, hs);
   return e;
