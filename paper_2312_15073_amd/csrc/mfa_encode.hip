@@ -45,7 +45,7 @@ struct GemmArgs {
 };
 
 constexpr int kGemmBlock = 256;   // 4 waves, each computing its own C tile
-constexpr int kGemmTile = 32;     // C tile per wave: 2 x 2 MFMA blocks of 16 x 16
+constexpr int kGemmTile = 32;     // C tile rows per wave: 2 MFMA blocks of 16 (columns: NT blocks)
 
 // One wave per 32 x 16 NT tile of C; tiles are numbered with the M tile
 // fastest, so the waves of a workgroup share the columns of B they read
