@@ -65,6 +65,8 @@ using gptr = const __attribute__((address_space(1))) T*;   // global-memory poin
 // per tile the largest error of each of its rows, rowpart[jn * M + m], and
 // of each of its columns, colpart[im * N + n] (jn, im: the tile's column
 // and row index); out-of-range elements count as 0.
+constexpr int kErrNT = 2;         // the error product's tiles: 32 x 32 (32 x 64 measured slower)
+
 struct ErrOut {
   const float* f;
   int64_t ldf;
@@ -87,7 +89,6 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
   const int64_t nb = gridDim.x, xq = nb / 8, xr = nb % 8, xcd = blockIdx.x % 8, xi = blockIdx.x / 8;
   const int64_t lb = xcd < xr ? xcd * (xq + 1) + xi : xr * (xq + 1) + (xcd - xr) * xq + xi;
   const int64_t w = lb * (kGemmBlock / 64) + (threadIdx.x >> 6);
-  static_assert(!ERR || NT == 2, "the error epilogue works on 32 x 32 tiles");
   constexpr int TN = 16 * NT;                          // tile width along N
   const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + TN - 1) / TN;
   if (w >= tm * tn * g.batch) return;                  // whole wave
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < NT; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
@@ -184,12 +185,14 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
                              ? fabs(acc[t][u][r] - (double)F[m * eo.ldf + n]) * eo.inv_range
                              : 0.0;
         }
-    // rows: the 16 lanes of one q hold a row's 32 columns (two per lane)
+    // rows: the 16 lanes of one q hold a row's 16 NT columns (NT per lane)
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double v = fmax(acc[t][0][r], acc[t][1][r]);
+        double v = acc[t][0][r];
+#pragma unroll
+        for (int u = 1; u < NT; ++u) v = fmax(v, acc[t][u][r]);
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) v = fmax(v, __shfl_xor(v, o));
         const int64_t m = m0 + 16 * t + q + 4 * r;
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
       }
     // columns: a lane holds 8 rows of a column, the four q groups the rest
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NT; ++u) {
       double v = 0.0;
 #pragma unroll
       for (int t = 0; t < 2; ++t)
@@ -368,7 +371,7 @@ hipError_t run_recon_err(const int64_t N[3], const int64_t n[3], const double* c
   GemmArgs g2{N[0] * N[1], N[2], n[2], 1, r1, N[0] * N[1], 0, bt[2], N[2], 0, nullptr, N[2], 0, 0};
   hipError_t e = gemm<double, true>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
-  if (e == hipSuccess) e = gemm<double, true, true>(g2, hs, eo);
+  if (e == hipSuccess) e = gemm<double, true, true, kErrNT>(g2, hs, eo);
   return e;
 }
 
@@ -599,7 +602,7 @@ struct AdaptLayout {
 AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   AdaptLayout L{};
   const size_t N0 = res[0], N1 = res[1], N2 = res[2], m0 = nm[0], m1 = nm[1], m2 = nm[2];
-  const size_t M = N0 * N1, tm = (M + kGemmTile - 1) / kGemmTile, tn = (N2 + kGemmTile - 1) / kGemmTile;
+  const size_t M = N0 * N1, tm = (M + kGemmTile - 1) / kGemmTile, tn = (N2 + 16 * kErrNT - 1) / (16 * kErrNT);
   auto up = [](size_t v) { return (v + kRedRows - 1) / kRedRows; };
   const size_t red = std::max({up(tm) * N2, tn > (size_t)kRedRows ? up(tn) * M : 0, up(N0) * N1});
   size_t o = 0;
@@ -685,7 +688,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
   auto at = [&](size_t off) { return reinterpret_cast<double*>(wb + off); };
   const int64_t N[3] = {res[0], res[1], res[2]};
   const int64_t rows = N[0] * N[1];
-  const int64_t tm = (rows + kGemmTile - 1) / kGemmTile, tn = (N[2] + kGemmTile - 1) / kGemmTile;
+  const int64_t tm = (rows + kGemmTile - 1) / kGemmTile, tn = (N[2] + 16 * kErrNT - 1) / (16 * kErrNT);
   if ((tm + kRedRows - 1) / kRedRows > 65535)
     return fail(MFA_E_ARG, "res0 * res1 above %lld", 65535LL * kRedRows * kGemmTile);
   // data range

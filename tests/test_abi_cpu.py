@@ -180,7 +180,7 @@ def test_encode_adaptive_workspace_size_and_rejections():
     al = lambda v: (v + 255) // 256 * 256
     want = 2 * sum(al(8 * n * r) for n, r in ((m0, N0), (m1, N1), (m2, N2)))
     M, up = N0 * N1, (lambda v, d: (v + d - 1) // d)
-    tm, tn = up(M, 32), up(N2, 32)                                      # 32 x 32 GEMM tiles
+    tm, tn = up(M, 32), up(N2, 32)                           # 32 x 32 tiles of the error GEMM
     red = max(up(tm, 64) * N2, up(tn, 64) * M if tn > 64 else 0, up(N0, 64) * N1)
     want += al(8 * m0 * N1 * N2) + al(8 * N2 * m0 * m1) + al(8 * N0 * m1 * m2) + al(8 * m2 * M) \
         + al(8 * tn * M) + al(8 * tm * N2) + al(8 * M) + 2 * al(8 * red) \
