@@ -349,8 +349,12 @@ hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, 
                    const double* const qt[3], double* y0, double* y1, hipStream_t hs) {
   GemmArgs g0{n[0], N[1] * N[2], N[0], 1, qt[0], n[0], 0, values, N[1] * N[2], 0, y0,
               N[1] * N[2], 0, 0};
-  GemmArgs g1{n[1], N[2], N[1], n[0], qt[1], n[1], 0, y0, N[2], N[1] * N[2], y1, n[0] * n[1],
-              n[1], 1};
+  // Y1 = Y0 x_1 B1+ as its transpose per batch i0, Y1[i2][i0][j1] = sum_i1
+  // Y0[i0][i1][i2] B1+[j1][i1]: rows i2 of Y0 as the (transposed) A operand,
+  // so that the stores run along j1 (the plain product would store along i2
+  // with a stride of n0 n1 values)
+  GemmArgs g1{N[2], n[1], N[1], n[0], y0, N[2], N[1] * N[2], qt[1], n[1], 0, y1, n[0] * n[1],
+              n[1], 0};
   GemmArgs g2{n[0] * n[1], n[2], N[2], 1, y1, n[0] * n[1], 0, qt[2], n[2], 0, ctrl, n[2], 0, 0};
   hipError_t e = gemm<float, true, false, 4>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
@@ -367,7 +371,8 @@ hipError_t run_recon_err(const int64_t N[3], const int64_t n[3], const double* c
                          const double* const bt[3], double* r0, double* r1, const ErrOut& eo,
                          hipStream_t hs) {
   GemmArgs g0{N[0], n[1] * n[2], n[0], 1, bt[0], N[0], 0, ctrl, n[1] * n[2], 0, r0, n[1] * n[2], 0, 0};
-  GemmArgs g1{N[1], n[2], n[1], N[0], bt[1], N[1], 0, r0, n[2], n[1] * n[2], r1, N[0] * N[1], N[1], 1};
+  // transposed per batch i0 like the fit's x_1 product: R1[j2][i0][i1]
+  GemmArgs g1{n[2], N[1], n[1], N[0], r0, n[2], n[1] * n[2], bt[1], N[1], 0, r1, N[0] * N[1], N[1], 0};
   GemmArgs g2{N[0] * N[1], N[2], n[2], 1, r1, N[0] * N[1], 0, bt[2], N[2], 0, nullptr, N[2], 0, 0};
   hipError_t e = gemm<double, true>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
