@@ -42,6 +42,11 @@ struct GemmArgs {
   double* C;
   int64_t ldc, sC;
   int32_t c_trans;     // element (m, n) of C at C[n * ldc + m]
+  // split-K (a product with too few tiles to fill the chip): split > 1
+  // chunks of kc values of K (a multiple of 4) per tile, each stored plain
+  // into part[((chunk * batch + b) * M + m) * N + n] and summed by split_sum_k
+  int64_t split, kc;
+  double* part;
 };
 
 constexpr int kGemmBlock = 256;   // 4 waves, each computing its own C tile
@@ -91,15 +96,18 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
   const int64_t w = lb * (kGemmBlock / 64) + (threadIdx.x >> 6);
   constexpr int TN = 16 * NT;                          // tile width along N
   const int64_t tm = (g.M + kGemmTile - 1) / kGemmTile, tn = (g.N + TN - 1) / TN;
-  if (w >= tm * tn * g.batch) return;                  // whole wave
+  const int64_t S = g.split > 1 ? g.split : 1;
+  if (w >= tm * tn * g.batch * S) return;              // whole wave
   // tiles numbered with M fastest (the waves of a run share B columns), or
   // N fastest for the error product (few, narrow B columns; tall A)
   const int64_t im = ERR ? (w / tn) % tm : w % tm, jn = ERR ? w % tn : (w / tm) % tn;
-  const int64_t b = w / (tm * tn);
+  const int64_t b = (w / (tm * tn)) / S, chunk = (w / (tm * tn)) % S;
+  const int64_t k_begin = S > 1 ? chunk * g.kc : 0;
+  const int64_t K = S > 1 ? min(g.kc, g.K - k_begin) : g.K;
   const int c16 = lane & 15, q = lane >> 4;
   const int64_t m0 = im * kGemmTile, n0 = jn * TN;
-  const double* A0 = gA + b * g.sA;
-  const TB* B0 = gB + b * g.sB;
+  const double* A0 = gA + b * g.sA + (TRANS_A ? k_begin * g.lda : k_begin);
+  const TB* B0 = gB + b * g.sB + k_begin * g.ldb;
   gptr<double> pa[2];
   gptr<TB> pb[NT];
 #pragma unroll
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
       for (int u = 0; u < NT; ++u)
         acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[u], acc[t][u], 0, 0, 0);
   };
-  const int64_t kfull = g.K & ~(int64_t)3;
+  const int64_t kfull = K & ~(int64_t)3;
   int64_t k0 = 0;
   for (; k0 + 4 * kGemmUnroll <= kfull; k0 += 4 * kGemmUnroll) {
     double a[kGemmUnroll][2];
@@ -163,8 +171,8 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
     }
     mma(a, bv);
   }
-  if (kfull < g.K) {
-    const bool kin = kfull + q < g.K;
+  if (kfull < K) {
+    const bool kin = kfull + q < K;
     double a[2], bv[NT];
 #pragma unroll
     for (int t = 0; t < 2; ++t) a[t] = kin ? *pa[t] : 0.0;
@@ -213,6 +221,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
     }
   } else {
     double* __restrict__ C = gC + b * g.sC;
+    double* __restrict__ Pc = S > 1 ? g.part + (chunk * g.batch + b) * g.M * g.N : nullptr;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -220,22 +229,70 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
-          if (m < g.M && n < g.N) C[g.c_trans ? n * g.ldc + m : m * g.ldc + n] = acc[t][u][r];
+          if (m < g.M && n < g.N) {
+            if (S > 1)
+              Pc[m * g.N + n] = acc[t][u][r];
+            else
+              C[g.c_trans ? n * g.ldc + m : m * g.ldc + n] = acc[t][u][r];
+          }
         }
   }
 }
 
+// C = sum over the split chunks of part (see GemmArgs): one thread per
+// element of C, in C's own layout.
+__global__ __launch_bounds__(256) void split_sum_k(GemmArgs g) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t per = g.M * g.N;
+  if (i >= g.batch * per) return;
+  const int64_t b = i / per, m = (i % per) / g.N, n = i % g.N;
+  double v = 0.0;
+  for (int64_t c = 0; c < g.split; ++c) v += g.part[(c * g.batch + b) * per + m * g.N + n];
+  g.C[b * g.sC + (g.c_trans ? n * g.ldc + m : m * g.ldc + n)] = v;
+}
+
 template <typename TB, bool TRANS_A, bool ERR = false, int NT = 2>
 hipError_t gemm(const GemmArgs& g, hipStream_t st, const ErrOut& eo = ErrOut{}) {
+  const int64_t S = g.split > 1 ? g.split : 1;
   const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + 16 * NT - 1) / (16 * NT)) *
-                        g.batch;
+                        g.batch * S;
   const int64_t blocks = (tiles + kGemmBlock / 64 - 1) / (kGemmBlock / 64);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  if (ERR && g.batch != 1) return hipErrorInvalidValue;
+  if (ERR && (g.batch != 1 || S > 1)) return hipErrorInvalidValue;
+  if (S > 1 && (!g.part || g.kc < 4 || g.kc % 4 != 0 || (S - 1) * g.kc >= g.K))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL((gemm_f64_k<TB, TRANS_A, ERR, NT>), dim3((unsigned)blocks), dim3(kGemmBlock), 0, st,
                      g.A, static_cast<const TB*>(g.B), g.C, g, eo);
+  if (S > 1) {
+    const int64_t n = g.batch * g.M * g.N;
+    hipLaunchKernelGGL(split_sum_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g);
+  }
   return hipGetLastError();
+}
+
+// Split-K for a product with few tiles (fewer waves than the chip holds
+// twice over): up to 8 chunks of at least 64 values of K, within the
+// scratch capacity cap (values) at part.
+void plan_split(GemmArgs& g, double* part, int64_t cap) {
+  g.split = 1;
+  g.kc = g.K;
+  g.part = nullptr;
+  if (!part) return;
+  const int64_t tiles = ((g.M + kGemmTile - 1) / kGemmTile) * ((g.N + kGemmTile - 1) / kGemmTile) *
+                        g.batch;
+  int64_t S = std::min<int64_t>(8, 2048 / std::max<int64_t>(tiles, 1));
+  while (S > 1 && (g.K / S < 64 || S * g.batch * g.M * g.N > cap)) --S;
+  if (S <= 1) return;
+  const int64_t kc = ((g.K + S - 1) / S + 3) & ~(int64_t)3;
+  g.split = (g.K + kc - 1) / kc;
+  g.kc = kc;
+  g.part = part;
+  if (g.split <= 1) {
+    g.split = 1;
+    g.kc = g.K;
+    g.part = nullptr;
+  }
 }
 
 // ------------------------------------------------------------------ host: collocation
@@ -346,7 +403,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // [N2][n0 * n1], so that the third product reads its A operand along rows
 // of 16 consecutive values.
 hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, double* ctrl,
-                   const double* const qt[3], double* y0, double* y1, hipStream_t hs) {
+                   const double* const qt[3], double* y0, double* y1, hipStream_t hs,
+                   double* split_part = nullptr, int64_t split_cap = 0) {
   GemmArgs g0{n[0], N[1] * N[2], N[0], 1, qt[0], n[0], 0, values, N[1] * N[2], 0, y0,
               N[1] * N[2], 0, 0};
   // Y1 = Y0 x_1 B1+ as its transpose per batch i0, Y1[i2][i0][j1] = sum_i1
@@ -356,6 +414,8 @@ hipError_t run_fit(const int64_t N[3], const int64_t n[3], const float* values, 
   GemmArgs g1{N[2], n[1], N[1], n[0], y0, N[2], N[1] * N[2], qt[1], n[1], 0, y1, n[0] * n[1],
               n[1], 0};
   GemmArgs g2{n[0] * n[1], n[2], N[2], 1, y1, n[0] * n[1], 0, qt[2], n[2], 0, ctrl, n[2], 0, 0};
+  plan_split(g1, split_part, split_cap);
+  plan_split(g2, split_part, split_cap);
   hipError_t e = gemm<float, true, false, 4>(g0, hs);
   if (e == hipSuccess) e = gemm<double, true>(g1, hs);
   if (e == hipSuccess) e = gemm<double, true>(g2, hs);
@@ -599,10 +659,15 @@ namespace {
 // Workspace of the adaptive loop, sized for max_ctrl control points per
 // axis: the tables, the intermediates of a fit and of a reconstruction, the
 // per-tile error maxima (rows m = i0 * N1 + i1 of the last reconstruction
-// product, columns i2), their reduction scratch and the three marginals.
+// product, columns i2), their reduction scratch, the three marginals and the
+// split-K partial products of the fit (a split product has at most 2048
+// tiles of 32 x 32 over all its chunks, so 2^21 values always suffice).
 struct AdaptLayout {
-  size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, total;
+  size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, part, total;
+  int64_t part_cap;
 };
+
+constexpr int64_t kSplitCap = int64_t(1) << 21;
 
 AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   AdaptLayout L{};
@@ -629,6 +694,8 @@ AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   L.red1 = take(8 * red);
   L.marg = take(8 * (N0 + N1 + N2));
   L.mm = take(sizeof(float2) * kMinMaxBlocks);
+  L.part_cap = std::min<int64_t>(kSplitCap, 8 * (int64_t)(m0 * m1 * N2));
+  L.part = take(8 * (size_t)L.part_cap);
   L.total = o;
   return L;
 }
@@ -749,7 +816,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     }
     const double* qt[3] = {at(lay.qt[0]), at(lay.qt[1]), at(lay.qt[2])};
     const double* bt[3] = {at(lay.bt[0]), at(lay.bt[1]), at(lay.bt[2])};
-    e = run_fit(N, n, values, ctrl, qt, at(lay.y0), at(lay.y1), hs);
+    e = run_fit(N, n, values, ctrl, qt, at(lay.y0), at(lay.y1), hs, at(lay.part), lay.part_cap);
     if (e == hipSuccess) e = run_recon_err(N, n, ctrl, bt, at(lay.r0), at(lay.r1), eo, hs);
     // marginals: m0[i0], m1[i1] from the row maxima over i2, m2[i2] over all rows
     if (e == hipSuccess) e = max_lead(eo.rowpart, tn, rows, at(lay.red0), at(lay.red1), at(lay.rowmax), hs);

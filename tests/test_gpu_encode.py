@@ -188,3 +188,17 @@ def test_encode_adaptive_loose_bound_is_one_fixed_knot_fit(mfa, dev):
     announce("adaptive encode, loose bound")
     knots, hist = run_adaptive(mfa, dev, F, axis_u, (3, 3, 3), (7, 8, 9), 10.0, 4)
     assert len(hist) == 1 and hist[0][0] == (7, 8, 9)
+
+
+def test_encode_adaptive_long_axes_split_products(mfa, dev):
+    """Long axes 1 and 2 with few control points: the fit's second and third
+    products have few tiles and run split along K (chunks of 84 and 77, and
+    of 68, 68 and 66 values, both with a ragged K tail)."""
+    res = (24, 161, 202)
+    x = [np.linspace(0.0, 1.0, r) for r in res]
+    g = np.meshgrid(*x, indexing="ij")
+    F = (np.sin(3.0 * g[0] + 5.0 * g[1]) * np.cos(4.0 * g[2]) + 0.2 * np.exp(-30 * (g[1] - 0.4) ** 2)
+         + 0.1 * g[0] * g[2]).astype(np.float32)
+    announce("adaptive encode 24x161x202 (split products)")
+    knots, hist = run_adaptive(mfa, dev, F, x, (3, 3, 3), (5, 6, 7), 1e-3, 3)
+    assert len(hist) >= 2
