@@ -133,6 +133,22 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
       for (int u = 0; u < NT; ++u)
         acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv[u], acc[t][u], 0, 0, 0);
   };
+  // the error product's samples are loaded before the K loop, so that their
+  // latency overlaps the products (rows and columns clamped in bounds, the
+  // ones past the edge are masked in the epilogue)
+  float fv[2][NT][4];
+  if constexpr (ERR) {
+    gptr<float> F = (gptr<float>)eo.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = min(m0 + 16 * t + q + 4 * r, g.M - 1), n = min(n0 + 16 * u + c16, g.N - 1);
+          fv[t][u][r] = F[m * eo.ldf + n];
+        }
+  }
   const int64_t kfull = K & ~(int64_t)3;
   int64_t k0 = 0;
   for (; k0 + 4 * kGemmUnroll <= kfull; k0 += 4 * kGemmUnroll) {
@@ -181,7 +197,6 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
     mma(a, bv);
   }
   if constexpr (ERR) {
-    gptr<float> F = (gptr<float>)eo.f;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -190,7 +205,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
           acc[t][u][r] = (m < g.M && n < g.N)
-                             ? fabs(acc[t][u][r] - (double)F[m * eo.ldf + n]) * eo.inv_range
+                             ? fabs(acc[t][u][r] - (double)fv[t][u][r]) * eo.inv_range
                              : 0.0;
         }
     // rows: the 16 lanes of one q hold a row's 16 NT columns (NT per lane)
@@ -295,6 +310,79 @@ void plan_split(GemmArgs& g, double* part, int64_t cap) {
   }
 }
 
+// ------------------------------------------------------------------ device: fit tables
+// The tables of one fit of the adaptive loop, from the knots T_a and the
+// Gram inverse Z_a of each axis: row i of qt[a] (N_a x n_a) is the
+// combination of the p + 1 rows of Z_a picked by the basis functions alive
+// at u_i (the pseudo-inverse, transposed), and column i of bt[a] (n_a x N_a)
+// holds those basis values, zeros elsewhere (the collocation matrix,
+// transposed).  Span rule and basis recurrence as on the host: the largest
+// i in [p, n-1] with T[i] <= u, and de Boor's triangular scheme.
+struct TabArgs {
+  const double* u[3];   // sample parameters in the caller's order
+  const double* T[3];   // knots, n + p + 1
+  const double* Z[3];   // Gram inverse, n x n
+  double* qt[3];
+  double* bt[3];
+  int32_t N[3], n[3], p[3];
+};
+
+__device__ int tab_span(const double* T, int p, int n, double u) {
+  int lo = p, hi = n - 1;
+  if (T[hi] <= u) return hi;
+  while (hi - lo > 1) {                // T[hi] > u; T[lo] <= u unless lo == p
+    const int mid = (lo + hi) >> 1;
+    if (T[mid] <= u)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// one wave per sample i of axis blockIdx.y; the lanes run over the n
+// control points (rows of Z read along their length, rows of qt written so)
+__global__ __launch_bounds__(256) void tables_k(TabArgs ta) {
+  const int a = blockIdx.y, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int N = ta.N[a], n = ta.n[a], p = ta.p[a];
+  if (i >= N) return;
+  const double* T = ta.T[a];
+  const double u = ta.u[a][i];
+  const int s = tab_span(T, p, n, u);
+  double bv[kMaxDegree + 1], left[kMaxDegree + 1], right[kMaxDegree + 1];
+  bv[0] = 1.0;
+#pragma unroll
+  for (int q = 1; q <= kMaxDegree; ++q) {
+    if (q > p) break;
+    left[q] = u - T[s + 1 - q];
+    right[q] = T[s + q] - u;
+    double carry = 0.0;
+#pragma unroll
+    for (int r = 0; r < q; ++r) {
+      const double den = right[r + 1] + left[q - r];
+      const double t = den != 0.0 ? bv[r] / den : 0.0;
+      bv[r] = carry + right[r + 1] * t;
+      carry = left[q - r] * t;
+    }
+    bv[q] = carry;
+  }
+  const double* Z = ta.Z[a] + (int64_t)(s - p) * n;
+  double* qrow = ta.qt[a] + (int64_t)i * n;
+  for (int j = lane; j < n; j += 64) {
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r <= kMaxDegree; ++r)
+      if (r <= p) v += bv[r] * Z[(int64_t)r * n + j];
+    qrow[j] = v;
+    double b = 0.0;
+#pragma unroll
+    for (int r = 0; r <= kMaxDegree; ++r)
+      if (r <= p && j == s - p + r) b = bv[r];
+    ta.bt[a][(int64_t)j * N + i] = b;
+  }
+}
+
 // ------------------------------------------------------------------ host: collocation
 // Span rule s = max{ i in [p, n-1] : T[i] <= u }.
 int span_of(const double* T, int p, int n, double u) {
@@ -322,24 +410,19 @@ void basis_values(const double* T, int p, int s, double u, double* N) {
   }
 }
 
-// Q = (B^T B)^-1 B^T, stored transposed (N x n row-major), for the collocation matrix B of one
-// axis: the Gram matrix G = B^T B is banded (bandwidth p) and factorised as
-// L L^T; its inverse Z is formed column by column (two banded triangular
-// solves per unit vector), and row i of Q is the combination of the p + 1
-// rows of Z picked by the non-zeros of row i of B (Z is symmetric).
-mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N, int axis,
-                          std::vector<double>& Q, std::vector<double>* Bt = nullptr) {
+// Z = (B^T B)^-1 (n x n, row-major, symmetric) for the collocation matrix B
+// of one axis: the Gram matrix G = B^T B is banded (bandwidth p) and
+// factorised as L L^T; Z is formed column by column (two banded triangular
+// solves per unit vector).  The spans and basis values of the samples are
+// left in s and Bv ((p + 1) per sample).
+mfa_status gram_inverse(const double* T, int p, int n, const double* u, int N, int axis,
+                        std::vector<double>& Z, std::vector<int>& s, std::vector<double>& Bv) {
   const int w = p + 1;
-  std::vector<int> s(N);
-  std::vector<double> Bv((size_t)N * w);
+  s.resize(N);
+  Bv.resize((size_t)N * w);
   for (int i = 0; i < N; ++i) {
     s[i] = span_of(T, p, n, u[i]);
     basis_values(T, p, s[i], u[i], &Bv[(size_t)i * w]);
-  }
-  if (Bt) {                                   // collocation matrix, transposed: Bt[j * N + i]
-    Bt->assign((size_t)n * N, 0.0);
-    for (int i = 0; i < N; ++i)
-      for (int r = 0; r <= p; ++r) (*Bt)[(size_t)(s[i] - p + r) * N + i] = Bv[(size_t)i * w + r];
   }
   // G[j * w + d] = (B^T B)[j][j - d], d = 0..p
   std::vector<double> G((size_t)n * w, 0.0);
@@ -366,7 +449,7 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
         L[(size_t)j * w] = std::sqrt(v);
       }
     }
-  std::vector<double> Z((size_t)n * n);
+  Z.resize((size_t)n * n);
   std::vector<double> y(n);
   for (int c = 0; c < n; ++c) {
     std::fill(y.begin(), y.end(), 0.0);
@@ -382,6 +465,19 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
     }
     std::copy(y.begin(), y.end(), Z.begin() + (size_t)c * n);
   }
+  return MFA_OK;
+}
+
+// Q = (B^T B)^-1 B^T, stored transposed (N x n row-major): row i of Q is the
+// combination of the p + 1 rows of Z picked by the non-zeros of row i of B
+// (Z is symmetric).
+mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N, int axis,
+                          std::vector<double>& Q) {
+  const int w = p + 1;
+  std::vector<double> Z, Bv;
+  std::vector<int> s;
+  const mfa_status st = gram_inverse(T, p, n, u, N, axis, Z, s, Bv);
+  if (st != MFA_OK) return st;
   Q.assign((size_t)n * N, 0.0);
   for (int i = 0; i < N; ++i) {
     double* q = &Q[(size_t)i * n];
@@ -661,9 +757,13 @@ namespace {
 // per-tile error maxima (rows m = i0 * N1 + i1 of the last reconstruction
 // product, columns i2), their reduction scratch, the three marginals and the
 // split-K partial products of the fit (a split product has at most 2048
-// tiles of 32 x 32 over all its chunks, so 2^21 values always suffice).
+// tiles of 32 x 32 over all its chunks, so 2^21 values always suffice), the
+// sample parameters, and the staging area of each fit's knots and Gram
+// inverses (packed, at most max_ctrl + kMaxDegree + 1 and max_ctrl^2 per
+// axis).
 struct AdaptLayout {
-  size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, part, total;
+  size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, part, u, stage,
+      total;
   int64_t part_cap;
 };
 
@@ -696,6 +796,8 @@ AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   L.mm = take(sizeof(float2) * kMinMaxBlocks);
   L.part_cap = std::min<int64_t>(kSplitCap, 8 * (int64_t)(m0 * m1 * N2));
   L.part = take(8 * (size_t)L.part_cap);
+  L.u = take(8 * (N0 + N1 + N2));
+  L.stage = take(8 * (m0 + m1 + m2 + 3 * (kMaxDegree + 1) + m0 * m0 + m1 * m1 + m2 * m2));
   L.total = o;
   return L;
 }
@@ -763,38 +865,37 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
   const int64_t tm = (rows + kGemmTile - 1) / kGemmTile, tn = (N[2] + 16 * kErrNT - 1) / (16 * kErrNT);
   if ((tm + kRedRows - 1) / kRedRows > 65535)
     return fail(MFA_E_ARG, "res0 * res1 above %lld", 65535LL * kRedRows * kGemmTile);
-  // data range
+  // sample parameters on the device, in the caller's order
+  std::vector<double> hu(N[0] + N[1] + N[2]);
+  const double* du[3] = {at(lay.u), at(lay.u) + N[0], at(lay.u) + N[0] + N[1]};
+  for (int a = 0; a < 3; ++a) std::copy(axis_u[a], axis_u[a] + res[a], hu.begin() + (du[a] - du[0]));
+  hipError_t e = hipMemcpyAsync(at(lay.u), hu.data(), hu.size() * 8, hipMemcpyHostToDevice, hs);
+  if (e != hipSuccess) return hip_fail(e, "encode: parameter upload");
+  // data range, reduced on the device while the host forms the first tables
   float2* mm = reinterpret_cast<float2*>(wb + lay.mm);
   hipLaunchKernelGGL(minmax_k, dim3(kMinMaxBlocks), dim3(256), 0, hs, values, rows * N[2], mm);
-  std::vector<float2> hmm(kMinMaxBlocks);
-  hipError_t e = hipMemcpyAsync(hmm.data(), mm, sizeof(float2) * kMinMaxBlocks, hipMemcpyDeviceToHost, hs);
-  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "encode: data range");
-  float lo = hmm[0].x, hi = hmm[0].y;
-  for (const float2& v : hmm) {
-    lo = std::min(lo, v.x);
-    hi = std::max(hi, v.y);
-  }
-  const double range = (double)hi - (double)lo;
-  const double inv_range = range > 0.0 ? 1.0 / range : 1.0;
   // initial knots: clamped uniform with n_init control points
   std::vector<double> T[3];
   for (int a = 0; a < 3; ++a) {
     T[a].resize(n_init[a] + degree[a] + 1);
     default_knots(n_init[a], degree[a], T[a].data());
   }
-  std::vector<double> Q[3], Bt[3], marg(N[0] + N[1] + N[2]);
+  std::vector<double> Z[3], Bv[3], stage, marg(N[0] + N[1] + N[2]);
+  std::vector<int> spans[3];
   double* dmarg = at(lay.marg);
-  const ErrOut eo{values, N[2], inv_range, at(lay.rowpart), at(lay.colpart)};
+  ErrOut eo{values, N[2], 1.0, at(lay.rowpart), at(lay.colpart)};
   int fits = 0;
   for (;;) {
     int64_t n[3];
     for (int a = 0; a < 3; ++a) n[a] = (int64_t)T[a].size() - degree[a] - 1;
-    // the three axes' tables are independent: two of them on helper threads
+    // the three axes' Gram inverses are independent: two of them on helper
+    // threads
     mfa_status sts[3] = {MFA_OK, MFA_OK, MFA_OK};
     std::string msg[3];
     auto tables = [&](int a) {
-      sts[a] = pseudo_inverse(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Q[a], &Bt[a]);
+      sts[a] = gram_inverse(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Z[a], spans[a], Bv[a]);
       if (sts[a] != MFA_OK) msg[a] = mfa_last_error();     // the message is per thread
     };
     std::thread th[2];
@@ -808,12 +909,46 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     for (int k = 0; k < started; ++k) th[k].join();
     for (int a = 0; a < 3; ++a)
       if (sts[a] != MFA_OK) return fail(sts[a], "%s", msg[a].c_str());
-    for (int a = 0; a < 3; ++a) {
-      e = hipMemcpyAsync(at(lay.qt[a]), Q[a].data(), Q[a].size() * 8, hipMemcpyHostToDevice, hs);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(at(lay.bt[a]), Bt[a].data(), Bt[a].size() * 8, hipMemcpyHostToDevice, hs);
-      if (e != hipSuccess) return hip_fail(e, "encode: table upload");
+    if (fits == 0) {
+      std::vector<float2> hmm(kMinMaxBlocks);
+      e = hipMemcpyAsync(hmm.data(), mm, sizeof(float2) * kMinMaxBlocks, hipMemcpyDeviceToHost, hs);
+      if (e == hipSuccess) e = hipStreamSynchronize(hs);
+      if (e != hipSuccess) return hip_fail(e, "encode: data range");
+      float lo = hmm[0].x, hi = hmm[0].y;
+      for (const float2& v : hmm) {
+        lo = std::min(lo, v.x);
+        hi = std::max(hi, v.y);
+      }
+      const double range = (double)hi - (double)lo;
+      eo.inv_range = range > 0.0 ? 1.0 / range : 1.0;
     }
+    // knots and Gram inverses in one copy; the device forms the tables (the
+    // previous pass ended with a synchronisation, so stage is free to reuse)
+    TabArgs ta{};
+    stage.clear();
+    for (int a = 0; a < 3; ++a) {
+      ta.T[a] = at(lay.stage) + stage.size();
+      stage.insert(stage.end(), T[a].begin(), T[a].end());
+    }
+    for (int a = 0; a < 3; ++a) {
+      ta.Z[a] = at(lay.stage) + stage.size();
+      stage.insert(stage.end(), Z[a].begin(), Z[a].end());
+    }
+    e = hipMemcpyAsync(at(lay.stage), stage.data(), stage.size() * 8, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "encode: table upload");
+    int maxN = 0;
+    for (int a = 0; a < 3; ++a) {
+      ta.u[a] = du[a];
+      ta.qt[a] = at(lay.qt[a]);
+      ta.bt[a] = at(lay.bt[a]);
+      ta.N[a] = res[a];
+      ta.n[a] = (int32_t)n[a];
+      ta.p[a] = degree[a];
+      maxN = std::max(maxN, res[a]);
+    }
+    hipLaunchKernelGGL(tables_k, dim3((unsigned)((maxN + 3) / 4), 3), dim3(256), 0, hs, ta);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "encode: tables");
     const double* qt[3] = {at(lay.qt[0]), at(lay.qt[1]), at(lay.qt[2])};
     const double* bt[3] = {at(lay.bt[0]), at(lay.bt[1]), at(lay.bt[2])};
     e = run_fit(N, n, values, ctrl, qt, at(lay.y0), at(lay.y1), hs, at(lay.part), lay.part_cap);
