@@ -16,8 +16,6 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
-#include <system_error>
-#include <thread>
 #include <vector>
 
 #include "mfa_model.h"
@@ -66,7 +64,8 @@ using gptr = const __attribute__((address_space(1))) T*;   // global-memory poin
 
 // With ERR the GEMM is the last product of a reconstruction: instead of
 // storing C it takes every element's relative error against the samples,
-// |C(m, n) - F(m, n)| * inv_range (F(m, n) at f[m * ldf + n]), and stores
+// |C(m, n) - F(m, n)| * inv_range (F(m, n) at f[m * ldf + n], inv_range
+// read from device memory), and stores
 // per tile the largest error of each of its rows, rowpart[jn * M + m], and
 // of each of its columns, colpart[im * N + n] (jn, im: the tile's column
 // and row index); out-of-range elements count as 0.
@@ -75,7 +74,7 @@ constexpr int kErrNT = 2;         // the error product's tiles: 32 x 32 (32 x 64
 struct ErrOut {
   const float* f;
   int64_t ldf;
-  double inv_range;
+  const double* inv_range;
   double* rowpart;
   double* colpart;
 };
@@ -137,7 +136,9 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
   // latency overlaps the products (rows and columns clamped in bounds, the
   // ones past the edge are masked in the epilogue)
   float fv[2][NT][4];
+  double inv_range = 0.0;
   if constexpr (ERR) {
+    inv_range = *eo.inv_range;
     gptr<float> F = (gptr<float>)eo.f;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kGemmBlock) void gemm_f64_k(const double* __restric
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + 16 * t + q + 4 * r, n = n0 + 16 * u + c16;
           acc[t][u][r] = (m < g.M && n < g.N)
-                             ? fabs(acc[t][u][r] - (double)fv[t][u][r]) * eo.inv_range
+                             ? fabs(acc[t][u][r] - (double)fv[t][u][r]) * inv_range
                              : 0.0;
         }
     // rows: the 16 lanes of one q hold a row's 16 NT columns (NT per lane)
@@ -340,6 +341,52 @@ __device__ int tab_span(const double* T, int p, int n, double u) {
   return lo;
 }
 
+// Z = (L L^T)^-1 of each axis from its banded Cholesky factor (layout as
+// on the host, L[j * (p + 1) + d] = L(j, j - d)): thread c solves L y = e_c
+// (y_j = 0 for j < c) and then L^T z = y, into row c of Z (Z is symmetric),
+// keeping the last p values of each recurrence in registers.
+struct ZinvArgs {
+  const double* L[3];
+  double* Z[3];
+  int32_t n[3], p[3];
+};
+
+__global__ __launch_bounds__(64) void zinv_k(ZinvArgs za) {
+  const int a = blockIdx.y, c = blockIdx.x * 64 + threadIdx.x;
+  const int n = za.n[a], p = za.p[a], w = p + 1;
+  if (c >= n) return;
+  const double* L = za.L[a];
+  double* z = za.Z[a] + (int64_t)c * n;
+  for (int j = 0; j < c; ++j) z[j] = 0.0;
+  double win[kMaxDegree + 1];           // win[d] = y_{j-d} (0 before c)
+#pragma unroll
+  for (int d = 0; d <= kMaxDegree; ++d) win[d] = 0.0;
+  for (int j = c; j < n; ++j) {
+    double v = j == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int d = kMaxDegree; d >= 1; --d)
+      if (d <= p) v -= L[(int64_t)j * w + d] * win[d];
+    const double y = v / L[(int64_t)j * w];
+    z[j] = y;
+#pragma unroll
+    for (int d = kMaxDegree; d >= 2; --d) win[d] = win[d - 1];
+    win[1] = y;
+  }
+#pragma unroll
+  for (int d = 0; d <= kMaxDegree; ++d) win[d] = 0.0;   // now win[d] = z_{j+d} (0 past n-1)
+  for (int j = n - 1; j >= 0; --j) {
+    double v = z[j];
+#pragma unroll
+    for (int d = 1; d <= kMaxDegree; ++d)
+      if (d <= p && j + d < n) v -= L[(int64_t)(j + d) * w + d] * win[d];
+    const double x = v / L[(int64_t)j * w];
+    z[j] = x;
+#pragma unroll
+    for (int d = kMaxDegree; d >= 2; --d) win[d] = win[d - 1];
+    win[1] = x;
+  }
+}
+
 // one wave per sample i of axis blockIdx.y; the lanes run over the n
 // control points (rows of Z read along their length, rows of qt written so)
 __global__ __launch_bounds__(256) void tables_k(TabArgs ta) {
@@ -383,6 +430,33 @@ __global__ __launch_bounds__(256) void tables_k(TabArgs ta) {
   }
 }
 
+// inv_range = 1 / (max - min) of the samples from the per-block partial
+// minima and maxima of minmax_k (1 when the samples are constant): one
+// workgroup.
+__global__ __launch_bounds__(256) void range_k(const float2* __restrict__ part, int nb,
+                                               double* __restrict__ inv_range) {
+  __shared__ float lo[256], hi[256];
+  float a = __builtin_inff(), b = -__builtin_inff();
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a = fminf(a, part[i].x);
+    b = fmaxf(b, part[i].y);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o; o >>= 1) {
+    if (threadIdx.x < o) {
+      lo[threadIdx.x] = fminf(lo[threadIdx.x], lo[threadIdx.x + o]);
+      hi[threadIdx.x] = fmaxf(hi[threadIdx.x], hi[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double range = (double)hi[0] - (double)lo[0];
+    *inv_range = range > 0.0 ? 1.0 / range : 1.0;
+  }
+}
+
 // ------------------------------------------------------------------ host: collocation
 // Span rule s = max{ i in [p, n-1] : T[i] <= u }.
 int span_of(const double* T, int p, int n, double u) {
@@ -410,13 +484,12 @@ void basis_values(const double* T, int p, int s, double u, double* N) {
   }
 }
 
-// Z = (B^T B)^-1 (n x n, row-major, symmetric) for the collocation matrix B
-// of one axis: the Gram matrix G = B^T B is banded (bandwidth p) and
-// factorised as L L^T; Z is formed column by column (two banded triangular
-// solves per unit vector).  The spans and basis values of the samples are
-// left in s and Bv ((p + 1) per sample).
-mfa_status gram_inverse(const double* T, int p, int n, const double* u, int N, int axis,
-                        std::vector<double>& Z, std::vector<int>& s, std::vector<double>& Bv) {
+// The Cholesky factor of the Gram matrix G = B^T B of the collocation
+// matrix B of one axis: G is banded (bandwidth p), G = L L^T with L stored
+// by rows, L[j * (p + 1) + d] = L(j, j - d).  The spans and basis values of
+// the samples are left in s and Bv ((p + 1) per sample).
+mfa_status gram_factor(const double* T, int p, int n, const double* u, int N, int axis,
+                       std::vector<double>& L, std::vector<int>& s, std::vector<double>& Bv) {
   const int w = p + 1;
   s.resize(N);
   Bv.resize((size_t)N * w);
@@ -433,7 +506,7 @@ mfa_status gram_inverse(const double* T, int p, int n, const double* u, int N, i
   double gmax = 0.0;
   for (int j = 0; j < n; ++j) gmax = std::max(gmax, G[(size_t)j * w]);
   // L[j * w + d] = L[j][j - d]
-  std::vector<double> L((size_t)n * w, 0.0);
+  L.assign((size_t)n * w, 0.0);
   for (int j = 0; j < n; ++j)
     for (int k = std::max(0, j - p); k <= j; ++k) {
       double v = G[(size_t)j * w + (j - k)];
@@ -449,6 +522,17 @@ mfa_status gram_inverse(const double* T, int p, int n, const double* u, int N, i
         L[(size_t)j * w] = std::sqrt(v);
       }
     }
+  return MFA_OK;
+}
+
+// Z = (B^T B)^-1 = (L L^T)^-1 (n x n, row-major, symmetric), formed column
+// by column (two banded triangular solves per unit vector).
+mfa_status gram_inverse(const double* T, int p, int n, const double* u, int N, int axis,
+                        std::vector<double>& Z, std::vector<int>& s, std::vector<double>& Bv) {
+  const int w = p + 1;
+  std::vector<double> L;
+  const mfa_status st = gram_factor(T, p, n, u, N, axis, L, s, Bv);
+  if (st != MFA_OK) return st;
   Z.resize((size_t)n * n);
   std::vector<double> y(n);
   for (int c = 0; c < n; ++c) {
@@ -758,12 +842,13 @@ namespace {
 // product, columns i2), their reduction scratch, the three marginals and the
 // split-K partial products of the fit (a split product has at most 2048
 // tiles of 32 x 32 over all its chunks, so 2^21 values always suffice), the
-// sample parameters, and the staging area of each fit's knots and Gram
-// inverses (packed, at most max_ctrl + kMaxDegree + 1 and max_ctrl^2 per
-// axis).
+// sample parameters, the staging area of each fit's knots and Gram factors
+// (packed, at most max_ctrl + kMaxDegree + 1 and (kMaxDegree + 1) max_ctrl
+// values per axis), the Gram inverses (packed, at most max_ctrl^2 per axis)
+// and 1 / data range.
 struct AdaptLayout {
   size_t qt[3], bt[3], y0, y1, r0, r1, rowpart, colpart, rowmax, red0, red1, marg, mm, part, u, stage,
-      total;
+      z, inv, total;
   int64_t part_cap;
 };
 
@@ -797,7 +882,9 @@ AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   L.part_cap = std::min<int64_t>(kSplitCap, 8 * (int64_t)(m0 * m1 * N2));
   L.part = take(8 * (size_t)L.part_cap);
   L.u = take(8 * (N0 + N1 + N2));
-  L.stage = take(8 * (m0 + m1 + m2 + 3 * (kMaxDegree + 1) + m0 * m0 + m1 * m1 + m2 * m2));
+  L.stage = take(8 * (m0 + m1 + m2 + 3 * (kMaxDegree + 1) + (kMaxDegree + 1) * (m0 + m1 + m2)));
+  L.z = take(8 * (m0 * m0 + m1 * m1 + m2 * m2));
+  L.inv = take(8);
   L.total = o;
   return L;
 }
@@ -871,10 +958,14 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
   for (int a = 0; a < 3; ++a) std::copy(axis_u[a], axis_u[a] + res[a], hu.begin() + (du[a] - du[0]));
   hipError_t e = hipMemcpyAsync(at(lay.u), hu.data(), hu.size() * 8, hipMemcpyHostToDevice, hs);
   if (e != hipSuccess) return hip_fail(e, "encode: parameter upload");
-  // data range, reduced on the device while the host forms the first tables
+  // data range, reduced on the device (the error products read 1 / range there)
   float2* mm = reinterpret_cast<float2*>(wb + lay.mm);
   hipLaunchKernelGGL(minmax_k, dim3(kMinMaxBlocks), dim3(256), 0, hs, values, rows * N[2], mm);
   e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(range_k, dim3(1), dim3(256), 0, hs, mm, kMinMaxBlocks, at(lay.inv));
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return hip_fail(e, "encode: data range");
   // initial knots: clamped uniform with n_init control points
   std::vector<double> T[3];
@@ -882,62 +973,48 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     T[a].resize(n_init[a] + degree[a] + 1);
     default_knots(n_init[a], degree[a], T[a].data());
   }
-  std::vector<double> Z[3], Bv[3], stage, marg(N[0] + N[1] + N[2]);
+  std::vector<double> Lg[3], Bv[3], stage, marg(N[0] + N[1] + N[2]);
   std::vector<int> spans[3];
   double* dmarg = at(lay.marg);
-  ErrOut eo{values, N[2], 1.0, at(lay.rowpart), at(lay.colpart)};
+  const ErrOut eo{values, N[2], at(lay.inv), at(lay.rowpart), at(lay.colpart)};
   int fits = 0;
   for (;;) {
     int64_t n[3];
     for (int a = 0; a < 3; ++a) n[a] = (int64_t)T[a].size() - degree[a] - 1;
-    // the three axes' Gram inverses are independent: two of them on helper
-    // threads
-    mfa_status sts[3] = {MFA_OK, MFA_OK, MFA_OK};
-    std::string msg[3];
-    auto tables = [&](int a) {
-      sts[a] = gram_inverse(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Z[a], spans[a], Bv[a]);
-      if (sts[a] != MFA_OK) msg[a] = mfa_last_error();     // the message is per thread
-    };
-    std::thread th[2];
-    int started = 0;                                  // axes 1..started run on threads
-    try {
-      for (; started < 2; ++started) th[started] = std::thread(tables, started + 1);
-    } catch (const std::system_error&) {
-    }
-    for (int a = 0; a < 3; ++a)
-      if (a == 0 || a > started) tables(a);
-    for (int k = 0; k < started; ++k) th[k].join();
-    for (int a = 0; a < 3; ++a)
-      if (sts[a] != MFA_OK) return fail(sts[a], "%s", msg[a].c_str());
-    if (fits == 0) {
-      std::vector<float2> hmm(kMinMaxBlocks);
-      e = hipMemcpyAsync(hmm.data(), mm, sizeof(float2) * kMinMaxBlocks, hipMemcpyDeviceToHost, hs);
-      if (e == hipSuccess) e = hipStreamSynchronize(hs);
-      if (e != hipSuccess) return hip_fail(e, "encode: data range");
-      float lo = hmm[0].x, hi = hmm[0].y;
-      for (const float2& v : hmm) {
-        lo = std::min(lo, v.x);
-        hi = std::max(hi, v.y);
+    // the Gram factors on the host (banded, O(res p^2) per axis); the device
+    // inverts them and forms the tables
+    for (int a = 0; a < 3; ++a) {
+      const mfa_status sa = gram_factor(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Lg[a],
+                                        spans[a], Bv[a]);
+      if (sa != MFA_OK) {
+        (void)hipStreamSynchronize(hs);        // the parameter upload has its source in hu
+        return sa;
       }
-      const double range = (double)hi - (double)lo;
-      eo.inv_range = range > 0.0 ? 1.0 / range : 1.0;
     }
-    // knots and Gram inverses in one copy; the device forms the tables (the
-    // previous pass ended with a synchronisation, so stage is free to reuse)
+    // knots and Gram factors in one copy (the previous pass ended with a
+    // synchronisation, so stage is free to reuse)
     TabArgs ta{};
+    ZinvArgs za{};
     stage.clear();
     for (int a = 0; a < 3; ++a) {
       ta.T[a] = at(lay.stage) + stage.size();
       stage.insert(stage.end(), T[a].begin(), T[a].end());
     }
     for (int a = 0; a < 3; ++a) {
-      ta.Z[a] = at(lay.stage) + stage.size();
-      stage.insert(stage.end(), Z[a].begin(), Z[a].end());
+      za.L[a] = at(lay.stage) + stage.size();
+      stage.insert(stage.end(), Lg[a].begin(), Lg[a].end());
     }
     e = hipMemcpyAsync(at(lay.stage), stage.data(), stage.size() * 8, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "encode: table upload");
-    int maxN = 0;
+    int maxN = 0, maxn = 0;
+    int64_t zo = 0;
     for (int a = 0; a < 3; ++a) {
+      za.Z[a] = at(lay.z) + zo;
+      za.n[a] = (int32_t)n[a];
+      za.p[a] = degree[a];
+      zo += n[a] * n[a];
+      maxn = std::max(maxn, (int)n[a]);
+      ta.Z[a] = za.Z[a];
       ta.u[a] = du[a];
       ta.qt[a] = at(lay.qt[a]);
       ta.bt[a] = at(lay.bt[a]);
@@ -946,8 +1023,12 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
       ta.p[a] = degree[a];
       maxN = std::max(maxN, res[a]);
     }
-    hipLaunchKernelGGL(tables_k, dim3((unsigned)((maxN + 3) / 4), 3), dim3(256), 0, hs, ta);
+    hipLaunchKernelGGL(zinv_k, dim3((unsigned)((maxn + 63) / 64), 3), dim3(64), 0, hs, za);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(tables_k, dim3((unsigned)((maxN + 3) / 4), 3), dim3(256), 0, hs, ta);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return hip_fail(e, "encode: tables");
     const double* qt[3] = {at(lay.qt[0]), at(lay.qt[1]), at(lay.qt[2])};
     const double* bt[3] = {at(lay.bt[0]), at(lay.bt[1]), at(lay.bt[2])};

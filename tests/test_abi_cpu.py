@@ -185,7 +185,8 @@ def test_encode_adaptive_workspace_size_and_rejections():
     want += al(8 * m0 * N1 * N2) + al(8 * N2 * m0 * m1) + al(8 * N0 * m1 * m2) + al(8 * m2 * M) \
         + al(8 * tn * M) + al(8 * tm * N2) + al(8 * M) + 2 * al(8 * red) \
         + al(8 * (N0 + N1 + N2)) + al(8 * 2048) + al(8 * min(1 << 21, 8 * m0 * m1 * N2)) \
-        + al(8 * (N0 + N1 + N2)) + al(8 * (m0 + m1 + m2 + 3 * 8 + m0 * m0 + m1 * m1 + m2 * m2))
+        + al(8 * (N0 + N1 + N2)) + al(8 * (m0 + m1 + m2 + 3 * 8 + 8 * (m0 + m1 + m2))) \
+        + al(8 * (m0 * m0 + m1 * m1 + m2 * m2)) + al(8)
     assert nb.value == want
     assert lib.mfa_encode_adaptive_workspace(_i3(4, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_E_ARG
 
