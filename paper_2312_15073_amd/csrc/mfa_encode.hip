@@ -342,48 +342,65 @@ __device__ int tab_span(const double* T, int p, int n, double u) {
 }
 
 // Z = (L L^T)^-1 of each axis from its banded Cholesky factor (layout as
-// on the host, L[j * (p + 1) + d] = L(j, j - d)): thread c solves L y = e_c
-// (y_j = 0 for j < c) and then L^T z = y, into row c of Z (Z is symmetric),
-// keeping the last p values of each recurrence in registers.
+// on the host, L[j * (p + 1) + d] = L(j, j - d), except that the diagonal
+// slot d = 0 holds 1 / L(j, j)): thread c solves L y = e_c (y_j = 0 for
+// j < c) and then L^T z = y, into row c of Z (Z is symmetric), keeping the
+// last p values of each recurrence in registers.
 struct ZinvArgs {
   const double* L[3];
   double* Z[3];
   int32_t n[3], p[3];
 };
 
-__global__ __launch_bounds__(64) void zinv_k(ZinvArgs za) {
-  const int a = blockIdx.y, c = blockIdx.x * 64 + threadIdx.x;
-  const int n = za.n[a], p = za.p[a], w = p + 1;
-  if (c >= n) return;
-  const double* L = za.L[a];
-  double* z = za.Z[a] + (int64_t)c * n;
+template <int P>
+__device__ __forceinline__ void zinv_row(const double* __restrict__ L, double* __restrict__ z, int n,
+                                         int c) {
+  constexpr int w = P + 1;
   for (int j = 0; j < c; ++j) z[j] = 0.0;
-  double win[kMaxDegree + 1];           // win[d] = y_{j-d} (0 before c)
+  double win[P + 1];                    // win[d] = y_{j-d} (0 before c)
 #pragma unroll
-  for (int d = 0; d <= kMaxDegree; ++d) win[d] = 0.0;
+  for (int d = 0; d <= P; ++d) win[d] = 0.0;
+#pragma unroll 4
   for (int j = c; j < n; ++j) {
     double v = j == c ? 1.0 : 0.0;
 #pragma unroll
-    for (int d = kMaxDegree; d >= 1; --d)
-      if (d <= p) v -= L[(int64_t)j * w + d] * win[d];
-    const double y = v / L[(int64_t)j * w];
+    for (int d = P; d >= 1; --d) v -= L[(int64_t)j * w + d] * win[d];
+    const double y = v * L[(int64_t)j * w];
     z[j] = y;
 #pragma unroll
-    for (int d = kMaxDegree; d >= 2; --d) win[d] = win[d - 1];
+    for (int d = P; d >= 2; --d) win[d] = win[d - 1];
     win[1] = y;
   }
 #pragma unroll
-  for (int d = 0; d <= kMaxDegree; ++d) win[d] = 0.0;   // now win[d] = z_{j+d} (0 past n-1)
+  for (int d = 0; d <= P; ++d) win[d] = 0.0;   // now win[d] = z_{j+d} (0 past n-1)
+#pragma unroll 4
   for (int j = n - 1; j >= 0; --j) {
     double v = z[j];
 #pragma unroll
-    for (int d = 1; d <= kMaxDegree; ++d)
-      if (d <= p && j + d < n) v -= L[(int64_t)(j + d) * w + d] * win[d];
-    const double x = v / L[(int64_t)j * w];
+    for (int d = 1; d <= P; ++d)
+      if (j + d < n) v -= L[(int64_t)(j + d) * w + d] * win[d];
+    const double x = v * L[(int64_t)j * w];
     z[j] = x;
 #pragma unroll
-    for (int d = kMaxDegree; d >= 2; --d) win[d] = win[d - 1];
+    for (int d = P; d >= 2; --d) win[d] = win[d - 1];
     win[1] = x;
+  }
+}
+
+__global__ __launch_bounds__(64) void zinv_k(ZinvArgs za) {
+  const int a = blockIdx.y, c = blockIdx.x * 64 + threadIdx.x;
+  const int n = za.n[a];
+  if (c >= n) return;
+  const double* L = za.L[a];
+  double* z = za.Z[a] + (int64_t)c * n;
+  switch (za.p[a]) {
+    case 1: zinv_row<1>(L, z, n, c); break;
+    case 2: zinv_row<2>(L, z, n, c); break;
+    case 3: zinv_row<3>(L, z, n, c); break;
+    case 4: zinv_row<4>(L, z, n, c); break;
+    case 5: zinv_row<5>(L, z, n, c); break;
+    case 6: zinv_row<6>(L, z, n, c); break;
+    default: zinv_row<kMaxDegree>(L, z, n, c); break;
   }
 }
 
@@ -1002,7 +1019,9 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     }
     for (int a = 0; a < 3; ++a) {
       za.L[a] = at(lay.stage) + stage.size();
+      const size_t o = stage.size();
       stage.insert(stage.end(), Lg[a].begin(), Lg[a].end());
+      for (int64_t j = 0; j < n[a]; ++j) stage[o + j * (degree[a] + 1)] = 1.0 / stage[o + j * (degree[a] + 1)];
     }
     e = hipMemcpyAsync(at(lay.stage), stage.data(), stage.size() * 8, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "encode: table upload");
