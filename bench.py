@@ -234,42 +234,32 @@ def run_single128(args, graded: bool = False):
     n_grid = GRID_N ** 3
     samples_step = n_grid + N_POINTS + s_frame
 
-    # The frame runs on the main stream and the two decodes on a second one
-    # (default priority): independent outputs from the same model, so the
-    # decodes fill the CUs that the frame's longest ray tiles leave idle
-    # while they finish.  Each kernel is timed on its own stream.
-    side = torch.cuda.Stream(device=dev)
-    spans = {"render": (0, 1), "decode_grid": (2, 3), "decode_points": (3, 4)}
+    names = ["decode_grid", "decode_points", "render"]
 
     def step(ev=None):
-        side.wait_stream(stream)
         if ev is not None:
             ev[0].record(stream)
-        mfa.render_frame(model, cam, params, FRAME, FRAME, tf_dev=tf, out=rgba, device=dev)
+        mfa.decode_grid(model, axes, out=grid_out)
         if ev is not None:
             ev[1].record(stream)
-        with torch.cuda.stream(side):
-            if ev is not None:
-                ev[2].record(side)
-            mfa.decode_grid(model, axes, out=grid_out)
-            if ev is not None:
-                ev[3].record(side)
-            mfa.decode_points(model, xyz, out=pts_out, sorted_order=True)
-            if ev is not None:
-                ev[4].record(side)
-        stream.wait_stream(side)
+        mfa.decode_points(model, xyz, out=pts_out, sorted_order=True)
+        if ev is not None:
+            ev[2].record(stream)
+        mfa.render_frame(model, cam, params, FRAME, FRAME, tf_dev=tf, out=rgba, device=dev)
+        if ev is not None:
+            ev[3].record(stream)
 
     for _ in range(args.warmup):
         step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(events[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern_ms = {n: float(np.mean([events[k][i].elapsed_time(events[k][j]) for k in range(args.steps)]))
-               for n, (i, j) in spans.items()}
+    kern_ms = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1])
+                                 for k in range(args.steps)])) for i, n in enumerate(names)}
     ms_step = 1e3 * elapsed / args.steps
     info = model.info()
 
@@ -323,9 +313,7 @@ def run_single128(args, graded: bool = False):
                                 f"(max 1024 samples/ray)"),
                    "samples_per_step": samples_step, "frame_samples": s_frame,
                    "frame_samples_evaluated": s_eval,
-                   "parallelism": "single GPU",
-                   "streams": "frame on the main stream, grid and point decodes on a second "
-                              "stream (concurrent; kernel times measured under that overlap)"},
+                   "parallelism": "single GPU"},
         "ms_per_frame": kern_ms["render"],
         "kernels": kernels,
         "roofline": roofline,
