@@ -50,8 +50,8 @@ FRAME = 1024
 TRAFFIC = {
     # 1024^2 frame of the 128^3 model; copy reference: 512 MiB read + 512 MiB
     # written, FETCH_SIZE 262162 KiB (scale 2.0), WRITE_SIZE 524288 KiB (1.0)
-    "render": {"kernels_sha256": "f8a477cca305c92dd9d9a850f37628c2e67819618674325f96fec96222f7ae04",
-               "fetch_kib": 31635.3, "fetch_scale": 2.0, "write_kib": 16384.0, "write_scale": 1.0},
+    "render": {"kernels_sha256": "6916f073cec718f0efe15a3b7cbbe38c7ce7f3d9df1e8daf0fd2865ca3de8f5e",
+               "fetch_kib": 37295.8, "fetch_scale": 2.0, "write_kib": 16399.2, "write_scale": 1.0},
 }
 
 
