@@ -265,7 +265,8 @@ def run_single128(args, graded: bool = False):
 
     fl = flop_per_sample(p)
     fl_r = fl + 54
-    model_bytes = info["device_bytes"]
+    model_bytes = info["ctrl_bytes"]     # the model read once per launch (device_bytes also
+                                         # counts the sorted decode's scratch)
     grid_bytes = n_grid * 16 + model_bytes + 3 * GRID_N * 8
     pts_bytes = N_POINTS * 28 + model_bytes
     kernels = {
