@@ -352,8 +352,12 @@ struct ZinvArgs {
   int32_t n[3], p[3];
 };
 
+constexpr int kZinvThreads = 16;      // columns per workgroup (their y rows share the LDS)
+
+// L and y in LDS (the recurrences' operands one LDS round trip away), z
+// written to global memory once.
 template <int P>
-__device__ __forceinline__ void zinv_row(const double* __restrict__ L, double* __restrict__ z, int n,
+__device__ __forceinline__ void zinv_row(const double* L, double* y, double* __restrict__ z, int n,
                                          int c) {
   constexpr int w = P + 1;
   for (int j = 0; j < c; ++j) z[j] = 0.0;
@@ -364,22 +368,33 @@ __device__ __forceinline__ void zinv_row(const double* __restrict__ L, double* _
   for (int j = c; j < n; ++j) {
     double v = j == c ? 1.0 : 0.0;
 #pragma unroll
-    for (int d = P; d >= 1; --d) v -= L[(int64_t)j * w + d] * win[d];
-    const double y = v * L[(int64_t)j * w];
-    z[j] = y;
+    for (int d = P; d >= 1; --d) v -= L[j * w + d] * win[d];
+    const double yj = v * L[j * w];
+    y[j] = yj;
 #pragma unroll
     for (int d = P; d >= 2; --d) win[d] = win[d - 1];
-    win[1] = y;
+    win[1] = yj;
   }
 #pragma unroll
   for (int d = 0; d <= P; ++d) win[d] = 0.0;   // now win[d] = z_{j+d} (0 past n-1)
 #pragma unroll 4
-  for (int j = n - 1; j >= 0; --j) {
-    double v = z[j];
+  for (int j = n - 1; j >= c; --j) {           // z_j for j < c needs y_j = 0 only
+    double v = y[j];
 #pragma unroll
     for (int d = 1; d <= P; ++d)
-      if (j + d < n) v -= L[(int64_t)(j + d) * w + d] * win[d];
-    const double x = v * L[(int64_t)j * w];
+      if (j + d < n) v -= L[(j + d) * w + d] * win[d];
+    const double x = v * L[j * w];
+    z[j] = x;
+#pragma unroll
+    for (int d = P; d >= 2; --d) win[d] = win[d - 1];
+    win[1] = x;
+  }
+  for (int j = c - 1; j >= 0; --j) {
+    double v = 0.0;
+#pragma unroll
+    for (int d = 1; d <= P; ++d)
+      if (j + d < n) v -= L[(j + d) * w + d] * win[d];
+    const double x = v * L[j * w];
     z[j] = x;
 #pragma unroll
     for (int d = P; d >= 2; --d) win[d] = win[d - 1];
@@ -387,20 +402,27 @@ __device__ __forceinline__ void zinv_row(const double* __restrict__ L, double* _
   }
 }
 
-__global__ __launch_bounds__(64) void zinv_k(ZinvArgs za) {
-  const int a = blockIdx.y, c = blockIdx.x * 64 + threadIdx.x;
-  const int n = za.n[a];
+// dynamic LDS: the axis' factor (n (p + 1) values), then one y row of n
+// values per thread
+__global__ __launch_bounds__(kZinvThreads) void zinv_k(ZinvArgs za) {
+  extern __shared__ double zsh[];
+  const int a = blockIdx.y, c = blockIdx.x * kZinvThreads + threadIdx.x;
+  const int n = za.n[a], p = za.p[a];
+  if (blockIdx.x * kZinvThreads >= n) return;                  // whole workgroup
+  for (int q = threadIdx.x; q < n * (p + 1); q += kZinvThreads) zsh[q] = za.L[a][q];
+  __syncthreads();
   if (c >= n) return;
-  const double* L = za.L[a];
+  const double* L = zsh;
+  double* y = zsh + n * (p + 1) + threadIdx.x * n;
   double* z = za.Z[a] + (int64_t)c * n;
-  switch (za.p[a]) {
-    case 1: zinv_row<1>(L, z, n, c); break;
-    case 2: zinv_row<2>(L, z, n, c); break;
-    case 3: zinv_row<3>(L, z, n, c); break;
-    case 4: zinv_row<4>(L, z, n, c); break;
-    case 5: zinv_row<5>(L, z, n, c); break;
-    case 6: zinv_row<6>(L, z, n, c); break;
-    default: zinv_row<kMaxDegree>(L, z, n, c); break;
+  switch (p) {
+    case 1: zinv_row<1>(L, y, z, n, c); break;
+    case 2: zinv_row<2>(L, y, z, n, c); break;
+    case 3: zinv_row<3>(L, y, z, n, c); break;
+    case 4: zinv_row<4>(L, y, z, n, c); break;
+    case 5: zinv_row<5>(L, y, z, n, c); break;
+    case 6: zinv_row<6>(L, y, z, n, c); break;
+    default: zinv_row<kMaxDegree>(L, y, z, n, c); break;
   }
 }
 
@@ -1042,7 +1064,10 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
       ta.p[a] = degree[a];
       maxN = std::max(maxN, res[a]);
     }
-    hipLaunchKernelGGL(zinv_k, dim3((unsigned)((maxn + 63) / 64), 3), dim3(64), 0, hs, za);
+    int maxw = 0;
+    for (int a = 0; a < 3; ++a) maxw = std::max(maxw, (int)n[a] * (degree[a] + 1) + kZinvThreads * (int)n[a]);
+    hipLaunchKernelGGL(zinv_k, dim3((unsigned)((maxn + kZinvThreads - 1) / kZinvThreads), 3),
+                       dim3(kZinvThreads), (size_t)maxw * 8, hs, za);
     e = hipGetLastError();
     if (e == hipSuccess) {
       hipLaunchKernelGGL(tables_k, dim3((unsigned)((maxN + 3) / 4), 3), dim3(256), 0, hs, ta);
