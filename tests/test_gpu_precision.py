@@ -8,7 +8,8 @@ frame of the same model and against the frame of the analytic field (the
 paper's ground-truth comparison, Table II / Fig. 10).  "Equal image error"
 holds when the reduced form's RMSE against ground truth is within 5 % of
 the FP32 one or both 8-bit PSNRs differ by at most 0.1 dB.  The table is
-written to gpurun_out/precision_table.json.
+printed, and written as precision_table.json into the directory named by
+the MFA_TABLE_DIR environment variable when it is set.
 """
 import json
 import os
@@ -25,7 +26,6 @@ from tests.gpu_common import announce
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _rel(d, scale):
@@ -82,8 +82,8 @@ def test_precision_tables(dev):
         r["equal_image_error_to_f32"] = bool(
             r["image_rmse_vs_ground_truth"] <= 1.05 * f32["image_rmse_vs_ground_truth"]
             or abs(r["image_psnr8_vs_ground_truth"] - f32["image_psnr8_vs_ground_truth"]) <= 0.1)
-    outdir = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(outdir):
+    outdir = os.environ.get("MFA_TABLE_DIR")
+    if outdir and os.path.isdir(outdir):
         with open(os.path.join(outdir, "precision_table.json"), "w") as fh:
             json.dump(rows, fh, indent=1)
     for r in rows:
