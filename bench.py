@@ -10,8 +10,11 @@ sort is inside the timed step).  Inputs are resident in device memory
 before timing starts.
 
 Prints one JSON line.  value = decoded samples (value + gradient) per second
-over the step, counting the grid points, the random points and every sample
-the frame composites.
+over the step, counting the grid points, the random points and the frame
+samples whose value and gradient the renderer evaluates.  Samples that the
+renderer steps over exactly (the transfer function is zero over the value
+bounds of their cell, so they cannot change the pixel) are not decoded and
+not counted; they are reported as frame_samples_stepped.
 """
 from __future__ import annotations
 
@@ -131,6 +134,29 @@ def cpu_baseline(spec, cam, params, pts):
 
 
 def _cpu_model() -> str:
+    """The host CPU as lscpu names it (model name, family/model/stepping,
+    sockets x cores x threads, hypervisor), else /proc/cpuinfo's model name."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, timeout=10).stdout
+        f = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f[k.strip()] = v.strip()
+        if "Model name" in f:
+            desc = f["Model name"]
+            if "CPU family" in f:
+                desc += (f" (family {f['CPU family']}, model {f.get('Model', '?')}, "
+                         f"stepping {f.get('Stepping', '?')})")
+            desc += (f"; {f.get('Socket(s)', '?')} socket(s) x {f.get('Core(s) per socket', '?')} "
+                     f"cores x {f.get('Thread(s) per core', '?')} threads, {f.get('CPU(s)', '?')} CPUs")
+            if "Hypervisor vendor" in f:
+                desc += f", {f['Hypervisor vendor']} guest"
+            return desc
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
@@ -232,7 +258,7 @@ def run_single128(args, graded: bool = False):
     s_eval = int(ne.sum().item())
     del ns, ne
     n_grid = GRID_N ** 3
-    samples_step = n_grid + N_POINTS + s_frame
+    samples_step = n_grid + N_POINTS + s_eval       # decoded samples only
 
     names = ["decode_grid", "decode_points", "render"]
 
@@ -313,7 +339,7 @@ def run_single128(args, graded: bool = False):
                                 f"{N_POINTS} random points + {FRAME}x{FRAME} perspective frame "
                                 f"(max 1024 samples/ray)"),
                    "samples_per_step": samples_step, "frame_samples": s_frame,
-                   "frame_samples_evaluated": s_eval,
+                   "frame_samples_evaluated": s_eval, "frame_samples_stepped": s_frame - s_eval,
                    "parallelism": "single GPU"},
         "ms_per_frame": kern_ms["render"],
         "kernels": kernels,
@@ -430,7 +456,7 @@ def run_multiblock(args):
     dk = kernels[dom]
     roofline = {"bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
                 "unit": dk["unit"], "frac": dk["frac"], "traffic": None, "kernel": dom}
-    samples_step = MB_POINTS + s_frame
+    samples_step = MB_POINTS + s_eval                # decoded samples only
     print(json.dumps({
         "metric": METRIC, "value": samples_step / (ms_step * 1e-3), "unit": "samples/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -442,7 +468,8 @@ def run_multiblock(args):
                                 f"sorted decode of {MB_POINTS} random points + {MB_FRAME}^2 "
                                 f"perspective frame (max 2048 samples/ray)"),
                    "samples_per_step": samples_step, "frame_samples": s_frame,
-                   "frame_samples_evaluated": s_eval, "parallelism": "single GPU"},
+                   "frame_samples_evaluated": s_eval, "frame_samples_stepped": s_frame - s_eval,
+                   "parallelism": "single GPU"},
         "ms_per_frame": kms["render"], "kernels": kernels, "roofline": roofline,
         "cpu_baseline": cpu}), flush=True)
     model.close()

@@ -303,14 +303,23 @@ def test_reduced_precision_storage(mfa, dev, dtype, p):
                         extra_g=2 * p * (16 - p) * dP)
 
 
-def test_render_bf16_matches_oracle_on_stored_points(mfa, dev, c1):
-    qP = quant.stored_values(c1.blocks[0].ctrl, "bf16")
-    qmodel = synth.single_block_model(qP, [3] * 3, c1.blocks[0].knots, voxel=c1.voxel)
-    W = H = 64
-    cam = synth.ortho_camera(W, H, az_deg=120)
-    params = synth.render_params(c1)
-    announce("render c1 bf16 64x64")
-    check_render(mfa, dev, c1, cam, params, W, H, storage="bf16", ref_model=qmodel)
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_render_degree_and_storage(mfa, dev, p, storage):
+    """Every degree's and storage form's render kernel against the oracle on
+    the control points as stored (the kernel's own arithmetic error): sample
+    schedule exact, FP32 replay of the termination exact, samples used equal
+    outside the threshold band, image within the render tolerance.  The frame
+    is ragged (70 x 54: partial 8 x 8 tiles on two sides)."""
+    model = synth.model_c1(p=p)
+    qP = quant.stored_values(model.blocks[0].ctrl, storage)
+    qmodel = synth.single_block_model(qP, [p] * 3, model.blocks[0].knots, voxel=model.voxel)
+    W, H = 70, 54
+    cam = synth.perspective_camera(W, H, az_deg=25.0 + 40.0 * p, el_deg=15.0 + 5.0 * p, dist=1.9)
+    params = synth.render_params(model)
+    announce(f"render c1 p={p} {storage} {W}x{H} perspective")
+    r = check_render(mfa, dev, model, cam, params, W, H, storage=storage, ref_model=qmodel)
+    assert r["samples"] > 20000 and r["evaluated"] < r["samples"]
 
 
 # ------------------------------------------------------------------ full-size workloads (sampled)
@@ -589,14 +598,33 @@ def test_server_results_equal_direct_calls(mfa, dev, c1):
                 t = S.submit_points(ids[k], x, out)
                 jobs.append(("p", k, t, out, x))
         stats = [S.wait(j[2]) for j in jobs]
+    # the oracle on the control points as each model stores them
+    qc1 = synth.single_block_model(quant.stored_values(c1.blocks[0].ctrl, "bf16"), [3] * 3,
+                                   c1.blocks[0].knots, voxel=c1.voxel)
+    oracle_specs = [c1, qc1, multi]
+    pmax = [np.max(np.abs(c1.blocks[0].ctrl))] * 2 + [max(np.abs(b.ctrl).max() for b in multi.blocks)]
     for (kind, k, t, out, arg), st in zip(jobs, stats):
         assert st["status"] == 0 and st["done"] == 1
+        got = out.cpu().numpy()
         if kind == "r":
             cam, params, W, H, tf = arg
             ref = mfa.render_frame(models[k], cam, params, W, H, tf_dev=tf, device=dev)
         else:
             ref = mfa.decode_points(models[k], arg)
-        np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32),
-                                      ref.cpu().numpy().view(np.uint32))
+        # served results equal the direct calls bit for bit ...
+        np.testing.assert_array_equal(got.view(np.uint32), ref.cpu().numpy().view(np.uint32))
+        # ... and the oracle at the decode and render tolerances
+        spec = oracle_specs[k]
+        if kind == "r":
+            ro = orr.render(orr.model_field(spec), spec.lo, spec.hi, cam, params, W, H,
+                            record_alpha=True)
+            band = composite_band(ro["alpha"], ro["used"], float(params["ert_alpha"]))
+            diff = np.abs(got.reshape(-1, 4)[~band] - ro["rgba"][~band])
+            assert diff.max(initial=0.0) <= 1e-3, f"served frame {t}: max-abs {diff.max():.3e}"
+            rmse = float(np.sqrt(np.mean(diff ** 2))) if diff.size else 0.0
+            assert rmse <= 1e-5, f"served frame {t}: RMSE {rmse:.3e}"
+        else:
+            po = oracle_points(spec, arg.cpu().numpy().T)
+            assert_values_close(got, po["f"], po["grad"], pmax[k])
     for M in models:
         M.close()
