@@ -132,27 +132,35 @@ mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst,
 /* ------------------------------------------------------------------ decode */
 
 /* Value and gradient at n world points (the value/gradient query of
- * Sec. IV-A4; analytic derivatives, Sec. III-B).
+ * Sec. IV-A4; analytic derivatives, Sec. III-B; the value-only query of
+ * Fig. 8a with MFA_DECODE_VALUE).
  *  xyz   : device FP32, structure of arrays [3][n] (x then y then z); each
  *          coordinate is promoted exactly to FP64.
  *  n     : 0 <= n < 2^31 (n == 0 is a no-op).
- *  flags : 0, or MFA_DECODE_SORTED: points are first grouped by bucket =
- *          (owning block, tile of 2^k spans per axis, k chosen per model for
- *          at most 4096 buckets; models of more than 4096 blocks return
+ *  flags : a combination of
+ *          MFA_DECODE_SORTED: points are first grouped by bucket = (owning
+ *          block, tile of 2^k spans per axis, k chosen per model for at most
+ *          4096 buckets; models of more than 4096 blocks return
  *          MFA_E_UNSUPPORTED) and evaluated in that order, so neighbouring
- *          threads share control points; results are still written in
- *          input order and are identical bit for bit to the unsorted call.
- *          Uses scratch memory held by the model (16 bytes per point plus
- *          12 per bucket, allocated on first use and grown when a larger n
- *          arrives; MFA_E_NOMEM if that fails).  Sorted calls on one model
- *          must not overlap in time (they share the scratch).
- *  out   : device FP32 [n][4] = (f, df/dx, df/dy, df/dz) in world units.
+ *          threads share control points; results are still written in input
+ *          order and are identical bit for bit to the unsorted call.  Uses
+ *          scratch memory held by the model (16 bytes per point, 32 with
+ *          more than 64 buckets, plus 12 per bucket), allocated on first use
+ *          and grown when a larger n arrives (MFA_E_NOMEM if that fails).
+ *          Sorted calls on one model are ordered by the library: a call
+ *          waits (on its stream) for the previous sorted call's kernels
+ *          before it reuses the scratch, and for their completion (on the
+ *          host) before it replaces a smaller one.
+ *          MFA_DECODE_VALUE: value only, no gradient.
+ *  out   : device FP32 [n][4] = (f, df/dx, df/dy, df/dz) in world units;
+ *          with MFA_DECODE_VALUE device FP32 [n] = f.
  *  dbg   : NULL, or device int32 [n][4] = (span0, span1, span2, block)
  *          with block = (b0*grid1 + b1)*grid2 + b2.
  * Map: xc = clamp(x, E[0], E[G]); owning block b = max{i : E[i] <= xc};
  * u = clamp((xc - lo_b) * inv_ext_b, 0, 1) with inv_ext_b = 1/(hi_b - lo_b)
  * (FP64, unfused); span s = max{i in [p, n-1] : T[i] <= u}.               */
 #define MFA_DECODE_SORTED 1u
+#define MFA_DECODE_VALUE 2u
 mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint32_t flags,
                              float* out, int32_t* dbg, void* stream);
 
@@ -161,12 +169,14 @@ mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint3
  *  axis_u : three device FP64 tables of res[a] parameters (clamped to
  *           [0,1]); any order, nondecreasing tables are fastest.
  *  res    : 1 <= res[a], res0*res1*res2 < 2^40.
+ *  flags  : 0, or MFA_DECODE_VALUE (value only).
  *  out    : device FP32 [res0][res1][res2][4] (axis 2 fastest) =
- *           (f, df/dx, df/dy, df/dz), gradient in world units.
+ *           (f, df/dx, df/dy, df/dz), gradient in world units; with
+ *           MFA_DECODE_VALUE device FP32 [res0][res1][res2] = f.
  *  spans  : NULL, or device int32 [res0 + res1 + res2]: the span of each
  *           table entry, axis 0 entries first.                             */
 mfa_status mfa_decode_grid(mfa_model model, const double* const axis_u[3], const int32_t res[3],
-                           float* out, int32_t* spans, void* stream);
+                           uint32_t flags, float* out, int32_t* spans, void* stream);
 
 /* ------------------------------------------------------------------ render */
 
@@ -351,6 +361,9 @@ typedef struct {
   int32_t max_batch_items;    /* work items per batch (0 = 8192)                  */
   uint32_t flags;             /* 0 or MFA_SERVER_FAKE_EXECUTOR                    */
   double fake_item_us;        /* modelled time per item with the fake executor    */
+  int32_t fake_fail_batch;    /* fake executor only: the batch with this launch
+                                 number (1-based) fails as a device error would;
+                                 0 = none (host tests of the failure path)       */
 } mfa_server_config;
 
 enum { MFA_REQ_RENDER = 0, MFA_REQ_POINTS = 1 };
@@ -374,7 +387,13 @@ typedef struct {
 
 /* Host times in seconds since the server was created: submit, admission
  * (memory granted), launch of its first batch, completion noticed by the
- * scheduler.  status is MFA_OK or MFA_E_DEVICE; done is 0 or 1.           */
+ * scheduler.  status is MFA_OK or MFA_E_DEVICE; done is 0 or 1.
+ * A failure is per batch: a batch whose launch fails or whose completion
+ * event reports an error fails every request with items in it (status
+ * MFA_E_DEVICE once the request is done); such a request still releases its
+ * budget, and later batches run as usual (after a fault that leaves the
+ * device unusable they fail in turn, each with its own status).  Launches
+ * run outside the lock that submit, poll and wait take.                    */
 typedef struct {
   double t_submit, t_admit, t_start, t_done;
   int32_t status;

@@ -136,41 +136,45 @@ class Model:
 
 
 def decode_points(model: Model, xyz, out=None, dbg: bool = False, sorted_order: bool = False,
-                  stream=None):
+                  value_only: bool = False, stream=None):
     """Value and world gradient at points xyz (CUDA float32, shape (3, n)).
 
-    Returns out (n, 4) float32 = (f, df/dx, df/dy, df/dz) and, if dbg, an
-    int32 (n, 4) tensor of (span0, span1, span2, block).
+    Returns out (n, 4) float32 = (f, df/dx, df/dy, df/dz), or with
+    value_only (n,) float32 = f, and, if dbg, an int32 (n, 4) tensor of
+    (span0, span1, span2, block).
     """
     torch = _torch()
     if xyz.dim() != 2 or xyz.shape[0] != 3:
         raise ValueError("xyz must have shape (3, n)")
     n = int(xyz.shape[1])
     px = _dev_ptr(xyz, torch.float32, name="xyz")
+    shape = (n,) if value_only else (n, 4)
     if out is None:
-        out = torch.empty((n, 4), dtype=torch.float32, device=xyz.device)
-    po = _dev_ptr(out, torch.float32, (n, 4), "out")
+        out = torch.empty(shape, dtype=torch.float32, device=xyz.device)
+    po = _dev_ptr(out, torch.float32, shape, "out")
     d = None
     pd = C.c_void_p()
     if dbg:
         d = torch.empty((n, 4), dtype=torch.int32, device=xyz.device)
         pd = C.c_void_p(d.data_ptr())
-    flags = L.MFA_DECODE_SORTED if sorted_order else 0
+    flags = (L.MFA_DECODE_SORTED if sorted_order else 0) | (L.MFA_DECODE_VALUE if value_only else 0)
     L.check(L.lib().mfa_decode_points(model.handle, px, n, flags, po, pd, _stream_ptr(stream)))
     return (out, d) if dbg else out
 
 
-def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False, stream=None):
+def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False,
+                value_only: bool = False, stream=None):
     """Value and world gradient on the tensor grid of three CUDA float64
-    parameter tables.  Returns out (r0, r1, r2, 4) and, if spans, an int32
-    tensor of the r0 + r1 + r2 per-entry spans."""
+    parameter tables.  Returns out (r0, r1, r2, 4), or with value_only
+    (r0, r1, r2) = f, and, if spans, an int32 tensor of the r0 + r1 + r2
+    per-entry spans."""
     torch = _torch()
     if len(axis_u) != 3:
         raise ValueError("need three axis tables")
     res = (C.c_int32 * 3)(*[int(t.numel()) for t in axis_u])
     ptrs = (C.c_void_p * 3)(*[_dev_ptr(t, torch.float64, name=f"axis_u[{a}]").value
                               for a, t in enumerate(axis_u)])
-    shape = (res[0], res[1], res[2], 4)
+    shape = (res[0], res[1], res[2]) if value_only else (res[0], res[1], res[2], 4)
     dev = axis_u[0].device
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=dev)
@@ -180,7 +184,8 @@ def decode_grid(model: Model, axis_u: Sequence, out=None, spans: bool = False, s
     if spans:
         sp = torch.empty((res[0] + res[1] + res[2],), dtype=torch.int32, device=dev)
         ps = C.c_void_p(sp.data_ptr())
-    L.check(L.lib().mfa_decode_grid(model.handle, ptrs, res, po, ps, _stream_ptr(stream)))
+    flags = L.MFA_DECODE_VALUE if value_only else 0
+    L.check(L.lib().mfa_decode_grid(model.handle, ptrs, res, flags, po, ps, _stream_ptr(stream)))
     return (out, sp) if spans else out
 
 
@@ -527,16 +532,18 @@ class Server:
     """Request loop over resident models (mfa_server_*).
 
     fake_item_us switches to the host-only fake executor (no device work;
-    each batch takes fake_item_us per work item)."""
+    each batch takes fake_item_us per work item); with it, fake_fail_batch
+    = k makes the k-th batch fail as a device error would."""
 
     def __init__(self, hbm_budget_bytes: int, queue_cap: int = 1024, max_batch_items: int = 0,
-                 fake_item_us: Optional[float] = None):
+                 fake_item_us: Optional[float] = None, fake_fail_batch: int = 0):
         cfg = L.ServerConfig()
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.queue_cap = int(queue_cap)
         cfg.max_batch_items = int(max_batch_items)
         cfg.flags = L.MFA_SERVER_FAKE_EXECUTOR if fake_item_us is not None else 0
         cfg.fake_item_us = float(fake_item_us or 0.0)
+        cfg.fake_fail_batch = int(fake_fail_batch)
         h = C.c_void_p()
         L.check(L.lib().mfa_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

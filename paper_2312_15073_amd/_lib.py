@@ -12,6 +12,7 @@ MFA_E_BUDGET, MFA_E_BUSY, MFA_E_NOTFOUND, MFA_E_UNSUPPORTED = -4, -5, -6, -7
 MFA_F64, MFA_F32, MFA_BF16, MFA_F16 = 0, 1, 2, 3
 MFA_ORTHO, MFA_PERSPECTIVE = 0, 1
 MFA_DECODE_SORTED = 1
+MFA_DECODE_VALUE = 2
 
 STATUS_NAMES = {0: "MFA_OK", -1: "MFA_E_ARG", -2: "MFA_E_NOMEM", -3: "MFA_E_DEVICE",
                 -4: "MFA_E_BUDGET", -5: "MFA_E_BUSY", -6: "MFA_E_NOTFOUND",
@@ -65,7 +66,8 @@ FILTER_TRILINEAR, FILTER_CATMULL_ROM, FILTER_CUBIC_BSPLINE, FIELD_MARSCHNER_LOBB
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("queue_cap", C.c_int32),
-                ("max_batch_items", C.c_int32), ("flags", C.c_uint32), ("fake_item_us", C.c_double)]
+                ("max_batch_items", C.c_int32), ("flags", C.c_uint32), ("fake_item_us", C.c_double),
+                ("fake_fail_batch", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -92,7 +94,7 @@ SIGNATURES = {
     "mfa_decode_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
     "mfa_decode_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
-                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+                                  C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mfa_render_frame": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),
                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(RenderDebug),
                                    C.c_void_p]),

@@ -13,6 +13,8 @@
 // cores (v_mfma_f64_16x16x4f64).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -350,6 +352,8 @@ struct ZinvArgs {
   const double* L[3];
   double* Z[3];
   int32_t n[3], p[3];
+  int32_t l_lds;   // the factor is staged in LDS (else read from global memory)
+  int32_t y_lds;   // the y rows live in LDS (else in the output row of Z itself)
 };
 
 constexpr int kZinvThreads = 16;      // columns per workgroup (their y rows share the LDS)
@@ -403,18 +407,23 @@ __device__ __forceinline__ void zinv_row(const double* L, double* y, double* __r
 }
 
 // dynamic LDS: the axis' factor (n (p + 1) values), then one y row of n
-// values per thread
+// values per thread, as far as the device's LDS holds them.  Without room
+// for the y rows, y is kept in the thread's own output row of Z (the
+// backward solve reads y_j before it overwrites it with z_j); without room
+// for the factor either, the factor is read from global memory.
 __global__ __launch_bounds__(kZinvThreads) void zinv_k(ZinvArgs za) {
   extern __shared__ double zsh[];
   const int a = blockIdx.y, c = blockIdx.x * kZinvThreads + threadIdx.x;
   const int n = za.n[a], p = za.p[a];
   if (blockIdx.x * kZinvThreads >= n) return;                  // whole workgroup
-  for (int q = threadIdx.x; q < n * (p + 1); q += kZinvThreads) zsh[q] = za.L[a][q];
-  __syncthreads();
+  if (za.l_lds) {
+    for (int q = threadIdx.x; q < n * (p + 1); q += kZinvThreads) zsh[q] = za.L[a][q];
+    __syncthreads();
+  }
   if (c >= n) return;
-  const double* L = zsh;
-  double* y = zsh + n * (p + 1) + threadIdx.x * n;
+  const double* L = za.l_lds ? zsh : za.L[a];
   double* z = za.Z[a] + (int64_t)c * n;
+  double* y = za.y_lds ? zsh + n * (p + 1) + threadIdx.x * n : z;
   switch (p) {
     case 1: zinv_row<1>(L, y, z, n, c); break;
     case 2: zinv_row<2>(L, y, z, n, c); break;
@@ -928,6 +937,25 @@ AdaptLayout adapt_layout(const int32_t res[3], const int32_t nm[3]) {
   return L;
 }
 
+// Dynamic LDS a workgroup may take on the current device (read once per
+// device).
+hipError_t device_lds_limit(size_t* bytes) {
+  static std::atomic<int> limit[64];     // zero: not read yet
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  int v = limit[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if (v <= 0) return hipErrorInvalidValue;
+    limit[dev].store(v, std::memory_order_relaxed);
+  }
+  *bytes = (size_t)v;
+  return hipSuccess;
+}
+
 mfa_status check_adaptive(const int32_t res[3], const int32_t degree[3], const int32_t n_init[3],
                           const int32_t max_ctrl[3]) {
   if (!res || !degree || !n_init || !max_ctrl) return fail(MFA_E_ARG, "null res / degree / n_init / max_ctrl");
@@ -986,6 +1014,12 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
   hipStream_t hs = (hipStream_t)stream;
   uint8_t* wb = static_cast<uint8_t*>(work);
   auto at = [&](size_t off) { return reinterpret_cast<double*>(wb + off); };
+  // an error return after an upload from host vectors of this call waits
+  // for the stream first, so no copy still reads from a destroyed vector
+  auto bail = [&](mfa_status st) {
+    (void)hipStreamSynchronize(hs);
+    return st;
+  };
   const int64_t N[3] = {res[0], res[1], res[2]};
   const int64_t rows = N[0] * N[1];
   const int64_t tm = (rows + kGemmTile - 1) / kGemmTile, tn = (N[2] + 16 * kErrNT - 1) / (16 * kErrNT);
@@ -1005,7 +1039,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     hipLaunchKernelGGL(range_k, dim3(1), dim3(256), 0, hs, mm, kMinMaxBlocks, at(lay.inv));
     e = hipGetLastError();
   }
-  if (e != hipSuccess) return hip_fail(e, "encode: data range");
+  if (e != hipSuccess) return bail(hip_fail(e, "encode: data range"));
   // initial knots: clamped uniform with n_init control points
   std::vector<double> T[3];
   for (int a = 0; a < 3; ++a) {
@@ -1025,10 +1059,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     for (int a = 0; a < 3; ++a) {
       const mfa_status sa = gram_factor(T[a].data(), degree[a], (int)n[a], axis_u[a], res[a], a, Lg[a],
                                         spans[a], Bv[a]);
-      if (sa != MFA_OK) {
-        (void)hipStreamSynchronize(hs);        // the parameter upload has its source in hu
-        return sa;
-      }
+      if (sa != MFA_OK) return bail(sa);    // the parameter upload has its source in hu
     }
     // knots and Gram factors in one copy (the previous pass ended with a
     // synchronisation, so stage is free to reuse)
@@ -1046,7 +1077,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
       for (int64_t j = 0; j < n[a]; ++j) stage[o + j * (degree[a] + 1)] = 1.0 / stage[o + j * (degree[a] + 1)];
     }
     e = hipMemcpyAsync(at(lay.stage), stage.data(), stage.size() * 8, hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(e, "encode: table upload");
+    if (e != hipSuccess) return bail(hip_fail(e, "encode: table upload"));
     int maxN = 0, maxn = 0;
     int64_t zo = 0;
     for (int a = 0; a < 3; ++a) {
@@ -1064,16 +1095,26 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
       ta.p[a] = degree[a];
       maxN = std::max(maxN, res[a]);
     }
-    int maxw = 0;
-    for (int a = 0; a < 3; ++a) maxw = std::max(maxw, (int)n[a] * (degree[a] + 1) + kZinvThreads * (int)n[a]);
+    // LDS of the inversion: factor and y rows, else the factor alone, else none
+    size_t lds_l = 0, lds_y = 0;
+    for (int a = 0; a < 3; ++a) {
+      lds_l = std::max(lds_l, (size_t)n[a] * (degree[a] + 1) * 8);
+      lds_y = std::max(lds_y, (size_t)n[a] * (degree[a] + 1 + kZinvThreads) * 8);
+    }
+    size_t lds_limit = 0;
+    e = device_lds_limit(&lds_limit);
+    if (e != hipSuccess) return bail(hip_fail(e, "encode: device LDS size"));
+    za.y_lds = lds_y <= lds_limit;
+    za.l_lds = lds_l <= lds_limit;
+    const size_t lds = za.y_lds ? lds_y : (za.l_lds ? lds_l : 0);
     hipLaunchKernelGGL(zinv_k, dim3((unsigned)((maxn + kZinvThreads - 1) / kZinvThreads), 3),
-                       dim3(kZinvThreads), (size_t)maxw * 8, hs, za);
+                       dim3(kZinvThreads), lds, hs, za);
     e = hipGetLastError();
     if (e == hipSuccess) {
       hipLaunchKernelGGL(tables_k, dim3((unsigned)((maxN + 3) / 4), 3), dim3(256), 0, hs, ta);
       e = hipGetLastError();
     }
-    if (e != hipSuccess) return hip_fail(e, "encode: tables");
+    if (e != hipSuccess) return bail(hip_fail(e, "encode: tables"));
     const double* qt[3] = {at(lay.qt[0]), at(lay.qt[1]), at(lay.qt[2])};
     const double* bt[3] = {at(lay.bt[0]), at(lay.bt[1]), at(lay.bt[2])};
     e = run_fit(N, n, values, ctrl, qt, at(lay.y0), at(lay.y1), hs, at(lay.part), lay.part_cap);
@@ -1092,7 +1133,7 @@ extern "C" mfa_status mfa_encode_adaptive(const int32_t res[3], const double* co
     if (e == hipSuccess)
       e = hipMemcpyAsync(marg.data(), dmarg, marg.size() * 8, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
-    if (e != hipSuccess) return hip_fail(e, "encode: adaptive fit");
+    if (e != hipSuccess) return bail(hip_fail(e, "encode: adaptive fit"));
     // largest error per sample index of each axis
     const double* m[3] = {marg.data(), marg.data() + N[0], marg.data() + N[0] + N[1]};
     double emax = 0.0;

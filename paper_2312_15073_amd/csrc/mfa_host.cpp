@@ -17,11 +17,12 @@
 #include "mfa_model.h"
 
 namespace mfa {
-hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, const float* xyz,
-                                int64_t n, float* out, int32_t* dbg, hipStream_t st);
-hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, bool grad,
+                                const float* xyz, int64_t n, float* out, int32_t* dbg,
+                                hipStream_t st);
+hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, bool grad, const GridArgs& ga,
                               hipStream_t st);
-hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind,
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind, bool grad,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st);
 hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                          hipStream_t st);
@@ -201,6 +202,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 
 static void free_model(mfa_model m) {
   if (!m) return;
+  if (m->ws_done) (void)hipEventDestroy(m->ws_done);
   void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -713,70 +715,124 @@ Storage storage_of(mfa_model m) {
   return m->storage == MFA_F32 ? Storage::F32 : m->storage == MFA_BF16 ? Storage::BF16 : Storage::F16;
 }
 
-extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n, uint32_t flags,
-                                        float* out, int32_t* dbg, void* stream) {
+// Arguments shared by the point decodes.
+static mfa_status check_points(mfa_model m, const float* xyz, int64_t n, uint32_t flags,
+                               const float* out) {
   if (!m) return fail(MFA_E_ARG, "null model");
   if (n < 0 || n >= (1ll << 31)) return fail(MFA_E_ARG, "n = %lld out of range", (long long)n);
-  if (flags & ~MFA_DECODE_SORTED) return fail(MFA_E_ARG, "unknown flags 0x%x", flags);
-  if (n == 0) return MFA_OK;
-  if (!xyz || !out) return fail(MFA_E_ARG, "null xyz/out");
-  mfa_status st = check_device(m);
+  if (flags & ~(MFA_DECODE_SORTED | MFA_DECODE_VALUE)) return fail(MFA_E_ARG, "unknown flags 0x%x", flags);
+  if (n > 0 && (!xyz || !out)) return fail(MFA_E_ARG, "null xyz/out");
+  return MFA_OK;
+}
+
+// Scratch of a sorted decode of n points over nb buckets, one region after
+// another (256-byte aligned): one 16-byte record per point, counts, starts
+// and cursors per bucket, the decode items and their count, and with the
+// two-level split the coarse cursors and a second record per point.
+struct SortLayout {
+  size_t o_hist, o_start, o_cur, o_items, o_nitems, o_ccur, o_tmp, bytes;
+  bool two;
+};
+
+static SortLayout sort_layout(int64_t n, int64_t nb) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  SortLayout L{};
+  const size_t nbk = (size_t)nb;
+  const size_t n_items = (size_t)((n + kTilePoints - 1) / kTilePoints) + nbk;
+  L.o_hist = al(16 * (size_t)n);
+  L.o_start = L.o_hist + al(4 * nbk);
+  L.o_cur = L.o_start + al(4 * nbk);
+  L.o_items = L.o_cur + al(4 * nbk);
+  L.o_nitems = L.o_items + al(8 * n_items);
+  L.o_ccur = L.o_nitems + al(4);
+  L.two = nbk > (size_t)kCoarseBuckets;
+  L.o_tmp = L.o_ccur + al(4 * kCoarseBuckets * kCursorStride);
+  L.bytes = L.two ? L.o_tmp + al(16 * (size_t)n) : L.o_ccur;
+  return L;
+}
+
+// Sorts and decodes with the scratch at w (device, >= sort_layout().bytes).
+static mfa_status sorted_decode(mfa_model m, uint8_t* w, const SortLayout& L, const float* xyz,
+                                int64_t n, bool grad, float* out, int32_t* dbg, void* stream) {
+  SortArgs sa{};
+  sa.xyz = xyz;
+  sa.n = n;
+  sa.rec = (float4*)w;
+  sa.hist = (uint32_t*)(w + L.o_hist);
+  sa.start = (uint32_t*)(w + L.o_start);
+  sa.cursor = (uint32_t*)(w + L.o_cur);
+  sa.items = (int2*)(w + L.o_items);
+  sa.n_items = (int32_t*)(w + L.o_nitems);
+  sa.nb = (int32_t)m->n_buckets;
+  sa.tmp = L.two ? (float4*)(w + L.o_tmp) : nullptr;
+  sa.ccursor = L.two ? (uint32_t*)(w + L.o_ccur) : nullptr;
+  hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), grad, sa, out,
+                                      dbg, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "sorted decode launch");
+  return MFA_OK;
+}
+
+extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n, uint32_t flags,
+                                        float* out, int32_t* dbg, void* stream) {
+  mfa_status st = check_points(m, xyz, n, flags, out);
+  if (st != MFA_OK || n == 0) return st;
+  st = check_device(m);
   if (st != MFA_OK) return st;
+  const bool grad = !(flags & MFA_DECODE_VALUE);
   if (flags & MFA_DECODE_SORTED) {
-    // scratch: one 16-byte sorted record per point (two with the two-level
-    // split); counts, starts and cursors per bucket; the decode items
     if (m->n_buckets > kMaxBuckets)
       return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
-    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t nbk = (size_t)m->n_buckets;
-    const size_t o_rec = 0;
-    const size_t o_hist = o_rec + al(16 * (size_t)n), o_start = o_hist + al(4 * nbk);
-    const size_t o_cur = o_start + al(4 * nbk);
-    const size_t n_items = (size_t)((n + kTilePoints - 1) / kTilePoints) + nbk;
-    const size_t o_items = o_cur + al(4 * nbk), o_nitems = o_items + al(8 * n_items);
-    const bool two = nbk > (size_t)kCoarseBuckets;
-    const size_t o_ccur = o_nitems + al(4), o_tmp = o_ccur + al(4 * kCoarseBuckets * kCursorStride);
-    const size_t need = two ? o_tmp + al(16 * (size_t)n) : o_ccur;
-    if (need > m->ws_bytes) {
+    const SortLayout L = sort_layout(n, m->n_buckets);
+    // The scratch is the model's: a sorted call waits for the previous
+    // sorted call's kernels (an event recorded after them) before it reuses
+    // or replaces the buffer, so calls on different streams are ordered
+    // rather than racing.
+    std::lock_guard<std::mutex> guard(m->ws_mu);
+    hipError_t e;
+    if (!m->ws_done) {
+      e = hipEventCreateWithFlags(&m->ws_done, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "scratch event");
+    }
+    if (L.bytes > m->ws_bytes) {
       if (m->d_ws) {
-        hipError_t fe = hipFree(m->d_ws);   // waits for work still using it
+        e = hipEventSynchronize(m->ws_done);     // the previous sorted call's kernels
+        if (e != hipSuccess) return hip_fail(e, "scratch wait");
+        e = hipFree(m->d_ws);
         m->d_ws = nullptr;
         m->device_bytes -= (int64_t)m->ws_bytes;
         m->ws_bytes = 0;
-        if (fe != hipSuccess) return hip_fail(fe, "scratch free");
+        if (e != hipSuccess) return hip_fail(e, "scratch free");
       }
-      hipError_t ae = hipMalloc(&m->d_ws, need);
-      if (ae != hipSuccess) return hip_fail(ae, "scratch for sorted decode");
-      m->ws_bytes = need;
-      m->device_bytes += (int64_t)need;
+      e = hipMalloc(&m->d_ws, L.bytes);
+      if (e != hipSuccess) {
+        m->d_ws = nullptr;
+        return fail(MFA_E_NOMEM, "scratch for sorted decode (%zu bytes): %s", L.bytes,
+                    hipGetErrorString(e));
+      }
+      m->ws_bytes = L.bytes;
+      m->device_bytes += (int64_t)L.bytes;
+    } else if (m->ws_used && (hipStream_t)stream != m->ws_stream) {
+      e = hipStreamWaitEvent((hipStream_t)stream, m->ws_done, 0);
+      if (e != hipSuccess) return hip_fail(e, "scratch stream wait");
     }
-    uint8_t* w = (uint8_t*)m->d_ws;
-    SortArgs sa{};
-    sa.xyz = xyz;
-    sa.n = n;
-    sa.rec = (float4*)(w + o_rec);
-    sa.hist = (uint32_t*)(w + o_hist);
-    sa.start = (uint32_t*)(w + o_start);
-    sa.cursor = (uint32_t*)(w + o_cur);
-    sa.items = (int2*)(w + o_items);
-    sa.n_items = (int32_t*)(w + o_nitems);
-    sa.nb = (int32_t)nbk;
-    sa.tmp = two ? (float4*)(w + o_tmp) : nullptr;
-    sa.ccursor = two ? (uint32_t*)(w + o_ccur) : nullptr;
-    hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), sa, out, dbg,
-                                        (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "sorted decode launch");
+    st = sorted_decode(m, (uint8_t*)m->d_ws, L, xyz, n, grad, out, dbg, stream);
+    if (st != MFA_OK) return st;
+    e = hipEventRecord(m->ws_done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "scratch event record");
+    m->ws_stream = (hipStream_t)stream;
+    m->ws_used = true;
     return MFA_OK;
   }
-  hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), kernel_kind(m), xyz, n, out,
-                                      dbg, (hipStream_t)stream);
+  hipError_t e = launch_decode_points(m->dm, m->degree, storage_of(m), kernel_kind(m), grad, xyz, n,
+                                      out, dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_points launch");
   return MFA_OK;
 }
 
 extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3], const int32_t res[3],
-                                      float* out, int32_t* spans, void* stream) {
+                                      uint32_t flags, float* out, int32_t* spans, void* stream) {
   if (!m || !axis_u || !res || !out) return fail(MFA_E_ARG, "null argument");
+  if (flags & ~MFA_DECODE_VALUE) return fail(MFA_E_ARG, "unknown flags 0x%x", flags);
   if (m->nblocks != 1) return fail(MFA_E_ARG, "grid decode needs a single-block model");
   int64_t total = 1;
   for (int a = 0; a < 3; ++a) {
@@ -795,7 +851,8 @@ extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3]
   }
   ga.out = out;
   ga.spans = spans;
-  hipError_t e = launch_decode_grid(m->dm, m->degree, storage_of(m), ga, (hipStream_t)stream);
+  hipError_t e = launch_decode_grid(m->dm, m->degree, storage_of(m), !(flags & MFA_DECODE_VALUE), ga,
+                                    (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_grid launch");
   return MFA_OK;
 }

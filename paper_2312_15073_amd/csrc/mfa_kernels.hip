@@ -465,7 +465,18 @@ __device__ __forceinline__ float4 evaluate(const Loc& L, __amdgpu_buffer_rsrc_t 
 }
 
 // ------------------------------------------------------------------ K1: points
-template <int P, Storage S, bool MULTI, bool GT = false>
+// Result of point i: (f, df/dx, df/dy, df/dz) as a float4 at out[4 i], or
+// (G = false, value-only queries) f alone at out[i]; the gradient terms of
+// the contraction and the derivative basis are then dead code.
+template <bool G>
+__device__ __forceinline__ void put_result(float* __restrict__ out, int64_t i, const float4& e) {
+  if constexpr (G)
+    reinterpret_cast<float4*>(out)[i] = e;
+  else
+    out[i] = e.x;
+}
+
+template <int P, Storage S, bool MULTI, bool GT = false, bool G = true>
 __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const float* __restrict__ xyz,
                                                           int64_t n, float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -474,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void decode_points_k(DevModel m, const floa
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const double x[3] = {(double)xyz[i], (double)xyz[n + i], (double)xyz[2 * n + i]};
   const Loc L = locate<P, MULTI, GT>(m, m.rec, x);
-  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
+  put_result<G>(out, i, evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat));
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
 
@@ -725,7 +736,7 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
 // for non-uniform knots) reads its rows from global memory.  Both paths sum
 // in the same order.  LDSREC: the span records and basis tables of a
 // single-block model are staged too, ahead of the window.
-template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false>
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false, bool G = true>
 __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
                                                          float* __restrict__ out,
                                                          int32_t* __restrict__ dbg) {
@@ -817,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
                             m.mat_stride, m.imat);
     else
       res = evaluate<P, S, !MULTI>(L, rs, MT, m.mat_stride, m.imat);
-    reinterpret_cast<float4*>(out)[i] = res;
+    put_result<G>(out, i, res);
     if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
   }
 }
@@ -825,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
 // Sorted decode for models whose bucket windows exceed the LDS budget: one
 // point per thread over the sorted records (workgroup ranges dealt to XCDs
 // in contiguous bands), rows from global memory.
-template <int P, Storage S, bool MULTI, bool GT = false>
+template <int P, Storage S, bool MULTI, bool GT = false, bool G = true>
 __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs sa,
                                                           float* __restrict__ out,
                                                           int32_t* __restrict__ dbg) {
@@ -838,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void decode_sorted_k(DevModel m, SortArgs s
   const Loc L = locate<P, MULTI, GT>(m, m.rec, x);
   const uint32_t i = __float_as_uint(q.w);
   if ((int64_t)i >= sa.n) return;
-  reinterpret_cast<float4*>(out)[i] = evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat);
+  put_result<G>(out, i, evaluate<P, S, !MULTI>(L, rs, m.mats, m.mat_stride, m.imat));
   if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
 }
 
@@ -870,7 +881,7 @@ __device__ __forceinline__ void axis_basis(const DevModel& m, int a, double uraw
   ds = rec.dscale;
 }
 
-template <int P, Storage S>
+template <int P, Storage S, bool G = true>
 __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga) {
   __shared__ ABasis<P> sa[kGridTA];
   const int lane = threadIdx.x & (kWave - 1);
@@ -928,7 +939,6 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
   float Y[P + 1], YY[P + 1], YZ[P + 1];
   int wj = -(1 << 30);
   const int64_t plane = (int64_t)ga.res[1] * ga.res[2];
-  float4* out = reinterpret_cast<float4*>(ga.out);
   for (int t = 0; t < na; ++t) {
     const int ja = __builtin_amdgcn_readfirstlane(sa[t].j);
     if (ja != wj) {
@@ -951,9 +961,14 @@ __global__ __launch_bounds__(kBlock) void decode_grid_k(DevModel m, GridArgs ga)
       fy = fmaf(nx, YY[r], fy);
       fz = fmaf(nx, YZ[r], fz);
     }
-    if (cvalid)     // whole lines, written once: streaming store
-      store_stream(&out[(int64_t)(a0 + t) * plane + (int64_t)b * ga.res[2] + c],
-                   make_float4(f, fx * sa[t].ds, fy * dsy, fz * dsz));
+    // whole lines, written once: streaming stores
+    const int64_t o = (int64_t)(a0 + t) * plane + (int64_t)b * ga.res[2] + c;
+    if (cvalid) {
+      if constexpr (G)
+        store_stream(reinterpret_cast<float4*>(ga.out) + o, make_float4(f, fx * sa[t].ds, fy * dsy, fz * dsz));
+      else
+        __builtin_nontemporal_store(f, ga.out + o);
+    }
   }
 }
 
@@ -1871,19 +1886,28 @@ static bool lds_fits(size_t dyn) {
   return dyn + kStaticLdsBytes <= (size_t)v;
 }
 
-template <int P, Storage S>
-static hipError_t points_p(const DevModel& m, int kind, const float* xyz, int64_t n, float* out,
-                           int32_t* dbg, hipStream_t st) {
+template <int P, Storage S, bool G>
+static void points_g(const DevModel& m, int kind, const float* xyz, int64_t n, float* out,
+                     int32_t* dbg, hipStream_t st) {
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
   if (kind == kKindMulti)
-    hipLaunchKernelGGL((decode_points_k<P, S, true>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
-                       out, dbg);
+    hipLaunchKernelGGL((decode_points_k<P, S, true, false, G>), dim3(grid), dim3(kBlock), 0, st, m,
+                       xyz, n, out, dbg);
   else if (kind == kKindGraded)
-    hipLaunchKernelGGL((decode_points_k<P, S, false, true>), dim3(grid), dim3(kBlock), 0, st, m, xyz,
-                       n, out, dbg);
+    hipLaunchKernelGGL((decode_points_k<P, S, false, true, G>), dim3(grid), dim3(kBlock), 0, st, m,
+                       xyz, n, out, dbg);
   else
-    hipLaunchKernelGGL((decode_points_k<P, S, false>), dim3(grid), dim3(kBlock), 0, st, m, xyz, n,
-                       out, dbg);
+    hipLaunchKernelGGL((decode_points_k<P, S, false, false, G>), dim3(grid), dim3(kBlock), 0, st, m,
+                       xyz, n, out, dbg);
+}
+
+template <int P, Storage S>
+static hipError_t points_p(const DevModel& m, int kind, bool grad, const float* xyz, int64_t n,
+                           float* out, int32_t* dbg, hipStream_t st) {
+  if (grad)
+    points_g<P, S, true>(m, kind, xyz, n, out, dbg, st);
+  else
+    points_g<P, S, false>(m, kind, xyz, n, out, dbg, st);
   return hipGetLastError();
 }
 
@@ -1904,8 +1928,41 @@ static void sort_launch(const DevModel& m, const SortArgs& sa, unsigned gc, hipS
   }
 }
 
+template <int P, Storage S, bool G>
+static void decode_sorted_g(const DevModel& m, int kind, const SortArgs& sa, float* out,
+                            int32_t* dbg, hipStream_t st) {
+  if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
+    const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
+    if (kind != kKindPlain)
+      hipLaunchKernelGGL((decode_sorted_k<P, S, true, false, G>), dim3(g), dim3(kBlock), 0, st, m, sa,
+                         out, dbg);
+    else
+      hipLaunchKernelGGL((decode_sorted_k<P, S, false, false, G>), dim3(g), dim3(kBlock), 0, st, m, sa,
+                         out, dbg);
+    return;
+  }
+  // items: at most ceil(n / kTilePoints) + nb; the surplus workgroups exit
+  const unsigned gi = (unsigned)((sa.n + kTilePoints - 1) / kTilePoints + sa.nb);
+  const int cap = m.win_max;
+  const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
+  const size_t wb = (size_t)cap * 4;
+  const bool lds_tabs = tabs <= (size_t)kLdsRecBytes && lds_fits(tabs + wb);
+  if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
+    hipLaunchKernelGGL((decode_tiles_k<P, S, true, false, false, G>), dim3(gi), dim3(kBlock), wb, st, m,
+                       sa, cap, out, dbg);
+  else if (kind == kKindGraded)
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true, true, G>), dim3(gi), dim3(kBlock), tabs + wb,
+                       st, m, sa, cap, out, dbg);
+  else if (lds_tabs)
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true, false, G>), dim3(gi), dim3(kBlock), tabs + wb,
+                       st, m, sa, cap, out, dbg);
+  else
+    hipLaunchKernelGGL((decode_tiles_k<P, S, false, false, false, G>), dim3(gi), dim3(kBlock), wb, st, m,
+                       sa, cap, out, dbg);
+}
+
 template <int P, Storage S>
-static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, float* out,
+static hipError_t sorted_p(const DevModel& m, int kind, bool grad, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
   const bool multi = kind == kKindMulti;
   const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
@@ -1917,33 +1974,10 @@ static hipError_t sorted_p(const DevModel& m, int kind, const SortArgs& sa, floa
     sort_launch<false, true>(m, sa, gc, st);
   else
     sort_launch<false, false>(m, sa, gc, st);
-  if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
-    const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
-    if (kind != kKindPlain)
-      hipLaunchKernelGGL((decode_sorted_k<P, S, true>), dim3(g), dim3(kBlock), 0, st, m, sa, out, dbg);
-    else
-      hipLaunchKernelGGL((decode_sorted_k<P, S, false>), dim3(g), dim3(kBlock), 0, st, m, sa, out,
-                         dbg);
-    return hipGetLastError();
-  }
-  // items: at most ceil(n / kTilePoints) + nb; the surplus workgroups exit
-  const unsigned gi = (unsigned)((sa.n + kTilePoints - 1) / kTilePoints + sa.nb);
-  const int cap = m.win_max;
-  const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
-  const size_t wb = (size_t)cap * 4;
-  const bool lds_tabs = tabs <= (size_t)kLdsRecBytes && lds_fits(tabs + wb);
-  if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
-    hipLaunchKernelGGL((decode_tiles_k<P, S, true, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
-                       cap, out, dbg);
-  else if (kind == kKindGraded)
-    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true, true>), dim3(gi), dim3(kBlock), tabs + wb,
-                       st, m, sa, cap, out, dbg);
-  else if (lds_tabs)
-    hipLaunchKernelGGL((decode_tiles_k<P, S, false, true>), dim3(gi), dim3(kBlock), tabs + wb, st,
-                       m, sa, cap, out, dbg);
+  if (grad)
+    decode_sorted_g<P, S, true>(m, kind, sa, out, dbg, st);
   else
-    hipLaunchKernelGGL((decode_tiles_k<P, S, false, false>), dim3(gi), dim3(kBlock), wb, st, m, sa,
-                       cap, out, dbg);
+    decode_sorted_g<P, S, false>(m, kind, sa, out, dbg, st);
   return hipGetLastError();
 }
 
@@ -1960,10 +1994,13 @@ static hipError_t serve_p(bool multi, const DevModel* models, const ServeReq* re
 }
 
 template <int P, Storage S>
-static hipError_t grid_p(const DevModel& m, GridArgs ga, hipStream_t st) {
+static hipError_t grid_p(const DevModel& m, bool grad, GridArgs ga, hipStream_t st) {
   ga.ta = kGridTA;
   dim3 grid((ga.res[2] + kWave - 1) / kWave, (ga.res[1] + 3) / 4, (ga.res[0] + kGridTA - 1) / kGridTA);
-  hipLaunchKernelGGL((decode_grid_k<P, S>), grid, dim3(kBlock), 0, st, m, ga);
+  if (grad)
+    hipLaunchKernelGGL((decode_grid_k<P, S, true>), grid, dim3(kBlock), 0, st, m, ga);
+  else
+    hipLaunchKernelGGL((decode_grid_k<P, S, false>), grid, dim3(kBlock), 0, st, m, ga);
   return hipGetLastError();
 }
 
@@ -2038,14 +2075,15 @@ static hipError_t iso_p(const DevModel& m, int kind, const RenderArgs& r, hipStr
     default: return hipErrorInvalidValue;                                            \
   }
 
-hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, const float* xyz,
-                                int64_t n, float* out, int32_t* dbg, hipStream_t st) {
-  MFA_DISPATCH(points_p, m, kind, xyz, n, out, dbg, st)
+hipError_t launch_decode_points(const DevModel& m, int p, Storage s, int kind, bool grad,
+                                const float* xyz, int64_t n, float* out, int32_t* dbg,
+                                hipStream_t st) {
+  MFA_DISPATCH(points_p, m, kind, grad, xyz, n, out, dbg, st)
 }
 
-hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind,
+hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind, bool grad,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st) {
-  MFA_DISPATCH(sorted_p, m, kind, sa, out, dbg, st)
+  MFA_DISPATCH(sorted_p, m, kind, grad, sa, out, dbg, st)
 }
 
 hipError_t launch_serve(int p, Storage s, bool multi, const DevModel* models, const ServeReq* reqs,
@@ -2053,9 +2091,9 @@ hipError_t launch_serve(int p, Storage s, bool multi, const DevModel* models, co
   MFA_DISPATCH(serve_p, multi, models, reqs, items, n_items, cursor, grid, st)
 }
 
-hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, const GridArgs& ga,
+hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, bool grad, const GridArgs& ga,
                               hipStream_t st) {
-  MFA_DISPATCH(grid_p, m, ga, st)
+  MFA_DISPATCH(grid_p, m, grad, ga, st)
 }
 
 hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "mfa.h"
@@ -38,6 +39,10 @@ struct mfa_model_s {
   int64_t n_buckets = 0;        // sort buckets (block, tile)
   void* d_ws = nullptr;         // scratch of sorted decodes, grown on demand
   size_t ws_bytes = 0;
+  std::mutex ws_mu;             // guards d_ws and the fields below
+  hipEvent_t ws_done = nullptr; // recorded after the last sorted call's kernels
+  hipStream_t ws_stream = nullptr;
+  bool ws_used = false;
   mfa::DevModel dm{};
 };
 

@@ -66,6 +66,8 @@ struct Variant {
 
 struct Batch {
   int slot = 0;
+  int seq = 0;              // launch number, 1-based
+  int status = MFA_OK;      // MFA_E_DEVICE when its launch or its kernels failed
   hipEvent_t ev = nullptr;
   double t_launch = 0, t_end_fake = 0;
   std::vector<std::pair<Req*, int>> parts;   // request, items of it in this batch
@@ -92,7 +94,12 @@ struct mfa_server_s {
   Slot slots[kMaxInFlight];
   bool slot_busy[kMaxInFlight] = {false, false, false};
 
+  // mu guards the queue, the requests and their stats (clients and the
+  // scheduler); launch_mu serialises device-side changes of the model
+  // table against batch launches, which run outside mu so that submit and
+  // poll never wait for a launch.  Order: launch_mu before mu.
   std::mutex mu;
+  std::mutex launch_mu;
   std::condition_variable cv;       // scheduler wake-up
   std::condition_variable cv_done;  // request completions
   std::deque<Req*> queue;           // requests with items not yet batched
@@ -100,8 +107,8 @@ struct mfa_server_s {
   std::deque<Batch> inflight;
   int64_t in_use = 0;
   uint64_t next_ticket = 1;
+  int next_seq = 1;
   bool stop = false;
-  int fault = MFA_OK;
   std::thread th;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double fake_busy_until = 0;
@@ -160,16 +167,18 @@ bool mfa_server_s::form_batch(Batch& b, std::vector<ServeItem>& items, std::vect
   return true;
 }
 
+// Stages and enqueues one batch; runs on the scheduler thread without mu
+// (it touches only the batch, its slot and the model table, under
+// launch_mu).  The fake executor models the batch's duration instead and
+// fails the batch numbered cfg.fake_fail_batch.
 mfa_status mfa_server_s::launch(Batch& b, const std::vector<ServeItem>& items,
                                 const std::vector<ServeReq>& descs,
                                 const std::vector<std::pair<Variant, std::pair<int, int>>>& ranges) {
-  b.t_launch = now();
-  for (auto& pr : b.parts)
-    if (pr.first->t_start < 0) pr.first->t_start = b.t_launch;
   if (fake) {
     const double start = std::max(b.t_launch, fake_busy_until);
     b.t_end_fake = start + 1e-6 * cfg.fake_item_us * (double)items.size();
     fake_busy_until = b.t_end_fake;
+    if (b.seq == cfg.fake_fail_batch) return fail(MFA_E_DEVICE, "injected failure of batch %d", b.seq);
     return MFA_OK;
   }
   Slot& S = slots[b.slot];
@@ -196,14 +205,17 @@ mfa_status mfa_server_s::launch(Batch& b, const std::vector<ServeItem>& items,
   return MFA_OK;
 }
 
+// A failed batch fails every request with items in it (a request spanning
+// batches takes the first failure); each request releases its budget when
+// its last item is retired, failed or not.
 void mfa_server_s::retire(Batch& b, double t) {
   for (auto& pr : b.parts) {
     Req* r = pr.first;
     r->items_left -= pr.second;
+    if (b.status != MFA_OK && r->status == MFA_OK) r->status = b.status;
     if (r->items_left == 0) {
       r->done = true;
       r->t_done = t;
-      r->status = fault;
       in_use -= r->bytes;
     }
   }
@@ -223,8 +235,8 @@ void mfa_server_s::run() {
       if (fake) {
         fin = now() >= it->t_end_fake;
       } else {
-        const hipError_t q = hipEventQuery(it->ev);
-        if (q != hipSuccess && q != hipErrorNotReady) fault = MFA_E_DEVICE;
+        const hipError_t q = it->ev ? hipEventQuery(it->ev) : hipSuccess;
+        if (q != hipSuccess && q != hipErrorNotReady) it->status = MFA_E_DEVICE;
         fin = q != hipErrorNotReady;
       }
       if (fin) {
@@ -246,10 +258,36 @@ void mfa_server_s::run() {
       std::vector<std::pair<Variant, std::pair<int, int>>> ranges;
       if (form_batch(b, items, descs, ranges)) {
         slot_busy[slot] = true;
-        if (!fake) {
-          (void)hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+        b.seq = next_seq++;
+        b.t_launch = now();
+        for (auto& pr : b.parts)
+          if (pr.first->t_start < 0) pr.first->t_start = b.t_launch;
+        // the launch (staging copy, kernels, event) runs without mu
+        lk.unlock();
+        mfa_status st = MFA_OK;
+        {
+          std::lock_guard<std::mutex> lg(launch_mu);
+          if (!fake) {
+            const hipError_t e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+              b.ev = nullptr;
+              st = hip_fail(e, "server batch event");
+            }
+          }
+          if (st == MFA_OK) st = launch(b, items, descs, ranges);
         }
-        if (launch(b, items, descs, ranges) != MFA_OK) fault = MFA_E_DEVICE;
+        lk.lock();
+        if (st != MFA_OK) {
+          // the batch failed before (all of) its work was enqueued: its
+          // event, if recorded at all, is not waited for
+          b.status = MFA_E_DEVICE;
+          // work of it that was enqueued still reads the slot's buffers:
+          // the slot is free again only once its stream has passed it
+          if (!fake) (void)hipStreamSynchronize(slots[b.slot].stream);
+          if (b.ev) (void)hipEventDestroy(b.ev);
+          b.ev = nullptr;
+          b.t_end_fake = now();
+        }
         inflight.push_back(std::move(b));
         continue;
       }
@@ -326,6 +364,7 @@ extern "C" mfa_status mfa_server_add_model(mfa_server s, mfa_model m, int32_t* m
   if (!m && !s->fake) return fail(MFA_E_ARG, "null model");
   if (m && !s->fake && m->device != s->device)
     return fail(MFA_E_ARG, "model on device %d, server on device %d", m->device, s->device);
+  std::lock_guard<std::mutex> lg(s->launch_mu);    // no batch is being launched
   std::lock_guard<std::mutex> g(s->mu);
   if (!s->fake) {
     // grow the device model table; requests in flight keep using the old

@@ -202,3 +202,50 @@ def test_encode_adaptive_long_axes_split_products(mfa, dev):
     announce("adaptive encode 24x161x202 (split products)")
     knots, hist = run_adaptive(mfa, dev, F, x, (3, 3, 3), (5, 6, 7), 1e-3, 3)
     assert len(hist) >= 2
+
+
+def test_encode_adaptive_long_axis_y_rows_outside_lds(mfa, dev):
+    """1300 control points on axis 2 at degree 3: the inversion's y rows
+    (16 x 1300 doubles) exceed the LDS and stay in the output rows; the fit
+    still equals the oracle's."""
+    rng = np.random.default_rng(92)
+    res = (5, 6, 2600)
+    x = [np.linspace(0.0, 1.0, r) for r in res]
+    g = np.meshgrid(*x, indexing="ij")
+    F = (np.sin(40.0 * g[2]) * (1 + g[0]) + 0.5 * g[1] * np.cos(25.0 * g[2])
+         + 0.01 * rng.standard_normal(res)).astype(np.float32)
+    announce("adaptive encode 5x6x2600, 1300 control points on axis 2")
+    knots, hist = run_adaptive(mfa, dev, F, x, (1, 2, 3), (2, 3, 1300), 10.0, 2)
+    assert len(hist) == 1 and hist[0][0] == (2, 3, 1300)
+
+
+def test_encode_adaptive_factor_outside_lds(mfa, dev):
+    """5200 control points on axis 2 at degree 3: the factor alone (5200 x 4
+    doubles) exceeds the LDS and is read from global memory.  The field is
+    constant along axes 0 and 1 (linear there, two control points each), so
+    every row of the fit is the 1-D least-squares fit along axis 2, solved
+    here from the banded normal equations by scipy."""
+    import torch
+    from scipy.linalg import solveh_banded
+    from scipy.interpolate import BSpline
+    res = (3, 3, 10400)
+    x = [np.linspace(0.0, 1.0, r) for r in res]
+    g2 = np.sin(30.0 * x[2]) + 0.3 * np.cos(170.0 * x[2] ** 2)
+    F = np.broadcast_to(g2, res).astype(np.float32).copy()
+    n, p = 5200, 3
+    announce("adaptive encode 3x3x10400, 5200 control points on axis 2")
+    knots, P, hist = mfa.encode_adaptive(torch.as_tensor(F).to(dev), x, (1, 1, p), (2, 2, n), 10.0,
+                                         max_ctrl=(2, 2, n), max_fits=1)
+    T = synth.clamped_uniform_knots(n, p)
+    B = BSpline.design_matrix(x[2], T, p).toarray()
+    G = B.T @ B
+    ab = np.zeros((p + 1, n))                         # upper banded form of the Gram matrix
+    for d in range(p + 1):
+        ab[p - d, d:] = np.diagonal(G, d)
+    ref = solveh_banded(ab, B.T @ F[0, 0].astype(np.float64))
+    got = P.cpu().numpy()
+    assert got.shape == (2, 2, n)
+    tol = REL_ENC * np.abs(F).max() * 10
+    for i in range(2):
+        for j in range(2):
+            assert np.abs(got[i, j] - ref).max() <= tol

@@ -569,6 +569,74 @@ def test_sorted_decode_c4_2e7(mfa, dev, c4):
     _sorted_matches_unsorted(mfa, dev, c4, pts)
 
 
+# ------------------------------------------------------------------ value-only queries
+@pytest.mark.parametrize("which", ["c1", "graded", "multiblock"])
+@pytest.mark.parametrize("sorted_order", [False, True])
+def test_decode_points_value_only(mfa, dev, which, sorted_order):
+    """Value-only queries (Fig. 8a): the value of the value+gradient query,
+    bit for bit (the same sums; the gradient terms are dropped), and the
+    oracle's value within the FP32 tolerance."""
+    if which == "c1":
+        model = synth.model_c1()
+    elif which == "graded":
+        p, ns = 3, (41, 37, 29)
+        knots = [graded_knots(n, p, 5, phase=a) for a, n in enumerate(ns)]
+        model = synth.single_block_model(np.random.default_rng(18).standard_normal(ns), [p] * 3, knots)
+    else:
+        model = small_multiblock()
+    rng = np.random.default_rng(60)
+    pts = np.concatenate([rng.random((30001, 3)).astype(np.float32),
+                          adversarial_points(model, rng, 10)]).T.copy()
+    announce(f"value-only decode {which} sorted={sorted_order} n={pts.shape[1]}")
+    with mfa.Model(model, "f32") as M:
+        x = to_dev(pts, dev)
+        full = mfa.decode_points(M, x, sorted_order=sorted_order).cpu().numpy()
+        val = mfa.decode_points(M, x, sorted_order=sorted_order, value_only=True).cpu().numpy()
+    assert val.shape == (pts.shape[1],)
+    np.testing.assert_array_equal(val.view(np.uint32), full[:, 0].copy().view(np.uint32))
+    ref = oracle_points(model, pts.T)
+    pmax = max(np.abs(b.ctrl).max() for b in model.blocks)
+    assert np.max(np.abs(val - ref["f"])) <= 1e-5 * pmax
+
+
+def test_decode_grid_value_only(mfa, dev, c1):
+    rng = np.random.default_rng(61)
+    ax = [synth.grid_axis(64), np.sort(rng.random(37)), synth.grid_axis(70)]
+    announce("value-only grid 64x37x70")
+    with mfa.Model(c1, "f32") as M:
+        t = [to_dev(a, dev) for a in ax]
+        full = mfa.decode_grid(M, t).cpu().numpy()
+        val = mfa.decode_grid(M, t, value_only=True).cpu().numpy()
+    assert val.shape == (64, 37, 70)
+    np.testing.assert_array_equal(val.view(np.uint32), full[..., 0].copy().view(np.uint32))
+    ref = ob.decode_grid(c1, ax)
+    assert np.max(np.abs(val - ref[..., 0])) <= 1e-5 * np.max(np.abs(c1.blocks[0].ctrl))
+
+
+def test_sorted_decode_calls_on_two_streams_are_ordered(mfa, dev, c1):
+    """Sorted calls on one model from two streams share the model's scratch:
+    the library orders them (a call waits for the previous sorted call's
+    kernels), also when a larger n replaces the scratch; every result equals
+    the unsorted decode bit for bit."""
+    import torch
+    sizes = [300001, 1000, 700001, 200000, 5, 900000]
+    announce("sorted decode on two streams, growing and shrinking n")
+    with mfa.Model(c1, "f32") as M:
+        xs = [to_dev(synth.random_points(n, seed=70 + k), dev) for k, n in enumerate(sizes)]
+        refs = [mfa.decode_points(M, x) for x in xs]
+        outs = [torch.full((x.shape[1], 4), -1.0, device=dev) for x in xs]
+        torch.cuda.synchronize()
+        streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+        for k, (x, o) in enumerate(zip(xs, outs)):
+            s = streams[k % 2]
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                mfa.decode_points(M, x, out=o, sorted_order=True, stream=s)
+        torch.cuda.synchronize()
+        for r, o in zip(refs, outs):
+            np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32), r.cpu().numpy().view(np.uint32))
+
+
 # ------------------------------------------------------------------ serving
 def test_server_results_equal_direct_calls(mfa, dev, c1):
     import torch

@@ -1,7 +1,9 @@
 """Scheduler logic of the serving loop on the CPU, through the C ABI with
 the fake executor (no device work; each batch takes a modelled time per
 work item).  Covers admission by budget, queue limits, first-come-first-
-served order, batch splitting of large requests and the latency stamps."""
+served order, batch splitting of large requests, the latency stamps, and
+the failure path (a batch failed by injection fails only its requests and
+releases their budget)."""
 import os
 import time
 
@@ -104,3 +106,47 @@ def test_destroy_drains_queue(mfa):
     tickets = [s.submit_points(mid, ADDR, ADDR, n=512) for _ in range(10)]
     s.close()                                                  # returns after all are done
     assert len(tickets) == 10
+
+
+def test_failed_batch_fails_only_its_requests_and_releases_budget(mfa):
+    # one-item requests, one item per batch: batch k holds request k.  The
+    # second batch fails as a device error would: its request completes with
+    # MFA_E_DEVICE, the requests before and after it complete normally (the
+    # failure is not sticky), and its budget is released, which the last
+    # request (needing the whole budget) shows by being admitted at all.
+    budget = 28 * 256
+    with server(mfa, hbm_budget_bytes=budget, queue_cap=16, max_batch_items=1,
+                fake_item_us=500.0, fake_fail_batch=2) as s:
+        mid = s.add_model(None)
+        tickets = [s.submit_points(mid, ADDR, ADDR, n=100) for _ in range(4)]
+        tickets.append(s.submit_points(mid, ADDR, ADDR, n=256))     # the whole budget
+        stats = []
+        for t in tickets:
+            try:
+                st = s.wait(t)
+            except mfa.MFAError as e:
+                assert e.status == L.MFA_E_DEVICE
+                st = s.poll(t)
+            stats.append(st)
+    assert [x["done"] for x in stats] == [1] * 5
+    assert [x["status"] for x in stats] == [0, L.MFA_E_DEVICE, 0, 0, 0]
+    assert stats[4]["t_admit"] >= max(x["t_done"] for x in stats[:4]) - 1e-9
+
+
+def test_failure_of_a_split_request_marks_the_whole_request(mfa):
+    # a 9-item frame over 4-item batches spans batches 1..3; batch 2 fails:
+    # the frame fails as a whole (its other batches succeed), the queries
+    # queued behind it (batch 3 or later) succeed
+    with server(mfa, hbm_budget_bytes=1 << 30, queue_cap=16, max_batch_items=4,
+                fake_item_us=300.0, fake_fail_batch=2) as s:
+        mid = s.add_model(None)
+        frame = s.submit_render(mid, None, None, 48, 48, ADDR)      # 3 x 3 tiles
+        q1 = s.submit_points(mid, ADDR, ADDR, n=200)
+        with pytest.raises(mfa.MFAError) as e:
+            s.wait(frame)
+        assert e.value.status == L.MFA_E_DEVICE
+        st = s.poll(frame)
+        assert st["done"] == 1 and st["status"] == L.MFA_E_DEVICE
+        assert s.wait(q1)["status"] == 0
+        q2 = s.submit_points(mid, ADDR, ADDR, n=200)
+        assert s.wait(q2)["status"] == 0
