@@ -164,6 +164,25 @@ mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst,
 mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint32_t flags,
                              float* out, int32_t* dbg, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it): the sorted decode of mfa_decode_points (MFA_DECODE_SORTED is
+ * implied; MFA_DECODE_VALUE may be given) with its scratch in a file-scope
+ * device array of the library, 64 MiB per device, held until the process
+ * ends.  No device memory is allocated or freed by the call.  Arguments,
+ * outputs and results are those of mfa_decode_points (bit-identical).
+ *  n     : the scratch must hold the layout of the sorted decode: 16 bytes
+ *          per point (32 with more than 64 buckets) plus 12 per bucket and
+ *          the decode items, at most 64 MiB (about 2 million points with
+ *          4096 buckets, 4 million with 64 or fewer); a larger n returns
+ *          MFA_E_ARG with the largest n accepted for this model.
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (the kernels clear what must start at zero): calls whose
+ * kernels overlap in time on one device race and give undefined results;
+ * order them on one stream or synchronise between them.                   */
+mfa_status mfa_decode_points_noalloc(mfa_model model, const float* xyz, int64_t n, uint32_t flags,
+                                     float* out, int32_t* dbg, void* stream);
+
 /* Value and gradient on the tensor grid axis_u[0] x axis_u[1] x axis_u[2]
  * of parameters of a single-block model (MFA_E_ARG for multi-block).
  *  axis_u : three device FP64 tables of res[a] parameters (clamped to

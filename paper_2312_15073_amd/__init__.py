@@ -136,12 +136,13 @@ class Model:
 
 
 def decode_points(model: Model, xyz, out=None, dbg: bool = False, sorted_order: bool = False,
-                  value_only: bool = False, stream=None):
+                  value_only: bool = False, stream=None, noalloc: bool = False):
     """Value and world gradient at points xyz (CUDA float32, shape (3, n)).
 
     Returns out (n, 4) float32 = (f, df/dx, df/dy, df/dz), or with
     value_only (n,) float32 = f, and, if dbg, an int32 (n, 4) tensor of
-    (span0, span1, span2, block).
+    (span0, span1, span2, block).  noalloc: the sorted decode through
+    mfa_decode_points_noalloc (library-held static scratch, no allocation).
     """
     torch = _torch()
     if xyz.dim() != 2 or xyz.shape[0] != 3:
@@ -158,7 +159,8 @@ def decode_points(model: Model, xyz, out=None, dbg: bool = False, sorted_order: 
         d = torch.empty((n, 4), dtype=torch.int32, device=xyz.device)
         pd = C.c_void_p(d.data_ptr())
     flags = (L.MFA_DECODE_SORTED if sorted_order else 0) | (L.MFA_DECODE_VALUE if value_only else 0)
-    L.check(L.lib().mfa_decode_points(model.handle, px, n, flags, po, pd, _stream_ptr(stream)))
+    fn = L.lib().mfa_decode_points_noalloc if noalloc else L.lib().mfa_decode_points
+    L.check(fn(model.handle, px, n, flags, po, pd, _stream_ptr(stream)))
     return (out, d) if dbg else out
 
 

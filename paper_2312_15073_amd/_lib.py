@@ -93,6 +93,8 @@ SIGNATURES = {
     "mfa_model_export_ctrl": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "mfa_decode_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p,
                                     C.c_void_p, C.c_void_p]),
+    "mfa_decode_points_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]),
     "mfa_decode_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
                                   C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mfa_render_frame": (C.c_int, [C.c_void_p, C.POINTER(Camera), C.POINTER(RenderParams),

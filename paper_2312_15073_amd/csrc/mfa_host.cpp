@@ -24,6 +24,7 @@ hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, bool grad, co
                               hipStream_t st);
 hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind, bool grad,
                                 const SortArgs& sa, float* out, int32_t* dbg, hipStream_t st);
+hipError_t static_scratch(void** ptr);
 hipError_t launch_render(const DevModel& m, int p, Storage s, int kind, const RenderArgs& r,
                          hipStream_t st);
 hipError_t launch_composite(const CompositeArgs& c, hipStream_t st);
@@ -827,6 +828,34 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
                                       out, dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_points launch");
   return MFA_OK;
+}
+
+extern "C" mfa_status mfa_decode_points_noalloc(mfa_model m, const float* xyz, int64_t n,
+                                                uint32_t flags, float* out, int32_t* dbg,
+                                                void* stream) {
+  mfa_status st = check_points(m, xyz, n, flags, out);
+  if (st != MFA_OK) return st;
+  if (m->n_buckets > kMaxBuckets)
+    return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
+  const SortLayout L = sort_layout(n, m->n_buckets);
+  if (L.bytes > kStaticScratchBytes) {
+    // largest n whose scratch fits, for the message
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (sort_layout(mid, m->n_buckets).bytes <= kStaticScratchBytes) lo = mid; else hi = mid - 1;
+    }
+    return fail(MFA_E_ARG, "n = %lld needs %zu bytes of scratch, more than the %zu of the static "
+                "scratch (at most %lld points for this model)", (long long)n, L.bytes,
+                kStaticScratchBytes, (long long)lo);
+  }
+  if (n == 0) return MFA_OK;
+  st = check_device(m);
+  if (st != MFA_OK) return st;
+  void* w = nullptr;
+  hipError_t e = static_scratch(&w);
+  if (e != hipSuccess) return hip_fail(e, "static scratch address");
+  return sorted_decode(m, (uint8_t*)w, L, xyz, n, !(flags & MFA_DECODE_VALUE), out, dbg, stream);
 }
 
 extern "C" mfa_status mfa_decode_grid(mfa_model m, const double* const axis_u[3], const int32_t res[3],

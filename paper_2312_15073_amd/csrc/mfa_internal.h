@@ -13,6 +13,7 @@
 // is also copied into the kernel argument (DevModel::b0) so it is uniform.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace mfa {
@@ -69,6 +70,10 @@ constexpr int kCoarseBuckets = 64;
 // the same two L2 channels.
 constexpr int kCursorStride = 32;
 constexpr int kWinMax = 8192;
+
+// Size of the file-scope device scratch of the allocation-free sorted
+// decode (one copy per device, held until the process ends).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 
 struct BucketWin {
   int32_t block;        // owning block

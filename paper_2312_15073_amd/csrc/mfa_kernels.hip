@@ -15,6 +15,7 @@
 #include <hip/hip_fp16.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "mfa.h"
 #include "mfa_internal.h"
@@ -2089,6 +2090,36 @@ hipError_t launch_decode_sorted(const DevModel& m, int p, Storage s, int kind, b
 hipError_t launch_serve(int p, Storage s, bool multi, const DevModel* models, const ServeReq* reqs,
                         const ServeItem* items, int n_items, int* cursor, int grid, hipStream_t st) {
   MFA_DISPATCH(serve_p, multi, models, reqs, items, n_items, cursor, grid, st)
+}
+
+// Scratch of the allocation-free sorted decode: a file-scope device array
+// (each device holding its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: on the host it is a stand-in,
+// not a device address.  The device address is read once per device, with
+// that device current, by hipGetSymbolAddress and kept here.
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<void*> addr[kMaxDevices];
+  static std::mutex mu;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* a = addr[dev].load(std::memory_order_acquire);
+  if (a == nullptr) {
+    std::lock_guard<std::mutex> g(mu);
+    a = addr[dev].load(std::memory_order_relaxed);
+    if (a == nullptr) {
+      e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      if (a == nullptr) return hipErrorInvalidSymbol;
+      addr[dev].store(a, std::memory_order_release);
+    }
+  }
+  *ptr = a;
+  return hipSuccess;
 }
 
 hipError_t launch_decode_grid(const DevModel& m, int p, Storage s, bool grad, const GridArgs& ga,

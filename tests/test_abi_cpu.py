@@ -115,6 +115,7 @@ def test_model_create_rejects_bad_arguments_before_device_work():
 def test_null_model_calls_are_rejected():
     lib = L.lib()
     assert lib.mfa_decode_points(None, None, 10, 0, None, None, None) == L.MFA_E_ARG
+    assert lib.mfa_decode_points_noalloc(None, None, 10, 0, None, None, None) == L.MFA_E_ARG
     assert lib.mfa_decode_grid(None, None, None, 0, None, None, None) == L.MFA_E_ARG
     assert lib.mfa_render_frame(None, None, None, 4, 4, None, None, None) == L.MFA_E_ARG
     assert lib.mfa_model_info(None, None) == L.MFA_E_ARG
