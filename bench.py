@@ -177,7 +177,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single128",
                     choices=["single128", "multiblock", "serving", "points", "encode", "encode_adaptive",
-                             "composite", "iso", "graded", "quality"],
+                             "composite", "iso", "graded", "quality", "storage", "values", "cr_sweep"],
                     help="single128: 128^3 model, 512^3 grid + 1e7 points + 1024^2 frame (default); "
                          "multiblock: 8x8x8 blocks, 1e8 sorted points + 2048^2 frame; "
                          "serving: open-loop request trace over three resident models; "
@@ -187,7 +187,14 @@ def main(argv=None):
                          "quality: Marschner-Lobb frames, MFA vs local filters, PSNR vs analytic; "
                          "graded: the default step on the 128^3 model with graded knots; "
                          "iso: first-hit isosurface of the 128^3 model's 1024^2 frame; "
-                         "composite: 8 octant partial renders of the 8x8x8-block frame + over")
+                         "composite: 8 octant partial renders of the 8x8x8-block frame + over; "
+                         "storage: FP32 vs BF16 vs FP16 storage on the 128^3 and 8x8x8-block steps, "
+                         "kernel times and image error against the FP64 oracle and the analytic "
+                         "field; values: value-only vs value+gradient queries (grid and points); "
+                         "cr_sweep: Marschner-Lobb 256^3 encoded at compression ratios 20..212, "
+                         "encode time, ms/frame and PSNR")
+    ap.add_argument("--storage-model", default="both", choices=["both", "single128", "multiblock"],
+                    help="storage: which model(s) to compare")
     ap.add_argument("--points-model", default="single128", choices=["single128", "multiblock"],
                     help="points: the 128^3 model with 1e7 points or the 8x8x8-block model with 1e8")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -218,6 +225,12 @@ def main(argv=None):
         return run_iso(args)
     if args.workload == "quality":
         return run_quality(args)
+    if args.workload == "storage":
+        return run_storage(args)
+    if args.workload == "values":
+        return run_values(args)
+    if args.workload == "cr_sweep":
+        return run_cr_sweep(args)
     if args.workload == "graded":
         if args.steps is None:
             args.steps = 20
@@ -546,6 +559,16 @@ def encode_flop(res, n_ctrl) -> float:
     N0, N1, N2 = res
     n0, n1, n2 = n_ctrl
     return 2.0 * (n0 * N0 * N1 * N2 + n1 * N1 * n0 * N2 + n2 * N2 * n0 * n1)
+
+
+def _encode_bytes(res, n_ctrl) -> float:
+    """Algorithmic bytes of one apply: the FP32 samples read once, the two
+    FP64 intermediate products written and read once, the FP64 control
+    points written, the three FP64 pseudo-inverse tables read."""
+    N0, N1, N2 = res
+    n0, n1, n2 = n_ctrl
+    return (4.0 * N0 * N1 * N2 + 16.0 * n0 * N1 * N2 + 16.0 * n0 * n1 * N2 + 8.0 * n0 * n1 * n2
+            + 8.0 * (n0 * N0 + n1 * N1 + n2 * N2))
 
 
 def _encode_cpu_baseline():
@@ -1087,3 +1110,277 @@ def run_serving(args):
 
 if __name__ == "__main__":
     sys.exit(main())
+
+
+# ------------------------------------------------------------------ storage-form comparison
+def _image_errors(img, ref):
+    """RMSE over RGBA and 8-bit PSNR over RGB of sampled pixels (m, 4)."""
+    rmse = float(np.sqrt(np.mean((img.astype(np.float64) - ref) ** 2)))
+    return rmse, _psnr8(img, ref)[0]
+
+
+def _storage_case(args, name, spec, field, step_fn_factory, frame, params, n_pix, seed):
+    """Kernel times of one step per storage form, and the image error of
+    the frame on n_pix sampled pixels against the FP64 oracle (FP64 control
+    points) and against the analytic field rendered by the same oracle
+    renderer (the ground truth of the paper's image-error comparison)."""
+    import torch
+    import paper_2312_15073_amd as mfa
+    from oracle import render as orr
+    dev = torch.device("cuda:0")
+    steps = 10 if args.steps is None else args.steps
+    cam = synth.perspective_camera(frame, frame)
+    rng = np.random.default_rng(seed)
+    pix = np.stack([rng.integers(0, frame, n_pix), rng.integers(0, frame, n_pix)], axis=1)
+    flat = pix[:, 0] * frame + pix[:, 1]
+    t0 = time.perf_counter()
+    ref = orr.render(orr.model_field(spec), spec.lo, spec.hi, cam, params, frame, frame,
+                     pixels=pix)["rgba"]
+    gt = orr.render(lambda x: field.value_grad(x), spec.lo, spec.hi, cam, params, frame, frame,
+                    pixels=pix)["rgba"]
+    t_oracle = time.perf_counter() - t0
+    rows = {}
+    for storage in ("f32", "bf16", "f16"):
+        model = mfa.Model(spec, storage)
+        names, step = step_fn_factory(model, cam)
+        for _ in range(args.warmup):
+            step(None)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        ms_step = 1e3 * (time.perf_counter() - t0) / steps
+        kms = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+               for i, n in enumerate(names)}
+        tf = torch.as_tensor(params["tf"], device=dev)
+        img = mfa.render_frame(model, cam, params, frame, frame, tf_dev=tf, device=dev)
+        img = img.cpu().numpy().reshape(-1, 4)[flat]
+        e_or, p_or = _image_errors(img, ref)
+        e_gt, p_gt = _image_errors(img, gt)
+        rows[storage] = dict(ms_step=ms_step, kernels_ms=kms, ctrl_bytes=model.info()["ctrl_bytes"],
+                             image_rmse_vs_fp64_oracle=e_or, image_psnr8_vs_fp64_oracle=p_or,
+                             image_rmse_vs_ground_truth=e_gt, image_psnr8_vs_ground_truth=p_gt)
+        model.close()
+    f32 = rows["f32"]
+    for storage, r in rows.items():
+        r["speedup_vs_f32_step"] = f32["ms_step"] / r["ms_step"]
+        r["speedup_vs_f32_kernels"] = {k: f32["kernels_ms"][k] / v for k, v in r["kernels_ms"].items()}
+        r["equal_image_error_to_f32"] = bool(
+            r["image_rmse_vs_ground_truth"] <= 1.05 * f32["image_rmse_vs_ground_truth"]
+            or abs(r["image_psnr8_vs_ground_truth"] - f32["image_psnr8_vs_ground_truth"]) <= 0.1)
+    return {"model": name, "sampled_pixels": n_pix, "oracle_seconds": t_oracle, "forms": rows}
+
+
+def run_storage(args):
+    """FP32 against BF16 and FP16 control-point storage on the 128^3 step
+    (512^3 grid + 1e7 sorted points + 1024^2 frame) and the 8x8x8-block step
+    (1e8 sorted points + 2048^2 frame): per-kernel times and the speedup of
+    each form at the image error it reaches (Table II's comparison against
+    the analytic field)."""
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    out = []
+    if args.storage_model in ("both", "single128"):
+        spec = synth.model_c2()
+        params = synth.render_params(spec)
+        xyz = torch.as_tensor(synth.random_points(N_POINTS, seed=12), device=dev)
+        axes = [torch.as_tensor(synth.grid_axis(GRID_N), device=dev) for _ in range(3)]
+        grid_out = torch.empty((GRID_N, GRID_N, GRID_N, 4), dtype=torch.float32, device=dev)
+        pts_out = torch.empty((N_POINTS, 4), dtype=torch.float32, device=dev)
+        rgba = torch.empty((FRAME, FRAME, 4), dtype=torch.float32, device=dev)
+        tf = torch.as_tensor(params["tf"], device=dev)
+
+        def factory(model, cam):
+            def step(ev):
+                if ev is not None:
+                    ev[0].record(stream)
+                mfa.decode_grid(model, axes, out=grid_out)
+                if ev is not None:
+                    ev[1].record(stream)
+                mfa.decode_points(model, xyz, out=pts_out, sorted_order=True)
+                if ev is not None:
+                    ev[2].record(stream)
+                mfa.render_frame(model, cam, params, FRAME, FRAME, tf_dev=tf, out=rgba, device=dev)
+                if ev is not None:
+                    ev[3].record(stream)
+            return ["decode_grid", "decode_points", "render"], step
+
+        out.append(_storage_case(args, "single block, 128^3 control points, degree 3", spec,
+                                 synth.field_c2(), factory, FRAME, params, 1024, 31))
+        del grid_out, pts_out, xyz
+        torch.cuda.empty_cache()
+    if args.storage_model in ("both", "multiblock"):
+        spec = synth.model_c4()
+        params = synth.render_params(spec, max_samples=2048)
+        xyz = torch.as_tensor(synth.random_points(MB_POINTS, seed=14), device=dev)
+        pts_out = torch.empty((MB_POINTS, 4), dtype=torch.float32, device=dev)
+        rgba = torch.empty((MB_FRAME, MB_FRAME, 4), dtype=torch.float32, device=dev)
+        tf = torch.as_tensor(params["tf"], device=dev)
+
+        def factory(model, cam):
+            def step(ev):
+                if ev is not None:
+                    ev[0].record(stream)
+                mfa.decode_points(model, xyz, out=pts_out, sorted_order=True)
+                if ev is not None:
+                    ev[1].record(stream)
+                mfa.render_frame(model, cam, params, MB_FRAME, MB_FRAME, tf_dev=tf, out=rgba, device=dev)
+                if ev is not None:
+                    ev[2].record(stream)
+            return ["decode_points", "render"], step
+
+        out.append(_storage_case(args, "8x8x8 blocks, 56.8M control points, degree 3", spec,
+                                 synth.turbulence_field(512, 104), factory, MB_FRAME, params, 384, 32))
+    c = out[0]
+    bf = c["forms"]["bf16"]
+    print(json.dumps({
+        "metric": "speedup of BF16 control-point storage over FP32 (step time) at the image error it reaches",
+        "value": bf["speedup_vs_f32_step"], "unit": "x", "n_gpus": 1,
+        "steps": 10 if args.steps is None else args.steps, "warmup": args.warmup,
+        "ms_per_step": bf["ms_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f32 / bf16 / f16 storage)", "data": "synthetic",
+        "config": {"workload": "storage forms on the 128^3 step and the 8x8x8-block step",
+                   "cases": out, "parallelism": "single GPU"},
+        "cpu_baseline": None}), flush=True)
+    return 0
+
+
+# ------------------------------------------------------------------ value-only queries
+def run_values(args):
+    """Value-only against value+gradient queries (the paper's Fig. 8a and
+    8b) on the 128^3 model: the 512^3 grid and 1e7 random points (sorted)."""
+    steps = 10 if args.steps is None else args.steps
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    spec = synth.model_c2()
+    model = mfa.Model(spec, args.storage)
+    axes = [torch.as_tensor(synth.grid_axis(GRID_N), device=dev) for _ in range(3)]
+    xyz = torch.as_tensor(synth.random_points(N_POINTS, seed=12), device=dev)
+    g4 = torch.empty((GRID_N, GRID_N, GRID_N, 4), dtype=torch.float32, device=dev)
+    g1 = torch.empty((GRID_N, GRID_N, GRID_N), dtype=torch.float32, device=dev)
+    p4 = torch.empty((N_POINTS, 4), dtype=torch.float32, device=dev)
+    p1 = torch.empty((N_POINTS,), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+
+    rows = {
+        "grid value+gradient": (timed(lambda: mfa.decode_grid(model, axes, out=g4)), GRID_N ** 3, 16),
+        "grid value": (timed(lambda: mfa.decode_grid(model, axes, out=g1, value_only=True)), GRID_N ** 3, 4),
+        "points value+gradient (sorted)": (timed(lambda: mfa.decode_points(model, xyz, out=p4, sorted_order=True)),
+                                           N_POINTS, 28),
+        "points value (sorted)": (timed(lambda: mfa.decode_points(model, xyz, out=p1, sorted_order=True,
+                                                                  value_only=True)), N_POINTS, 16),
+        "points value+gradient (input order)": (timed(lambda: mfa.decode_points(model, xyz, out=p4)),
+                                                N_POINTS, 28),
+        "points value (input order)": (timed(lambda: mfa.decode_points(model, xyz, out=p1, value_only=True)),
+                                       N_POINTS, 16),
+    }
+    res = {k: dict(ms=ms, samples_per_s=n / (ms * 1e-3), hbm_gbs=(n * b + model.info()["ctrl_bytes"]) / (ms * 1e6),
+                   bytes_per_unit=b) for k, (ms, n, b) in rows.items()}
+    tot_ms = res["grid value"]["ms"] + res["points value (sorted)"]["ms"]
+    print(json.dumps({
+        "metric": "value-only queries/s (grid + sorted points)",
+        "value": (GRID_N ** 3 + N_POINTS) / (tot_ms * 1e-3), "unit": "samples/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": tot_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"f32 ({args.storage} storage)", "data": "synthetic",
+        "config": {"workload": f"128^3 model, degree 3: {GRID_N}^3 grid and {N_POINTS} random points, "
+                               "value only against value + gradient", "queries": res,
+                   "parallelism": "single GPU"},
+        "cpu_baseline": None}), flush=True)
+    model.close()
+    return 0
+
+
+# ------------------------------------------------------------------ compression-ratio sweep
+def run_cr_sweep(args):
+    """Marschner-Lobb 256^3 samples (Sec. V-A1 function on [0, 7]^3)
+    encoded by the fixed-knot least-squares fit (degree 2) at control-point
+    counts n^3 giving compression ratios (256/n)^3 of about 20, 69, 134 and
+    212 (the ratios of Fig. 5), plus 128^3 (8) and 256^3 (1) for reference:
+    encode time, the 768^2 frame time and its PSNR against the analytic
+    field."""
+    steps = 5 if args.steps is None else args.steps
+    import torch
+    import paper_2312_15073_amd as mfa
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    N, S = QUALITY_N, QUALITY_FRAME
+    lo, hi = (0.0, 0.0, 0.0), (7.0, 7.0, 7.0)
+    vol = torch.as_tensor(synth.marschner_lobb_samples(N)).to(dev)
+    cam = synth.perspective_camera(S, S, az_deg=30.0, el_deg=35.0, dist=15.0, centre=(3.5, 3.5, 3.5))
+    params = dict(tf=synth.tf_table_A(), vmin=np.float32(0.0), vmax=np.float32(1.0),
+                  step=0.5 * 7.0 / (N - 1), max_samples=2048, ert_alpha=np.float32(0.99),
+                  ka=np.float32(0.3), kd=np.float32(0.6), ks=np.float32(0.3),
+                  g0=np.float32(0.01), shininess=16)
+    tf = torch.as_tensor(params["tf"], device=dev)
+    out = torch.empty((S, S, 4), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+
+    mfa.render_volume(None, "marschner_lobb", lo, hi, cam, params, S, S, dims=(N, N, N), tf_dev=tf,
+                      out=out, device=dev)
+    gt = out.cpu().numpy().copy()
+    axis = np.arange(N, dtype=np.float64) / (N - 1)
+    rows = []
+    for n in (256, 128, 94, 62, 50, 43):
+        plan = mfa.EncodePlan((N, N, N), [axis] * 3, (2, 2, 2), (n, n, n))
+        P = plan.apply(vol)
+        ms_enc = timed(lambda: plan.apply(vol, out=P))
+        Ph = P.cpu().numpy()
+        del plan
+        fl = encode_flop((N, N, N), (n, n, n))
+        spec = synth.single_block_model(Ph, [2, 2, 2], None, lo=lo, hi=hi, voxel=7.0 / (N - 1))
+        with mfa.Model(spec, "f32") as M:
+            _, ns, ne = mfa.render_frame(M, cam, params, S, S, tf_dev=tf, nsamp=True, neval=True,
+                                         device=dev)
+            s_eval = int(ne.sum().item())
+            ms = timed(lambda: mfa.render_frame(M, cam, params, S, S, tf_dev=tf, out=out, device=dev))
+            ps, m = _psnr8(out.cpu().numpy(), gt)
+        rows.append(dict(n_ctrl=n, compression_ratio=(N / n) ** 3, encode_ms=ms_enc,
+                         encode_tflops_dense=fl / (ms_enc * 1e-3) / 1e12,
+                         encode_hbm_gbs=_encode_bytes((N, N, N), (n, n, n)) / (ms_enc * 1e6),
+                         ms_per_frame=ms, psnr8=ps, mse8=m, evaluated_samples=s_eval,
+                         render_tflops=s_eval * (flop_per_sample(2) + 54) / (ms * 1e-3) / 1e12))
+        del P, spec
+    r20 = next(r for r in rows if r["n_ctrl"] == 94)
+    print(json.dumps({
+        "metric": "PSNR (dB) of a 768^2 Marschner-Lobb frame at compression ratio 20",
+        "value": r20["psnr8"], "unit": "dB", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": r20["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (FP64 encode)", "data": "synthetic",
+        "config": {"workload": f"Marschner-Lobb {N}^3 FP32 samples on [0, 7]^3, degree 2 fits at "
+                               f"n^3 control points, {S}^2 perspective frames", "sweep": rows,
+                   "parallelism": "single GPU"},
+        "cpu_baseline": None}), flush=True)
+    return 0

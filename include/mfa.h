@@ -139,14 +139,16 @@ mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst,
  *  n     : 0 <= n < 2^31 (n == 0 is a no-op).
  *  flags : a combination of
  *          MFA_DECODE_SORTED: points are first grouped by bucket = (owning
- *          block, tile of 2^k spans per axis, k chosen per model for at most
- *          4096 buckets; models of more than 4096 blocks return
- *          MFA_E_UNSUPPORTED) and evaluated in that order, so neighbouring
- *          threads share control points; results are still written in input
- *          order and are identical bit for bit to the unsorted call.  Uses
- *          scratch memory held by the model (16 bytes per point, 32 with
- *          more than 64 buckets, plus 12 per bucket), allocated on first use
- *          and grown when a larger n arrives (MFA_E_NOMEM if that fails).
+ *          block, tile of 2^k spans per axis, k chosen per model: the
+ *          largest whose control-point windows fit 8192 values, larger
+ *          while the model has more than 32768 buckets; models of more than
+ *          32768 blocks return MFA_E_UNSUPPORTED) and evaluated in that
+ *          order, each bucket's control points staged once in on-chip
+ *          memory; results are still written in input order and are
+ *          identical bit for bit to the unsorted call.  Uses scratch memory
+ *          held by the model (16 bytes per point, 32 with more than 1024
+ *          buckets, plus about 20 per bucket), allocated on first use and
+ *          grown when a larger n arrives (MFA_E_NOMEM if that fails).
  *          Sorted calls on one model are ordered by the library: a call
  *          waits (on its stream) for the previous sorted call's kernels
  *          before it reuses the scratch, and for their completion (on the
@@ -172,10 +174,10 @@ mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint3
  * ends.  No device memory is allocated or freed by the call.  Arguments,
  * outputs and results are those of mfa_decode_points (bit-identical).
  *  n     : the scratch must hold the layout of the sorted decode: 16 bytes
- *          per point (32 with more than 64 buckets) plus 12 per bucket and
- *          the decode items, at most 64 MiB (about 2 million points with
- *          4096 buckets, 4 million with 64 or fewer); a larger n returns
- *          MFA_E_ARG with the largest n accepted for this model.
+ *          per point (32 with more than 1024 buckets) plus about 20 per
+ *          bucket and the decode items, at most 64 MiB (about 4 million
+ *          points with up to 1024 buckets, 2 million above); a larger n
+ *          returns MFA_E_ARG with the largest n accepted for this model.
  * Every call on a device shares that device's scratch, which keeps the last
  * call's contents (the kernels clear what must start at zero): calls whose
  * kernels overlap in time on one device race and give undefined results;

@@ -204,7 +204,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 static void free_model(mfa_model m) {
   if (!m) return;
   if (m->ws_done) (void)hipEventDestroy(m->ws_done);
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws, m->d_sblk};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -482,35 +482,43 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       for (int l = 0; l < 2; ++l)
         dblk[b].sc[l][a] = (dblk[b].nsp[a] + (1 << sc_shift[l]) - 1) >> sc_shift[l];
     }
-  // sort tiles: the finest power-of-two span groups giving at most
-  // kMaxBuckets buckets (blocks count at least one bucket each)
-  int sort_shift = -1;
-  int64_t buckets = 0;
-  for (int sh = 0; sh <= 16 && sort_shift < 0; ++sh) {
-    buckets = 0;
+  // sort tiles of 2^sort_shift spans per axis: the largest whose control-
+  // point windows (the tile's spans plus p per axis) hold at most kWinMax
+  // values, so the decode stages them in LDS; larger while the model would
+  // have more than kMaxBuckets buckets (blocks count at least one bucket
+  // each; their windows are then decoded from global memory)
+  auto tiles_of = [&](int64_t b, int sh, int a) { return (dblk[b].nsp[a] + (1 << sh) - 1) >> sh; };
+  auto count_buckets = [&](int sh) {
+    int64_t c = 0;
+    for (int64_t b = 0; b < nb; ++b) c += (int64_t)tiles_of(b, sh, 0) * tiles_of(b, sh, 1) * tiles_of(b, sh, 2);
+    return c;
+  };
+  auto max_window = [&](int sh) {
+    int64_t w = 0;
     for (int64_t b = 0; b < nb; ++b) {
-      int64_t t = 1;
-      for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << sh) - 1) >> sh;
-      buckets += t;
+      int64_t v = 1;
+      for (int a = 0; a < 3; ++a) v *= std::min(1 << sh, (int)dblk[b].nsp[a]) + p;
+      w = std::max(w, v);
     }
-    if (buckets <= kMaxBuckets) sort_shift = sh;
-  }
-  if (sort_shift < 0) sort_shift = 16;    // more blocks than buckets: sorted decode rejected
+    return w;
+  };
+  int sort_shift = 0;
+  while (sort_shift < 16 && max_window(sort_shift + 1) <= kWinMax) ++sort_shift;
+  while (sort_shift < 16 && count_buckets(sort_shift) > kMaxBuckets) ++sort_shift;
+  const int64_t buckets = count_buckets(sort_shift);   // > kMaxBuckets: sorted decode rejected
   for (int64_t b = 0, acc = 0; b < nb; ++b) {
     dblk[b].tile_off = (int32_t)acc;
-    int64_t t = 1;
-    for (int a = 0; a < 3; ++a) t *= (dblk[b].nsp[a] + (1 << sort_shift) - 1) >> sort_shift;
-    acc += t;
+    acc += (int64_t)tiles_of(b, sort_shift, 0) * tiles_of(b, sort_shift, 1) * tiles_of(b, sort_shift, 2);
   }
   m->n_buckets = buckets;
   // control-point window of each sort bucket, in bucket order: the tile's
-  // spans widened by one span on each side, clamped to the block
+  // spans plus p control points per axis
   std::vector<BucketWin> bwin;
   if (buckets <= kMaxBuckets) {
     bwin.reserve((size_t)buckets);
     for (int64_t b = 0; b < nb; ++b) {
       int td[3];
-      for (int a = 0; a < 3; ++a) td[a] = (dblk[b].nsp[a] + (1 << sort_shift) - 1) >> sort_shift;
+      for (int a = 0; a < 3; ++a) td[a] = tiles_of(b, sort_shift, a);
       for (int t0 = 0; t0 < td[0]; ++t0)
         for (int t1 = 0; t1 < td[1]; ++t1)
           for (int t2 = 0; t2 < td[2]; ++t2) {
@@ -518,14 +526,24 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
             BucketWin w{};
             w.block = (int32_t)b;
             for (int a = 0; a < 3; ++a) {
-              const int j0 = std::max((t[a] << sort_shift) - 1, 0);
-              const int j1 = std::min((t[a] + 1) << sort_shift, dblk[b].nsp[a] - 1);
+              const int j0 = t[a] << sort_shift;
+              const int j1 = std::min((t[a] + 1) << sort_shift, dblk[b].nsp[a]);   // one past
               w.o[a] = j0;
-              w.w[a] = j1 + p - j0 + 1;
+              w.w[a] = j1 - j0 + p;
             }
             bwin.push_back(w);
           }
     }
+  }
+  // per block, the data of the sort-bucket computation
+  std::vector<SortBlk> sblk((size_t)nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      sblk[b].lo[a] = dblk[b].lo[a];
+      sblk[b].inv_ext[a] = dblk[b].inv_ext[a];
+      sblk[b].nsp[a] = dblk[b].nsp[a];
+    }
+    sblk[b].tile_off = dblk[b].tile_off;
   }
   int32_t win_max = 0;
   for (const BucketWin& w : bwin) win_max = std::max(win_max, w.w[0] * w.w[1] * w.w[2]);
@@ -620,6 +638,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (st = upload(&m->d_scb[1], scb16[1].data(), scb16[1].size() * 4, m, "bounds upload")) != MFA_OK ||
       (!bwin.empty() &&
        (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK) ||
+      (st = upload(&m->d_sblk, sblk.data(), sblk.size() * sizeof(SortBlk), m, "sort table upload")) != MFA_OK ||
       (!gtab.empty() &&
        ((st = upload(&m->d_gtab, gtab.data(), gtab.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK ||
         (st = upload(&m->d_gmeta, gmeta.data(), gmeta.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK))) {
@@ -655,6 +674,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     dm.sc_shift[l] = sc_shift[l];
   }
   dm.bwin = m->d_bwin;
+  dm.sblk = m->d_sblk;
+  dm.n_edges = (int32_t)edge_pool.size();
   dm.gtab = m->d_gtab;
   dm.gmeta = m->d_gmeta;
   dm.win_max = win_max;
@@ -733,6 +754,7 @@ static mfa_status check_points(mfa_model m, const float* xyz, int64_t n, uint32_
 struct SortLayout {
   size_t o_hist, o_start, o_cur, o_items, o_nitems, o_ccur, o_tmp, bytes;
   bool two;
+  int fine_shift;
 };
 
 static SortLayout sort_layout(int64_t n, int64_t nb) {
@@ -742,11 +764,13 @@ static SortLayout sort_layout(int64_t n, int64_t nb) {
   const size_t n_items = (size_t)((n + kTilePoints - 1) / kTilePoints) + nbk;
   L.o_hist = al(16 * (size_t)n);
   L.o_start = L.o_hist + al(4 * nbk);
-  L.o_cur = L.o_start + al(4 * nbk);
+  L.o_cur = L.o_start + al(4 * (nbk + 1));
   L.o_items = L.o_cur + al(4 * nbk);
   L.o_nitems = L.o_items + al(8 * n_items);
   L.o_ccur = L.o_nitems + al(4);
-  L.two = nbk > (size_t)kCoarseBuckets;
+  L.two = nbk > (size_t)kOneLevelBuckets;
+  L.fine_shift = 0;
+  while ((nb + (1ll << L.fine_shift) - 1) >> L.fine_shift > kCoarseBuckets) ++L.fine_shift;
   L.o_tmp = L.o_ccur + al(4 * kCoarseBuckets * kCursorStride);
   L.bytes = L.two ? L.o_tmp + al(16 * (size_t)n) : L.o_ccur;
   return L;
@@ -765,6 +789,7 @@ static mfa_status sorted_decode(mfa_model m, uint8_t* w, const SortLayout& L, co
   sa.items = (int2*)(w + L.o_items);
   sa.n_items = (int32_t*)(w + L.o_nitems);
   sa.nb = (int32_t)m->n_buckets;
+  sa.fine_shift = L.fine_shift;
   sa.tmp = L.two ? (float4*)(w + L.o_tmp) : nullptr;
   sa.ccursor = L.two ? (uint32_t*)(w + L.o_ccur) : nullptr;
   hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), grad, sa, out,
@@ -782,7 +807,7 @@ extern "C" mfa_status mfa_decode_points(mfa_model m, const float* xyz, int64_t n
   const bool grad = !(flags & MFA_DECODE_VALUE);
   if (flags & MFA_DECODE_SORTED) {
     if (m->n_buckets > kMaxBuckets)
-      return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
+      return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d buckets (blocks)", kMaxBuckets);
     const SortLayout L = sort_layout(n, m->n_buckets);
     // The scratch is the model's: a sorted call waits for the previous
     // sorted call's kernels (an event recorded after them) before it reuses
@@ -836,7 +861,7 @@ extern "C" mfa_status mfa_decode_points_noalloc(mfa_model m, const float* xyz, i
   mfa_status st = check_points(m, xyz, n, flags, out);
   if (st != MFA_OK) return st;
   if (m->n_buckets > kMaxBuckets)
-    return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d blocks", kMaxBuckets);
+    return fail(MFA_E_UNSUPPORTED, "sorted decode supports at most %d buckets (blocks)", kMaxBuckets);
   const SortLayout L = sort_layout(n, m->n_buckets);
   if (L.bytes > kStaticScratchBytes) {
     // largest n whose scratch fits, for the message

@@ -50,20 +50,26 @@ struct DevBlock {
 static_assert(sizeof(DevBlock) == 176, "DevBlock layout");
 
 // Points sorted for decode are grouped by (block, tile); a tile spans
-// 2^sort_shift knot spans per axis, the shift chosen per model so that there
-// are at most kMaxBuckets buckets.
-constexpr int kMaxBuckets = 4096;
+// 2^sort_shift knot spans per axis, the shift chosen per model: the largest
+// whose control-point windows fit kWinMax values, made larger while the
+// model would have more than kMaxBuckets buckets.
+constexpr int kMaxBuckets = 32768;
 
 // Sorted decode works on items of at most kTilePoints consecutive sorted
-// points of one bucket.  The control points a bucket's points can touch
-// (its spans widened by one span on each side, where the exact span of a
-// point can differ from the estimate that chose its bucket) form a window
-// that is staged in LDS when it holds at most kWinMax values.
-constexpr int kTilePoints = 2048;
+// points of one bucket (a bucket of c points is cut into ceil(c /
+// kTilePoints) items of equal size).  The control points the exact spans of
+// a bucket's points can touch (the tile's spans plus p per axis) form a
+// window that is staged in LDS when it holds at most kWinMax values; a point
+// whose exact spans leave the window (a span guess that rounding moved into
+// the neighbouring tile, or non-uniform knots) reads its rows from global
+// memory.
+constexpr int kTilePoints = 4096;
 
-// Above kCoarseBuckets buckets the points are split in two passes, first by
-// bucket >> kFineShift, so that every pass writes long runs of records.
-constexpr int kFineShift = 6;
+// Up to kOneLevelBuckets buckets the points are scattered to their buckets
+// in one pass; above, in two: first by coarse key bucket >> fine_shift (at
+// most kCoarseBuckets keys, runs of hundreds of records per chunk), then
+// within the coarse runs by bucket.
+constexpr int kOneLevelBuckets = 1024;
 constexpr int kCoarseBuckets = 64;
 // The coarse cursors sit one per 128-byte line: every chunk updates all of
 // them, and 64 counters in two lines would put every atomic of the pass on
@@ -74,6 +80,19 @@ constexpr int kWinMax = 8192;
 // Size of the file-scope device scratch of the allocation-free sorted
 // decode (one copy per device, held until the process ends).
 constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+
+// Per-block data of the bucket computation of multi-block models, staged in
+// LDS by the sort kernels (models of at most kSortBlkLds blocks and
+// kSortEdgesLds block edges).
+struct SortBlk {
+  double lo[3];
+  double inv_ext[3];
+  int32_t nsp[3];
+  int32_t tile_off;
+};
+static_assert(sizeof(SortBlk) == 64, "SortBlk layout");
+constexpr int kSortBlkLds = 512;
+constexpr int kSortEdgesLds = 256;
 
 struct BucketWin {
   int32_t block;        // owning block
@@ -115,6 +134,8 @@ struct DevModel {
   int32_t sort_shift;    // log2 of the spans per sort tile and axis
   const BucketWin* bwin;  // per sort bucket: control-point window
   int32_t win_max;       // largest window (values)
+  const SortBlk* sblk;   // per block: data of the sort-bucket computation
+  int32_t n_edges;       // block edges over the three axes
   const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
                          // two FP16 halves rounded outward, widened by a margin
                          // covering FP32 evaluation error
@@ -191,15 +212,16 @@ struct SortArgs {
   int64_t n;
   float4* rec;           // [n] sorted records (x, y, z, input index as bits)
   uint32_t* hist;        // [nb] points per bucket
-  uint32_t* start;       // [nb] first sorted position of each bucket
+  uint32_t* start;       // [nb + 1] first sorted position of each bucket; start[nb] = n
   uint32_t* cursor;      // [nb] positions handed out so far per bucket
   int2* items;           // [<= n / kTilePoints + nb] (bucket, part) per decode item
   int32_t* n_items;      // number of items
   int32_t nb;            // buckets (<= kMaxBuckets)
-  // two-level split (nb > kCoarseBuckets): records grouped by coarse bucket
-  // (bucket >> kFineShift) first, then by bucket
-  float4* tmp;           // [n] records in coarse-bucket order, or null (one level)
-  uint32_t* ccursor;     // [kCoarseBuckets * kCursorStride] positions handed out per coarse bucket
+  // two-level split (nb > kOneLevelBuckets): records grouped by coarse key
+  // (bucket >> fine_shift) first, then by bucket
+  int32_t fine_shift;
+  float4* tmp;           // [n] records in coarse order, or null (one level)
+  uint32_t* ccursor;     // [kCoarseBuckets * kCursorStride] positions handed out per coarse key
 };
 
 struct GridArgs {

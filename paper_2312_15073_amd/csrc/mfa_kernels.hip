@@ -502,35 +502,78 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 // Multisplit of the points by bucket = (owning block, tile of 2^sort_shift
 // spans per axis).  The bucket only orders the work; every point is then
 // evaluated by the same exact rules, so the results do not depend on it.
-// Pass 1 counts the buckets of each 8192-point chunk in LDS and adds the
-// counts to the global histogram; a one-workgroup scan gives each bucket's
-// start; a scatter pass recounts each chunk, claims a run per key with one
-// global atomic, and writes its records (x, y, z, input index) into those
-// runs.  With thousands of buckets a chunk has only a few points per
-// bucket, and runs that short reach HBM as partial-line writes; so above
-// kCoarseBuckets buckets the scatter is done twice: by coarse bucket
-// (bucket >> kFineShift, at most 64 keys: runs of ~128 records), then the
-// coarse runs by bucket (a chunk of them spans one or two coarse buckets:
-// again runs of ~128 records).
-constexpr int kSortPer = 32;                   // points per thread
-constexpr int kSortChunk = kBlock * kSortPer;  // points per workgroup
-// points per thread in the passes of the two-level split: chunks of 2048
-// points still write runs of >= 32 records per key, and the smaller
-// chunks keep more workgroups in flight
-constexpr int kSortPer2 = 8;
+// A histogram pass counts the buckets of large chunks in LDS (two 16-bit
+// counters per word) and adds them to the global counts; a one-workgroup
+// scan gives each bucket's start and the list of decode items; scatter
+// passes recount each chunk, claim a run per key with one global atomic,
+// and write the records (x, y, z, input index) into those runs.  With up to
+// kOneLevelBuckets buckets one pass writes runs of tens of records; above,
+// runs per bucket would be a record or two, which HBM takes as partial-line
+// writes, so the points go first to their coarse key (bucket >> fine_shift,
+// at most kCoarseBuckets keys) and then, from those coarse runs, to their
+// buckets: a chunk of the second pass covers one or two coarse keys, so its
+// keys relative to the chunk's first coarse key fit a small LDS table.
+constexpr int kSortPer = 32;                       // points per thread, one-level and coarse passes
+constexpr int kSortChunk = kBlock * kSortPer;      // points per workgroup
+constexpr int kFinePer = 8;                        // records per thread, fine pass
+constexpr int kFineKeys = 2048;                    // LDS keys of a fine-pass chunk
+constexpr int kHistThreads = 1024;                 // histogram workgroup
+constexpr int kHistPer = 63;                       // points per thread: at most 65535 per chunk
+constexpr int kHistChunk = kHistThreads * kHistPer;
+constexpr int kScanThreads = 1024;
 
+// Sort tables of a multi-block model in LDS: block edges, then one SortBlk
+// per block; null pointers when the model exceeds the LDS budget (then the
+// global copies are read).
+struct SortTabs {
+  const SortBlk* blk;
+  const double* edges;
+};
+
+// LDS bytes of the staged sort tables (0: not staged); the launchers add
+// them to the dynamic LDS of the sort kernels.
+template <bool MULTI>
+__host__ __device__ inline size_t sort_tabs_bytes(const DevModel& m) {
+  if (!MULTI) return 0;
+  return m.nblocks <= kSortBlkLds && m.n_edges <= kSortEdgesLds
+             ? (size_t)m.nblocks * sizeof(SortBlk) + (size_t)m.n_edges * 8
+             : 0;
+}
+
+template <bool MULTI>
+__device__ __forceinline__ SortTabs stage_sort_tabs(const DevModel& m, float4* lds) {
+  SortTabs t{m.sblk, m.edges};
+  if constexpr (MULTI) {
+    if (sort_tabs_bytes<MULTI>(m) != 0) {
+      SortBlk* lb = reinterpret_cast<SortBlk*>(lds);
+      double* le = reinterpret_cast<double*>(lb + m.nblocks);
+      for (int q = threadIdx.x; q < m.nblocks * 4; q += blockDim.x)
+        reinterpret_cast<float4*>(lb)[q] = reinterpret_cast<const float4*>(m.sblk)[q];
+      for (int q = threadIdx.x; q < m.n_edges; q += blockDim.x) le[q] = m.edges[q];
+      t.blk = lb;
+      t.edges = le;
+    }
+    __syncthreads();
+  }
+  return t;
+}
+
+// Bucket of a point: the exact owning block (the block-owner rule, as in
+// probe()) and, per axis, the tile of the span guess (the exact span or,
+// within rounding of a knot, a neighbour).
 template <bool MULTI, bool GT>
-__device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double (&x)[3]) {
-  const DevBlock* __restrict__ B = &m.b0;
-  int block = 0;
-  double u[3];
+__device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTabs& tb,
+                                                const double (&x)[3]) {
+  const int sh = m.sort_shift;
+  int t[3], td[3];
+  uint32_t off;
   if constexpr (MULTI) {
     int b[3];
     double xc[3], e0[3], e1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double* E = m.edges + m.edge_off[a];
-      xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
+      const double* E = tb.edges + m.edge_off[a];
+      xc[a] = clampd(x[a], m.box_lo[a], m.box_hi[a]);
       b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
       e0[a] = E[b[a]];
       e1[a] = E[b[a] + 1];
@@ -540,27 +583,29 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const double 
     for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
     if (!ok) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) fix_owner(m.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
+      for (int a = 0; a < 3; ++a) fix_owner(tb.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
     }
-    block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
-    B = m.blocks + block;
+    const SortBlk& B = tb.blk[(b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
+    for (int a = 0; a < 3; ++a) {
+      const double u = param_of(xc[a], B.lo[a], B.inv_ext[a]);
+      const int nsp = B.nsp[a];
+      t[a] = guess_span(nsp, u) >> sh;
+      td[a] = (nsp + (1 << sh) - 1) >> sh;
+    }
+    off = (uint32_t)B.tile_off;
   } else {
+    const DevBlock* __restrict__ B = &m.b0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+    for (int a = 0; a < 3; ++a) {
+      const double u = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+      const int nsp = B->nsp[a];
+      t[a] = guess_span<GT>(m, B, 0, a, u) >> sh;
+      td[a] = (nsp + (1 << sh) - 1) >> sh;
+    }
+    off = 0;
   }
-  const int sh = m.sort_shift;
-  int t[3], td[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int nsp = B->nsp[a];
-    const int j = guess_span<GT>(m, B, block, a, u[a]);  // the exact span or the one before
-    t[a] = j >> sh;
-    td[a] = (nsp + (1 << sh) - 1) >> sh;
-  }
-  return (uint32_t)(B->tile_off + (t[0] * td[1] + t[1]) * td[2] + t[2]);
+  return off + (uint32_t)((t[0] * td[1] + t[1]) * td[2] + t[2]);
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, int64_t n) {
@@ -568,26 +613,38 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
   if (i < n) p[i] = 0u;
 }
 
+// Bucket counts of one chunk of kHistChunk points (< 65536, so a 16-bit
+// counter cannot overflow): two counters per LDS word (bucket b in the
+// half b & 1 of word b >> 1).  Dynamic LDS: the sort tables, then the
+// counters.
 template <bool MULTI, bool GT>
-__global__ __launch_bounds__(kBlock) void sort_hist_k(DevModel m, SortArgs sa) {
-  __shared__ uint32_t h[kMaxBuckets];
-  for (int b = threadIdx.x; b < sa.nb; b += kBlock) h[b] = 0u;
+__global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs sa) {
+  extern __shared__ float4 sdyn[];
+  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
+  uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(sdyn) + sort_tabs_bytes<MULTI>(m));
+  const int nw = (sa.nb + 1) >> 1;
+  for (int w = threadIdx.x; w < nw; w += kHistThreads) h[w] = 0u;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kSortChunk;
-  for (int q = 0; q < kSortPer; ++q) {
-    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kHistChunk;
+  for (int q = 0; q < kHistPer; ++q) {
+    const int64_t i = c0 + (int64_t)q * kHistThreads + threadIdx.x;
     if (i < sa.n) {
       const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
-      atomicAdd(h + sort_bucket<MULTI, GT>(m, x), 1u);
+      const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
+      atomicAdd(h + (b >> 1), 1u << ((b & 1u) * 16u));
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < sa.nb; b += kBlock)
-    if (h[b]) atomicAdd(sa.hist + b, h[b]);
+  for (int w = threadIdx.x; w < nw; w += kHistThreads) {
+    const uint32_t v = h[w];
+    if (v & 0xFFFFu) atomicAdd(sa.hist + 2 * w, v & 0xFFFFu);
+    if (v >> 16) atomicAdd(sa.hist + 2 * w + 1, v >> 16);
+  }
 }
 
-// Exclusive scan over the workgroup of one value per thread; returns the
-// thread's exclusive prefix, the total in *tot.  wsum: kBlock / kWave words.
+// Exclusive scan over the workgroup of one value per thread (kScanThreads
+// threads); returns the thread's exclusive prefix, the total in *tot.
+// wsum: kScanThreads / kWave words.
 __device__ __forceinline__ uint32_t block_scan(uint32_t s, uint32_t* wsum, uint32_t* tot) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   uint32_t inc = s;
@@ -600,7 +657,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t s, uint32_t* wsum, uint3
   if (lane == kWave - 1) wsum[wave] = inc;
   __syncthreads();
   uint32_t run = inc - s, all = 0;
-  for (int w = 0; w < kBlock / kWave; ++w) {
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
     if (w < wave) run += wsum[w];
     all += wsum[w];
   }
@@ -608,19 +665,22 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t s, uint32_t* wsum, uint3
   return run;
 }
 
-// One workgroup: exclusive scan of the bucket counts, reset of the cursors,
-// and the list of decode items (bucket, part), ceil(count / kTilePoints)
-// parts per bucket in bucket order.
-__global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
-  __shared__ uint32_t wsum[kBlock / kWave];
-  constexpr int kPer = kMaxBuckets / kBlock;
+// Decode parts of a bucket of c points: ceil(c / kTilePoints).
+__device__ __forceinline__ uint32_t n_parts(uint32_t c) { return (c + kTilePoints - 1) / kTilePoints; }
+
+// One workgroup: exclusive scan of the bucket counts (start[nb] = n), reset
+// of the cursors, and the list of decode items (bucket, part) in bucket
+// order.
+__global__ __launch_bounds__(kScanThreads) void sort_scan_k(SortArgs sa) {
+  __shared__ uint32_t wsum[kScanThreads / kWave];
+  constexpr int kPer = kMaxBuckets / kScanThreads;
   uint32_t v[kPer], s = 0, parts = 0, tot;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int b = threadIdx.x * kPer + q;
     v[q] = b < sa.nb ? sa.hist[b] : 0u;
     s += v[q];
-    parts += (v[q] + kTilePoints - 1) / kTilePoints;
+    parts += n_parts(v[q]);
   }
   uint32_t run = block_scan(s, wsum, &tot);
   uint32_t irun = block_scan(parts, wsum, &tot);
@@ -630,18 +690,21 @@ __global__ __launch_bounds__(kBlock) void sort_scan_k(SortArgs sa) {
     if (b < sa.nb) {
       sa.start[b] = run;
       sa.cursor[b] = 0u;
-      const uint32_t np = (v[q] + kTilePoints - 1) / kTilePoints;
+      const uint32_t np = n_parts(v[q]);
       for (uint32_t u = 0; u < np; ++u) sa.items[irun + u] = make_int2(b, (int)u);
       irun += np;
     }
     run += v[q];
   }
-  if (threadIdx.x == 0) *sa.n_items = (int32_t)tot;
+  if (threadIdx.x == 0) {
+    *sa.n_items = (int32_t)tot;
+    sa.start[sa.nb] = (uint32_t)sa.n;
+  }
   if (sa.tmp && threadIdx.x < kCoarseBuckets) sa.ccursor[threadIdx.x * kCursorStride] = 0u;
 }
 
-// Point q of a chunk (q = 0..kSortPer-1) of the pass input: the points in
-// input order, or (FROM_TMP) the records of the coarse pass.
+// Record i of the pass input: the points in input order, or (FROM_TMP) the
+// records of the coarse pass.
 template <bool FROM_TMP>
 __device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
   if constexpr (FROM_TMP)
@@ -650,50 +713,86 @@ __device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
     return make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i], __uint_as_float((uint32_t)i));
 }
 
-// Scatter pass of the multisplit over one chunk: ranks within the chunk
-// from LDS counters, one run claimed per key and chunk with one global
-// atomic, records written to run start + rank.  COARSE: key = bucket >>
-// kFineShift (the coarse pass, runs from sa.ccursor, records to sa.tmp);
-// otherwise key = bucket (runs from sa.cursor, records to sa.rec).
-template <bool MULTI, bool COARSE, bool FROM_TMP, int PER, bool GT>
+// Scatter pass over one chunk of kBlock * PER records: ranks within the
+// chunk from LDS counters, one run claimed per key and chunk with one global
+// atomic, records written to run start + rank.
+//  kOne:    key = bucket, input order, runs from sa.cursor into sa.rec;
+//  kCoarse: key = bucket >> fine_shift, input order, runs from sa.ccursor
+//           into sa.tmp;
+//  kFine:   key = bucket, from sa.tmp (coarse order), runs from sa.cursor
+//           into sa.rec; the LDS counters cover the keys from the first
+//           coarse key of the chunk on (kFineKeys of them, at least two
+//           coarse keys); a record beyond them claims its slot with its own
+//           global atomic (chunks that span several small coarse runs only).
+constexpr int kOne = 0, kCoarse = 1, kFine = 2;
+
+template <bool MULTI, int MODE, int PER, bool GT>
 __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
-  constexpr int kKeys = COARSE ? kCoarseBuckets : kMaxBuckets;
+  constexpr int kKeys = MODE == kCoarse ? kCoarseBuckets : (MODE == kOne ? kOneLevelBuckets : kFineKeys);
   __shared__ uint32_t h[kKeys];
   __shared__ uint32_t base[kKeys];
-  const int nk = COARSE ? ((sa.nb + (1 << kFineShift) - 1) >> kFineShift) : sa.nb;
+  __shared__ uint32_t s_key0;
+  extern __shared__ float4 sdyn[];
+  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
+  const int64_t c0 = (int64_t)blockIdx.x * (kBlock * PER);
+  if (c0 >= sa.n) return;                                  // whole workgroup
+  uint32_t key0 = 0;
+  if constexpr (MODE == kFine) {
+    if (threadIdx.x == 0) {
+      const float4 r = sa.tmp[c0];
+      const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+      s_key0 = (sort_bucket<MULTI, GT>(m, tb, x) >> sa.fine_shift) << sa.fine_shift;
+    }
+  }
+  const int nk = MODE == kCoarse ? ((sa.nb + (1 << sa.fine_shift) - 1) >> sa.fine_shift)
+                                 : (MODE == kOne ? sa.nb : kFineKeys);
   for (int b = threadIdx.x; b < nk; b += kBlock) h[b] = 0u;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * (kBlock * PER);
+  if constexpr (MODE == kFine) key0 = s_key0;
   uint32_t key[PER], rank[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
     key[q] = 0xFFFFFFFFu;
     if (i < sa.n) {
-      const float4 r = sort_input<FROM_TMP>(sa, i);
+      const float4 r = sort_input<MODE == kFine>(sa, i);
       const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
-      const uint32_t b = sort_bucket<MULTI, GT>(m, x);
-      key[q] = COARSE ? b >> kFineShift : b;
-      rank[q] = atomicAdd(h + key[q], 1u);
+      const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
+      if constexpr (MODE == kCoarse) {
+        key[q] = b >> sa.fine_shift;
+        rank[q] = atomicAdd(h + key[q], 1u);
+      } else if constexpr (MODE == kOne) {
+        key[q] = b;
+        rank[q] = atomicAdd(h + key[q], 1u);
+      } else {
+        const uint32_t k = b - key0;              // b >= key0: coarse runs are in key order
+        if (k < (uint32_t)kFineKeys) {
+          key[q] = k;
+          rank[q] = atomicAdd(h + k, 1u);
+        } else {
+          key[q] = 0xFFFFFFFEu;                   // beyond the table: own slot
+          rank[q] = sa.start[b] + atomicAdd(sa.cursor + b, 1u);
+        }
+      }
     }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nk; b += kBlock)
     if (h[b]) {
-      if constexpr (COARSE)
-        base[b] = sa.start[b << kFineShift] + atomicAdd(sa.ccursor + b * kCursorStride, h[b]);
+      if constexpr (MODE == kCoarse)
+        base[b] = sa.start[b << sa.fine_shift] + atomicAdd(sa.ccursor + b * kCursorStride, h[b]);
       else
-        base[b] = sa.start[b] + atomicAdd(sa.cursor + b, h[b]);
+        base[b] = sa.start[key0 + b] + atomicAdd(sa.cursor + key0 + b, h[b]);
     }
   __syncthreads();
-  float4* dst = COARSE ? sa.tmp : sa.rec;
+  float4* dst = MODE == kCoarse ? sa.tmp : sa.rec;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
     if (key[q] == 0xFFFFFFFFu) continue;
-    const uint32_t pos = base[key[q]] + rank[q];
+    const uint32_t pos = key[q] == 0xFFFFFFFEu ? rank[q] : base[key[q]] + rank[q];
     if ((int64_t)pos >= sa.n) continue;        // cannot happen when the counts are consistent
-    dst[pos] = sort_input<FROM_TMP>(sa, i);
+    dst[pos] = sort_input<MODE == kFine>(sa, i);
   }
 }
 
@@ -730,13 +829,38 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
   return make_float4(f, fx * L.ds[0], fy * L.ds[1], fz * L.ds[2]);
 }
 
-// Decode in sorted order, one item (up to kTilePoints points of one bucket)
-// per workgroup; results go to the input positions.  The bucket's window of
-// control points is staged in LDS once (when it holds at most win_cap
-// values); a point whose exact spans fall outside the window (possible only
-// for non-uniform knots) reads its rows from global memory.  Both paths sum
-// in the same order.  LDSREC: the span records and basis tables of a
-// single-block model are staged too, ahead of the window.
+// A point of a known block B (the sort placed it in one of B's buckets by
+// the block-owner rule, the one probe() applies): the parameter map and the
+// span guesses with their records, as probe() computes them for B.
+template <bool GT>
+__device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* __restrict__ R,
+                                             const double (&x)[3], const DevBlock* __restrict__ B,
+                                             int block) {
+  Probe q;
+  q.B = B;
+  q.block = block;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.b[a] = 0;
+    q.u[a] = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), B->lo[a], B->inv_ext[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.j[a] = guess_span<GT>(m, B, block, a, q.u[a]);
+    q.rec[a] = R[B->rec_off[a] + q.j[a]];
+  }
+  return q;
+}
+
+// Decode in sorted order, one item (a bucket, or an equal part of a bucket
+// of more than kTilePoints points) per workgroup; results go to the input
+// positions.  The bucket's window of control points (the tile's spans plus
+// p per axis) is staged in LDS once (when it holds at most win_cap values);
+// a point whose exact spans fall outside the window reads its rows from
+// global memory.  Both paths sum in the same order.  LDSREC: the span
+// records and basis tables of a single-block model are staged too, ahead of
+// the window.  Multi-block models: every point of the bucket lies in the
+// bucket's block, whose record the workgroup reads as uniform data.
 template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false, bool G = true>
 __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
                                                          float* __restrict__ out,
@@ -760,18 +884,18 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   }
   const int2 it = sa.items[item];
   const int b = it.x;
-  const uint32_t end = b + 1 < sa.nb ? sa.start[b + 1] : (uint32_t)sa.n;
-  const uint32_t s0 = sa.start[b] + (uint32_t)it.y * (uint32_t)kTilePoints;
-  const uint32_t s1 = min(s0 + (uint32_t)kTilePoints, end);
+  const uint32_t b0 = sa.start[b], cnt = sa.start[b + 1] - b0, np = n_parts(cnt);
+  const uint32_t s0 = b0 + (uint32_t)(((uint64_t)cnt * (uint32_t)it.y) / np);
+  const uint32_t s1 = b0 + (uint32_t)(((uint64_t)cnt * (uint32_t)(it.y + 1)) / np);
   const BucketWin bw = m.bwin[b];
   const int w12 = bw.w[1] * bw.w[2];
   const int wn = bw.w[0] * w12;
   const bool staged = wn <= win_cap;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const DevBlock* __restrict__ B = MULTI ? m.blocks + bw.block : &m.b0;
   if (staged) {
     // lanes cover rpi whole rows of the window per pass (k = lane % w2);
     // the row index (i, j) of each lane advances without divisions
-    const DevBlock* __restrict__ B = MULTI ? m.blocks + bw.block : &m.b0;
     const uint32_t n1 = (uint32_t)B->n[1], rs1 = (uint32_t)B->rs1;
     const int w1 = bw.w[1], w2 = bw.w[2], rows = bw.w[0] * w1;
     if (w2 <= kWave) {
@@ -812,12 +936,18 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   for (; t < s1; t += kBlock) {
     const float4 qn = sa.rec[min(t + kBlock, s1 - 1)];   // next record in flight
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
-    const Loc L = locate<P, MULTI, GT>(m, R, x);
+    Loc L;
+    if constexpr (MULTI) {
+      Probe pr = probe_block<GT>(m, R, x, B, bw.block);
+      L = finish(m, R, pr);
+    } else {
+      L = locate<P, false, GT>(m, R, x);
+    }
     const uint32_t i = __float_as_uint(q.w);
     q = qn;
     if ((int64_t)i >= sa.n) continue;
     int d[3];
-    bool in = staged && L.block == bw.block;
+    bool in = staged;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       d[a] = L.j[a] - bw.o[a];
@@ -1914,18 +2044,22 @@ static hipError_t points_p(const DevModel& m, int kind, bool grad, const float* 
 
 // Histogram, scan and scatter of the (block, tile) sort.
 template <bool MULTI, bool GT>
-static void sort_launch(const DevModel& m, const SortArgs& sa, unsigned gc, hipStream_t st) {
-  hipLaunchKernelGGL((sort_hist_k<MULTI, GT>), dim3(gc), dim3(kBlock), 0, st, m, sa);
-  hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kBlock), 0, st, sa);
+static void sort_launch(const DevModel& m, const SortArgs& sa, hipStream_t st) {
+  const size_t tabs = sort_tabs_bytes<MULTI>(m);
+  const unsigned gh = (unsigned)((sa.n + kHistChunk - 1) / kHistChunk);
+  const size_t hist_lds = tabs + (size_t)((sa.nb + 1) / 2) * 4;
+  hipLaunchKernelGGL((sort_hist_k<MULTI, GT>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
+  hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kScanThreads), 0, st, sa);
+  const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
   if (sa.tmp) {                        // two levels: coarse runs, then buckets
-    const unsigned g2 = (unsigned)((sa.n + kBlock * kSortPer2 - 1) / (kBlock * kSortPer2));
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, true, false, kSortPer2, GT>), dim3(g2), dim3(kBlock), 0,
-                       st, m, sa);
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, false, true, kSortPer2, GT>), dim3(g2), dim3(kBlock), 0,
-                       st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, kSortPer, GT>), dim3(gc), dim3(kBlock), tabs, st,
+                       m, sa);
+    const unsigned gf = (unsigned)((sa.n + kBlock * kFinePer - 1) / (kBlock * kFinePer));
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, kFinePer, GT>), dim3(gf), dim3(kBlock), tabs, st,
+                       m, sa);
   } else {
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, false, false, kSortPer, GT>), dim3(gc), dim3(kBlock), 0,
-                       st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kOne, kSortPer, GT>), dim3(gc), dim3(kBlock), tabs, st,
+                       m, sa);
   }
 }
 
@@ -1966,15 +2100,14 @@ template <int P, Storage S>
 static hipError_t sorted_p(const DevModel& m, int kind, bool grad, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
   const bool multi = kind == kKindMulti;
-  const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
   const unsigned gb = (unsigned)((sa.nb + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(fill_u32_k, dim3(gb), dim3(kBlock), 0, st, sa.hist, (int64_t)sa.nb);
   if (multi)
-    sort_launch<true, false>(m, sa, gc, st);
+    sort_launch<true, false>(m, sa, st);
   else if (kind == kKindGraded)
-    sort_launch<false, true>(m, sa, gc, st);
+    sort_launch<false, true>(m, sa, st);
   else
-    sort_launch<false, false>(m, sa, gc, st);
+    sort_launch<false, false>(m, sa, st);
   if (grad)
     decode_sorted_g<P, S, true>(m, kind, sa, out, dbg, st);
   else

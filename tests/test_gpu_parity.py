@@ -511,8 +511,7 @@ def test_sorted_decode_single_block(mfa, dev, c1, storage):
 
 
 def test_sorted_decode_few_buckets(mfa, dev):
-    # 2 x 3 x 4 spans: few enough buckets for the one-level split (the models
-    # above take the two-level one).
+    # 2 x 3 x 4 spans: the whole model is one bucket (its window fits the LDS).
     rng = np.random.default_rng(31)
     P = rng.standard_normal((5, 6, 7))
     model = synth.single_block_model(P, [3] * 3)
@@ -561,6 +560,19 @@ def test_sorted_decode_c2_1e7(mfa, dev, c2):
     pts = synth.random_points(10_000_000, seed=12)
     announce("sorted decode c2 1e7")
     _sorted_matches_unsorted(mfa, dev, c2, pts)
+
+
+@pytest.mark.parametrize("n", [1, 777, 5000, 300001])
+def test_sorted_decode_c4_small_inputs(mfa, dev, c4, n):
+    """Few points over the 8x8x8-block model's ~18k buckets: the coarse runs
+    are short, so chunks of the second scatter pass span many coarse keys
+    and records beyond the chunk's key table claim their slots one by one."""
+    pts = synth.random_points(n, seed=200 + n, lo=(-0.02,) * 3, hi=(1.02,) * 3)
+    announce(f"sorted decode 8x8x8-block model n={n}")
+    out = _sorted_matches_unsorted(mfa, dev, c4, pts)
+    if n <= 5000:
+        ref = oracle_points(c4, pts.T)
+        assert_values_close(out, ref["f"], ref["grad"], max(np.abs(b.ctrl).max() for b in c4.blocks))
 
 
 def test_sorted_decode_c4_2e7(mfa, dev, c4):

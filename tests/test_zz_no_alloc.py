@@ -65,7 +65,7 @@ def test_noalloc_rejects_sizes_beyond_the_static_scratch(dev):
     import torch
     import paper_2312_15073_amd as mfa
     with mfa.Model(synth.model_c2(), "f32") as M:
-        n = 3_000_000                      # 32 bytes per point with 4096 buckets: > 64 MiB
+        n = 5_000_000                      # 16 bytes per point (512 buckets, one level): > 64 MiB
         x = torch.zeros((3, n), dtype=torch.float32, device=dev)
         out = torch.zeros((n, 4), dtype=torch.float32, device=dev)
         st = L.lib().mfa_decode_points_noalloc(M.handle, x.data_ptr(), n, L.MFA_DECODE_SORTED,
