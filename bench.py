@@ -1108,9 +1108,6 @@ def run_serving(args):
     return 0
 
 
-if __name__ == "__main__":
-    sys.exit(main())
-
 
 # ------------------------------------------------------------------ storage-form comparison
 def _image_errors(img, ref):
@@ -1384,3 +1381,7 @@ def run_cr_sweep(args):
                    "parallelism": "single GPU"},
         "cpu_baseline": None}), flush=True)
     return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

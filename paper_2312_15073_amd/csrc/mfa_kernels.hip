@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -513,13 +514,11 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 // at most kCoarseBuckets keys) and then, from those coarse runs, to their
 // buckets: a chunk of the second pass covers one or two coarse keys, so its
 // keys relative to the chunk's first coarse key fit a small LDS table.
-constexpr int kSortPer = 32;                       // points per thread, one-level and coarse passes
-constexpr int kSortChunk = kBlock * kSortPer;      // points per workgroup
-constexpr int kFinePer = 8;                        // records per thread, fine pass
-constexpr int kFineKeys = 2048;                    // LDS keys of a fine-pass chunk
+constexpr int kFineKeys = 1024;                    // LDS keys of a fine-pass chunk
 constexpr int kHistThreads = 1024;                 // histogram workgroup
 constexpr int kHistPer = 63;                       // points per thread: at most 65535 per chunk
 constexpr int kHistChunk = kHistThreads * kHistPer;
+constexpr int kHistIlp = 4;
 constexpr int kScanThreads = 1024;
 
 // Sort tables of a multi-block model in LDS: block edges, then one SortBlk
@@ -626,13 +625,22 @@ __global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs
   for (int w = threadIdx.x; w < nw; w += kHistThreads) h[w] = 0u;
   __syncthreads();
   const int64_t c0 = (int64_t)blockIdx.x * kHistChunk;
-  for (int q = 0; q < kHistPer; ++q) {
-    const int64_t i = c0 + (int64_t)q * kHistThreads + threadIdx.x;
-    if (i < sa.n) {
-      const double x[3] = {(double)sa.xyz[i], (double)sa.xyz[sa.n + i], (double)sa.xyz[2 * sa.n + i]};
-      const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
-      atomicAdd(h + (b >> 1), 1u << ((b & 1u) * 16u));
+  // kHistIlp independent points per step keep several bucket computations
+  // (chains of dependent LDS loads) in flight per thread
+  for (int q = 0; q < kHistPer; q += kHistIlp) {
+    uint32_t b[kHistIlp];
+    bool v[kHistIlp];
+#pragma unroll
+    for (int u = 0; u < kHistIlp; ++u) {
+      const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
+      v[u] = q + u < kHistPer && i < sa.n;
+      const int64_t ic = v[u] ? i : 0;
+      const double x[3] = {(double)sa.xyz[ic], (double)sa.xyz[sa.n + ic], (double)sa.xyz[2 * sa.n + ic]};
+      b[u] = sort_bucket<MULTI, GT>(m, tb, x);
     }
+#pragma unroll
+    for (int u = 0; u < kHistIlp; ++u)
+      if (v[u]) atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nw; w += kHistThreads) {
@@ -713,50 +721,86 @@ __device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
     return make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i], __uint_as_float((uint32_t)i));
 }
 
-// Scatter pass over one chunk of kBlock * PER records: ranks within the
-// chunk from LDS counters, one run claimed per key and chunk with one global
-// atomic, records written to run start + rank.
+// Exclusive scan over n <= 4 * kBlock LDS counters by the workgroup (kBlock
+// threads): v[k] becomes the sum of v[0..k-1], *total the sum of all.
+// wsum: kBlock / kWave words.
+__device__ __forceinline__ void lds_scan(uint32_t* v, int n, uint32_t* wsum, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int k0 = threadIdx.x * 4;
+  uint32_t a[4], s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    a[q] = k0 + q < n ? v[k0 + q] : 0u;
+    s += a[q];
+  }
+  uint32_t inc = s;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t o = __shfl_up(inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == kWave - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t run = inc - s;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  if (threadIdx.x == kBlock - 1) *total = run + s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (k0 + q < n) v[k0 + q] = run;
+    run += a[q];
+  }
+  __syncthreads();
+}
+
+// Scatter pass over one chunk of kScatterChunk records.  Each record's key
+// and rank within the chunk come from LDS counters; the chunk is then
+// ordered by key in LDS and written out by consecutive threads to
+// consecutive positions of each key's run (one run per key and chunk,
+// claimed with one global atomic), so the writes reach memory as whole
+// lines.
 //  kOne:    key = bucket, input order, runs from sa.cursor into sa.rec;
 //  kCoarse: key = bucket >> fine_shift, input order, runs from sa.ccursor
 //           into sa.tmp;
 //  kFine:   key = bucket, from sa.tmp (coarse order), runs from sa.cursor
-//           into sa.rec; the LDS counters cover the keys from the first
-//           coarse key of the chunk on (kFineKeys of them, at least two
-//           coarse keys); a record beyond them claims its slot with its own
-//           global atomic (chunks that span several small coarse runs only).
+//           into sa.rec; the LDS counters cover kFineKeys keys from the
+//           first coarse key of the chunk on (at least two coarse keys); a
+//           record beyond them claims its slot with its own global atomic
+//           and is written directly (chunks spanning several short coarse
+//           runs only).
 constexpr int kOne = 0, kCoarse = 1, kFine = 2;
+constexpr int kScatterPer = 8;
+constexpr int kScatterChunk = kBlock * kScatterPer;
 
-template <bool MULTI, int MODE, int PER, bool GT>
-__global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
-  constexpr int kKeys = MODE == kCoarse ? kCoarseBuckets : (MODE == kOne ? kOneLevelBuckets : kFineKeys);
-  __shared__ uint32_t h[kKeys];
-  __shared__ uint32_t base[kKeys];
-  __shared__ uint32_t s_key0;
-  extern __shared__ float4 sdyn[];
-  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
-  const int64_t c0 = (int64_t)blockIdx.x * (kBlock * PER);
-  if (c0 >= sa.n) return;                                  // whole workgroup
-  uint32_t key0 = 0;
+// One chunk of the scatter pass (see sort_scatter_k).
+template <bool MULTI, int MODE, bool GT, int kKeys>
+__device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs& sa, const SortTabs& tb,
+                                              int64_t c0, uint32_t* h, uint32_t* gbase, float4* recs,
+                                              uint16_t* keyof, uint32_t* wsum, uint32_t* s_key0,
+                                              uint32_t* s_staged) {
+  constexpr int PER = kScatterPer;
+  const int cn = (int)min((int64_t)kScatterChunk, sa.n - c0);
   if constexpr (MODE == kFine) {
     if (threadIdx.x == 0) {
       const float4 r = sa.tmp[c0];
       const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
-      s_key0 = (sort_bucket<MULTI, GT>(m, tb, x) >> sa.fine_shift) << sa.fine_shift;
+      *s_key0 = (sort_bucket<MULTI, GT>(m, tb, x) >> sa.fine_shift) << sa.fine_shift;
     }
   }
   const int nk = MODE == kCoarse ? ((sa.nb + (1 << sa.fine_shift) - 1) >> sa.fine_shift)
                                  : (MODE == kOne ? sa.nb : kFineKeys);
   for (int b = threadIdx.x; b < nk; b += kBlock) h[b] = 0u;
   __syncthreads();
-  if constexpr (MODE == kFine) key0 = s_key0;
+  uint32_t key0 = 0;
+  if constexpr (MODE == kFine) key0 = *s_key0;
+  float4 rec[PER];
   uint32_t key[PER], rank[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
+    const int l = q * kBlock + threadIdx.x;
     key[q] = 0xFFFFFFFFu;
-    if (i < sa.n) {
-      const float4 r = sort_input<MODE == kFine>(sa, i);
-      const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+    if (l < cn) {
+      rec[q] = sort_input<MODE == kFine>(sa, c0 + l);
+      const double x[3] = {(double)rec[q].x, (double)rec[q].y, (double)rec[q].z};
       const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
       if constexpr (MODE == kCoarse) {
         key[q] = b >> sa.fine_shift;
@@ -769,31 +813,59 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
         if (k < (uint32_t)kFineKeys) {
           key[q] = k;
           rank[q] = atomicAdd(h + k, 1u);
-        } else {
-          key[q] = 0xFFFFFFFEu;                   // beyond the table: own slot
-          rank[q] = sa.start[b] + atomicAdd(sa.cursor + b, 1u);
+        } else {                                  // beyond the table: own slot, written now
+          key[q] = 0xFFFFFFFEu;
+          const uint32_t pos = sa.start[b] + atomicAdd(sa.cursor + b, 1u);
+          if ((int64_t)pos < sa.n) sa.rec[pos] = rec[q];
         }
       }
     }
   }
   __syncthreads();
+  // one run per key and chunk
   for (int b = threadIdx.x; b < nk; b += kBlock)
     if (h[b]) {
       if constexpr (MODE == kCoarse)
-        base[b] = sa.start[b << sa.fine_shift] + atomicAdd(sa.ccursor + b * kCursorStride, h[b]);
+        gbase[b] = sa.start[b << sa.fine_shift] + atomicAdd(sa.ccursor + b * kCursorStride, h[b]);
       else
-        base[b] = sa.start[key0 + b] + atomicAdd(sa.cursor + key0 + b, h[b]);
+        gbase[b] = sa.start[key0 + b] + atomicAdd(sa.cursor + key0 + b, h[b]);
     }
-  __syncthreads();
-  float4* dst = MODE == kCoarse ? sa.tmp : sa.rec;
+  lds_scan(h, nk, wsum, s_staged);             // h: chunk-local start of each key
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int64_t i = c0 + (int64_t)q * kBlock + threadIdx.x;
-    if (key[q] == 0xFFFFFFFFu) continue;
-    const uint32_t pos = key[q] == 0xFFFFFFFEu ? rank[q] : base[key[q]] + rank[q];
-    if ((int64_t)pos >= sa.n) continue;        // cannot happen when the counts are consistent
-    dst[pos] = sort_input<MODE == kFine>(sa, i);
+    if (key[q] >= 0xFFFFFFFEu) continue;
+    const uint32_t sl = h[key[q]] + rank[q];
+    recs[sl] = rec[q];
+    keyof[sl] = (uint16_t)key[q];
   }
+  __syncthreads();
+  float4* dst = MODE == kCoarse ? sa.tmp : sa.rec;
+  const int staged = (int)*s_staged;          // cn less the records written directly
+  for (int sl = threadIdx.x; sl < staged; sl += kBlock) {
+    const uint32_t k = keyof[sl];
+    const uint32_t pos = gbase[k] + ((uint32_t)sl - h[k]);
+    if ((int64_t)pos < sa.n) dst[pos] = recs[sl];
+  }
+  __syncthreads();                             // LDS reused by the next chunk
+}
+
+// The workgroups loop over the chunks (grid-stride), so the sort tables
+// are staged once per workgroup rather than once per chunk.
+template <bool MULTI, int MODE, bool GT>
+__global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
+  constexpr int kKeys = MODE == kCoarse ? kCoarseBuckets : (MODE == kOne ? kOneLevelBuckets : kFineKeys);
+  static_assert(kKeys <= 4 * kBlock, "lds_scan covers 4 keys per thread");
+  __shared__ uint32_t h[kKeys];          // counts, then the chunk-local start of each key
+  __shared__ uint32_t gbase[kKeys];      // global start of each key's run
+  __shared__ float4 recs[kScatterChunk]; // the chunk in key order
+  __shared__ uint16_t keyof[kScatterChunk];
+  __shared__ uint32_t wsum[kBlock / kWave];
+  __shared__ uint32_t s_key0, s_staged;
+  extern __shared__ float4 sdyn[];
+  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
+  for (int64_t c0 = (int64_t)blockIdx.x * kScatterChunk; c0 < sa.n;
+       c0 += (int64_t)gridDim.x * kScatterChunk)
+    scatter_chunk<MULTI, MODE, GT, kKeys>(m, sa, tb, c0, h, gbase, recs, keyof, wsum, &s_key0, &s_staged);
 }
 
 // One stored control point, converted to FP32 as the row loaders do.
@@ -831,11 +903,14 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
 
 // A point of a known block B (the sort placed it in one of B's buckets by
 // the block-owner rule, the one probe() applies): the parameter map and the
-// span guesses with their records, as probe() computes them for B.
+// span guesses with their records, as probe() computes them for B.  TR:
+// the records of the tile's spans o[a] .. o[a] + ns[a] - 1 per axis (axis a
+// from toff[a] on), or null; a guess outside them reads R.
 template <bool GT>
 __device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* __restrict__ R,
                                              const double (&x)[3], const DevBlock* __restrict__ B,
-                                             int block) {
+                                             int block, const SpanRec* TR, const int (&o)[3],
+                                             const int (&ns)[3], const int (&toff)[3]) {
   Probe q;
   q.B = B;
   q.block = block;
@@ -847,9 +922,29 @@ __device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* _
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     q.j[a] = guess_span<GT>(m, B, block, a, q.u[a]);
-    q.rec[a] = R[B->rec_off[a] + q.j[a]];
+    const int jj = q.j[a] - o[a];
+    if (TR != nullptr && jj >= 0 && jj < ns[a])
+      q.rec[a] = TR[toff[a] + jj];
+    else
+      q.rec[a] = R[B->rec_off[a] + q.j[a]];
   }
   return q;
+}
+
+constexpr int kTileRecs = 96;      // span records of a tile staged for multi-block decodes
+
+// Basis tables of the model in LDS when they hold at most kMatsLds floats
+// (clamped uniform knots share a few span shapes); else the global pool.
+// The caller synchronises before the first use (both kernels that stage
+// them do for their own LDS staging).
+constexpr int kMatsLds = 1024;
+
+__device__ __forceinline__ const float* stage_mats(const DevModel& m, float4* lds) {
+  const int nf = m.n_mats * m.mat_stride;
+  if (nf > kMatsLds) return m.mats;
+  for (int q = threadIdx.x; q < nf / 4; q += kBlock)
+    lds[q] = reinterpret_cast<const float4*>(m.mats)[q];
+  return reinterpret_cast<const float*>(lds);
 }
 
 // Decode in sorted order, one item (a bucket, or an equal part of a bucket
@@ -866,6 +961,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
                                                          float* __restrict__ out,
                                                          int32_t* __restrict__ dbg) {
   extern __shared__ float4 dyn[];
+  __shared__ float4 lmats[LDSREC ? 1 : kMatsLds / 4];
   const int item = blockIdx.x;
   if (item >= *sa.n_items) return;                 // whole workgroup
   const SpanRec* R = m.rec;
@@ -881,18 +977,40 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     R = lr;
     MT = lm;
     W = lm + m.n_mats * m.mat_stride;
+  } else {
+    MT = stage_mats(m, lmats);
   }
   const int2 it = sa.items[item];
   const int b = it.x;
-  const uint32_t b0 = sa.start[b], cnt = sa.start[b + 1] - b0, np = n_parts(cnt);
-  const uint32_t s0 = b0 + (uint32_t)(((uint64_t)cnt * (uint32_t)it.y) / np);
-  const uint32_t s1 = b0 + (uint32_t)(((uint64_t)cnt * (uint32_t)(it.y + 1)) / np);
+  const uint32_t b0 = sa.start[b], bcnt = sa.start[b + 1] - b0, np = n_parts(bcnt);
+  const uint32_t s0 = b0 + (uint32_t)(((uint64_t)bcnt * (uint32_t)it.y) / np);
+  const uint32_t s1 = b0 + (uint32_t)(((uint64_t)bcnt * (uint32_t)(it.y + 1)) / np);
   const BucketWin bw = m.bwin[b];
   const int w12 = bw.w[1] * bw.w[2];
   const int wn = bw.w[0] * w12;
   const bool staged = wn <= win_cap;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
   const DevBlock* __restrict__ B = MULTI ? m.blocks + bw.block : &m.b0;
+  // multi-block models: the span records of the tile, per axis
+  __shared__ SpanRec trec[MULTI ? kTileRecs : 1];
+  int ns[3], toff[3];
+  const SpanRec* TR = nullptr;
+  if constexpr (MULTI) {
+    int tot = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ns[a] = bw.w[a] - P;
+      toff[a] = tot;
+      tot += ns[a];
+    }
+    if (tot <= kTileRecs) {
+      for (int q = threadIdx.x; q < tot; q += kBlock) {
+        const int a = q < toff[1] ? 0 : (q < toff[2] ? 1 : 2);
+        trec[q] = m.rec[B->rec_off[a] + bw.o[a] + (q - toff[a])];
+      }
+      TR = trec;
+    }
+  }
   if (staged) {
     // lanes cover rpi whole rows of the window per pass (k = lane % w2);
     // the row index (i, j) of each lane advances without divisions
@@ -929,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
       }
     }
   }
-  __syncthreads();
+  __syncthreads();                 // window and tile records staged
   if (s0 >= s1) return;
   uint32_t t = s0 + threadIdx.x;
   float4 q = sa.rec[min(t, s1 - 1)];
@@ -938,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
     Loc L;
     if constexpr (MULTI) {
-      Probe pr = probe_block<GT>(m, R, x, B, bw.block);
+      Probe pr = probe_block<GT>(m, R, x, B, bw.block, TR, bw.o, ns, toff);
       L = finish(m, R, pr);
     } else {
       L = locate<P, false, GT>(m, R, x);
@@ -1259,6 +1377,22 @@ __device__ __forceinline__ bool transparent(uint32_t bh, const RenderArgs& r, co
 // the sample's opacity.
 // The colour terms (c_rgb * shade + ks) and the opacity of one sample, which
 // do not depend on what lies in front of it.
+// diff^m by binary exponentiation (squarings, the set bits of m folded in
+// from the lowest); m = 16, the workloads' exponent, is four squarings
+// with the same roundings.
+__device__ __forceinline__ float spec_pow(float d, int m) {
+  if (m == 16) {
+    const float d2 = d * d, d4 = d2 * d2, d8 = d4 * d4;
+    return d8 * d8;
+  }
+  float spec = 1.f, bse = d;
+  for (int ex = m; ex; ex >>= 1) {
+    if (ex & 1) spec *= bse;
+    bse *= bse;
+  }
+  return spec;
+}
+
 __device__ __forceinline__ float4 shade_sample(const float4 e, const float (&L)[3], const float4* tf,
                                                const RenderArgs& r) {
   const float s = tf_coord(e.x, r.vmin, r.inv_range);
@@ -1274,13 +1408,8 @@ __device__ __forceinline__ float4 shade_sample(const float4 e, const float (&L)[
   const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
   const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
   const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
-  float spec = 1.f, bse = diff;
-  for (int ex = r.shininess; ex; ex >>= 1) {
-    if (ex & 1) spec *= bse;
-    bse *= bse;
-  }
   const float shade = fmaf(r.kd, diff, r.ka);
-  const float ks = r.ks * spec;
+  const float ks = r.ks * spec_pow(diff, r.shininess);
   return make_float4(fmaf(cr, shade, ks), fmaf(cg, shade, ks), fmaf(cb, shade, ks), alpha);
 }
 
@@ -1537,29 +1666,42 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
         ev = true;
       }
     }
-    // the group's four samples in ray order
-    const int evm = (int)ev;
-    const float4 q0 = quad_bcast4<0>(q), q1 = quad_bcast4<1>(q), q2 = quad_bcast4<2>(q),
-                 q3 = quad_bcast4<3>(q);
-    const int e0 = __float_as_int(quad_bcast<0>(__int_as_float(evm)));
-    const int e1 = __float_as_int(quad_bcast<1>(__int_as_float(evm)));
-    const int e2 = __float_as_int(quad_bcast<2>(__int_as_float(evm)));
-    const int e3 = __float_as_int(quad_bcast<3>(__int_as_float(evm)));
-    const int kmax = min(kb + 4, k_hi);
-    auto step = [&](const float4& qt, int et, int kt) {
-      if (done || kt >= kmax) return;
-      if (et) {
+    // The group's four samples in ray order.  A sample that was not
+    // evaluated (transparent cell, past the end of the ray) enters as
+    // colour 0 and opacity 0, for which "over" leaves C and A exactly
+    // unchanged, so every sample goes through the same steps; after the
+    // first sample that reaches the termination opacity the others are
+    // masked.  In an iteration where no lane of the wave evaluated, the
+    // four steps change nothing and are left out.
+    if (__ballot(ev) != 0) {
+      const float4 q0 = quad_bcast4<0>(q), q1 = quad_bcast4<1>(q), q2 = quad_bcast4<2>(q),
+                   q3 = quad_bcast4<3>(q);
+      int stop = 0;                // 1 + index of the terminating sample, 0: none
+      auto step = [&](float4 qt, int t) {
+        const bool live = stop == 0;
+        qt.w = live ? qt.w : 0.f;
         over(qt, C0, C1, C2, A);
-        ++nev;
-      }
-      used = kt + 1;
-      done = A >= r.ert_alpha;
-    };
-    step(q0, e0, kb);
-    step(q1, e1, kb + 1);
-    step(q2, e2, kb + 2);
-    step(q3, e3, kb + 3);
+        if (live && A >= r.ert_alpha) stop = t + 1;
+      };
+      step(q0, 0);
+      step(q1, 1);
+      step(q2, 2);
+      step(q3, 3);
+      done = stop != 0;
+      used = done ? kb + stop : min(kb + 4, k_hi);
+    } else {
+      used = min(kb + 4, k_hi);
+    }
+    nev += (ev && k < used) ? 1 : 0;
     if (r.alpha && k < used) r.alpha[pid * r.alpha_stride + k] = ev ? q.w : 0.f;
+  }
+  // evaluated samples of the ray: the sum over its four lanes
+  {
+    const int n1 = __float_as_int(quad_bcast<1>(__int_as_float(nev)));
+    const int n2 = __float_as_int(quad_bcast<2>(__int_as_float(nev)));
+    const int n3 = __float_as_int(quad_bcast<3>(__int_as_float(nev)));
+    const int n0 = __float_as_int(quad_bcast<0>(__int_as_float(nev)));
+    nev = n0 + n1 + n2 + n3;
   }
   if (pix && s == 0) {
     if (r.key) r.key[pid] = ray.K > 0 ? ray.t_near : __builtin_inf();
@@ -1592,6 +1734,7 @@ template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool 
           bool QUAD = false>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
+  __shared__ float4 lmats[LDSREC ? 1 : kMatsLds / 4];
   __shared__ float4 tf[256];
   __shared__ int zpre[257];
   __shared__ int wtot[kBlock / kWave];
@@ -1606,6 +1749,8 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
       reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
     R = lr;
     MT = lm;
+  } else {
+    MT = stage_mats(m, lmats);
   }
   stage_tf(r.tf, tf, zpre, wtot);
   if constexpr (QUAD) {
@@ -1781,13 +1926,8 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
     const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
     const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
     const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
-    float spec = 1.f, bse = diff;
-    for (int ex = r.shininess; ex; ex >>= 1) {
-      if (ex & 1) spec *= bse;
-      bse *= bse;
-    }
     const float shade = fmaf(r.kd, diff, r.ka);
-    const float ks = r.ks * spec;
+    const float ks = r.ks * spec_pow(diff, r.shininess);
     out = make_float4(fmaf(r.iso_rgb[0], shade, ks), fmaf(r.iso_rgb[1], shade, ks),
                       fmaf(r.iso_rgb[2], shade, ks), 1.f);
   }
@@ -2050,16 +2190,14 @@ static void sort_launch(const DevModel& m, const SortArgs& sa, hipStream_t st) {
   const size_t hist_lds = tabs + (size_t)((sa.nb + 1) / 2) * 4;
   hipLaunchKernelGGL((sort_hist_k<MULTI, GT>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
   hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kScanThreads), 0, st, sa);
-  const unsigned gc = (unsigned)((sa.n + kSortChunk - 1) / kSortChunk);
+  // at most 8 workgroups per CU, each looping over chunks
+  const unsigned gc = (unsigned)std::min<int64_t>((sa.n + kScatterChunk - 1) / kScatterChunk,
+                                                  8 * 256);
   if (sa.tmp) {                        // two levels: coarse runs, then buckets
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, kSortPer, GT>), dim3(gc), dim3(kBlock), tabs, st,
-                       m, sa);
-    const unsigned gf = (unsigned)((sa.n + kBlock * kFinePer - 1) / (kBlock * kFinePer));
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, kFinePer, GT>), dim3(gf), dim3(kBlock), tabs, st,
-                       m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
   } else {
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kOne, kSortPer, GT>), dim3(gc), dim3(kBlock), tabs, st,
-                       m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kOne, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
   }
 }
 
