@@ -204,7 +204,7 @@ static bool near_table(const std::vector<float>& a, const std::vector<float>& b)
 static void free_model(mfa_model m) {
   if (!m) return;
   if (m->ws_done) (void)hipEventDestroy(m->ws_done);
-  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws, m->d_sblk};
+  void* bufs[] = {m->d_ctrl, m->d_rec, m->d_mats, m->d_blocks, m->d_edges, m->d_mcb, m->d_scb[0], m->d_scb[1], m->d_bwin, m->d_gtab, m->d_gmeta, m->d_ws, m->d_sblk, m->d_sedges};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete m;
@@ -539,8 +539,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   std::vector<SortBlk> sblk((size_t)nb);
   for (int64_t b = 0; b < nb; ++b) {
     for (int a = 0; a < 3; ++a) {
-      sblk[b].lo[a] = dblk[b].lo[a];
-      sblk[b].inv_ext[a] = dblk[b].inv_ext[a];
+      sblk[b].lo[a] = (float)dblk[b].lo[a];
+      sblk[b].scale[a] = (float)(dblk[b].inv_ext[a] * (double)dblk[b].nsp[a]);
       sblk[b].nsp[a] = dblk[b].nsp[a];
     }
     sblk[b].tile_off = dblk[b].tile_off;
@@ -627,6 +627,8 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
     edge_pool.insert(edge_pool.end(), edges[a].begin(), edges[a].end());
   }
 
+  std::vector<float> sedges(edge_pool.begin(), edge_pool.end());   // FP32 copy for the sort
+
   mfa_status st;
   if ((st = upload(&m->d_ctrl, pool.data(), pool.size(), m, "ctrl upload")) != MFA_OK ||
       (st = upload(&m->d_rec, recs.data(), recs.size() * sizeof(SpanRec), m, "span upload")) != MFA_OK ||
@@ -639,6 +641,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
       (!bwin.empty() &&
        (st = upload(&m->d_bwin, bwin.data(), bwin.size() * sizeof(BucketWin), m, "window upload")) != MFA_OK) ||
       (st = upload(&m->d_sblk, sblk.data(), sblk.size() * sizeof(SortBlk), m, "sort table upload")) != MFA_OK ||
+      (st = upload(&m->d_sedges, sedges.data(), sedges.size() * sizeof(float), m, "sort edge upload")) != MFA_OK ||
       (!gtab.empty() &&
        ((st = upload(&m->d_gtab, gtab.data(), gtab.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK ||
         (st = upload(&m->d_gmeta, gmeta.data(), gmeta.size() * sizeof(int32_t), m, "span table upload")) != MFA_OK))) {
@@ -675,6 +678,7 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   }
   dm.bwin = m->d_bwin;
   dm.sblk = m->d_sblk;
+  dm.sedges = m->d_sedges;
   dm.n_edges = (int32_t)edge_pool.size();
   dm.gtab = m->d_gtab;
   dm.gmeta = m->d_gmeta;

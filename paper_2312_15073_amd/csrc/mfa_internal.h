@@ -83,14 +83,17 @@ constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 
 // Per-block data of the bucket computation of multi-block models, staged in
 // LDS by the sort kernels (models of at most kSortBlkLds blocks and
-// kSortEdgesLds block edges).
+// kSortEdgesLds block edges).  The bucket only orders the work, so it is
+// computed in FP32 (lo and nsp / (hi - lo) rounded to FP32); the decode
+// checks each point's exact FP64 owner against the bucket's block.
 struct SortBlk {
-  double lo[3];
-  double inv_ext[3];
+  float lo[3];
+  float scale[3];        // nsp / (hi - lo)
   int32_t nsp[3];
   int32_t tile_off;
+  int32_t pad[2];
 };
-static_assert(sizeof(SortBlk) == 64, "SortBlk layout");
+static_assert(sizeof(SortBlk) == 48, "SortBlk layout");
 constexpr int kSortBlkLds = 512;
 constexpr int kSortEdgesLds = 256;
 
@@ -135,6 +138,7 @@ struct DevModel {
   const BucketWin* bwin;  // per sort bucket: control-point window
   int32_t win_max;       // largest window (values)
   const SortBlk* sblk;   // per block: data of the sort-bucket computation
+  const float* sedges;   // the block edges rounded to FP32 (sort only)
   int32_t n_edges;       // block edges over the three axes
   const uint32_t* mcb;   // per macro cell (lo, hi) bounds of the stored values as
                          // two FP16 halves rounded outward, widened by a margin

@@ -521,12 +521,12 @@ constexpr int kHistChunk = kHistThreads * kHistPer;
 constexpr int kHistIlp = 4;
 constexpr int kScanThreads = 1024;
 
-// Sort tables of a multi-block model in LDS: block edges, then one SortBlk
-// per block; null pointers when the model exceeds the LDS budget (then the
-// global copies are read).
+// Sort tables of a multi-block model in LDS: block edges (FP32), then one
+// SortBlk per block; the global copies when the model exceeds the LDS
+// budget.
 struct SortTabs {
   const SortBlk* blk;
-  const double* edges;
+  const float* edges;
 };
 
 // LDS bytes of the staged sort tables (0: not staged); the launchers add
@@ -535,20 +535,20 @@ template <bool MULTI>
 __host__ __device__ inline size_t sort_tabs_bytes(const DevModel& m) {
   if (!MULTI) return 0;
   return m.nblocks <= kSortBlkLds && m.n_edges <= kSortEdgesLds
-             ? (size_t)m.nblocks * sizeof(SortBlk) + (size_t)m.n_edges * 8
+             ? (size_t)m.nblocks * sizeof(SortBlk) + (size_t)((m.n_edges + 3) / 4) * 16
              : 0;
 }
 
 template <bool MULTI>
 __device__ __forceinline__ SortTabs stage_sort_tabs(const DevModel& m, float4* lds) {
-  SortTabs t{m.sblk, m.edges};
+  SortTabs t{m.sblk, m.sedges};
   if constexpr (MULTI) {
     if (sort_tabs_bytes<MULTI>(m) != 0) {
       SortBlk* lb = reinterpret_cast<SortBlk*>(lds);
-      double* le = reinterpret_cast<double*>(lb + m.nblocks);
-      for (int q = threadIdx.x; q < m.nblocks * 4; q += blockDim.x)
+      float* le = reinterpret_cast<float*>(lb + m.nblocks);
+      for (int q = threadIdx.x; q < m.nblocks * 3; q += blockDim.x)
         reinterpret_cast<float4*>(lb)[q] = reinterpret_cast<const float4*>(m.sblk)[q];
-      for (int q = threadIdx.x; q < m.n_edges; q += blockDim.x) le[q] = m.edges[q];
+      for (int q = threadIdx.x; q < m.n_edges; q += blockDim.x) le[q] = m.sedges[q];
       t.blk = lb;
       t.edges = le;
     }
@@ -557,39 +557,38 @@ __device__ __forceinline__ SortTabs stage_sort_tabs(const DevModel& m, float4* l
   return t;
 }
 
-// Bucket of a point: the exact owning block (the block-owner rule, as in
-// probe()) and, per axis, the tile of the span guess (the exact span or,
-// within rounding of a knot, a neighbour).
+// Bucket of a point.  Single-block models: the tile of the span guesses
+// (the exact span or, within rounding of a knot, a neighbour).  Multi-block
+// models, in FP32 (the bucket only orders the work): the block from the
+// FP32 edges (the exact owner except within FP32 rounding of a face, which
+// the decode detects) and the tile of floor((x - lo) * nsp / (hi - lo)).
 template <bool MULTI, bool GT>
 __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTabs& tb,
-                                                const double (&x)[3]) {
+                                                const float (&x)[3]) {
   const int sh = m.sort_shift;
   int t[3], td[3];
   uint32_t off;
   if constexpr (MULTI) {
     int b[3];
-    double xc[3], e0[3], e1[3];
+    float xc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double* E = tb.edges + m.edge_off[a];
-      xc[a] = clampd(x[a], m.box_lo[a], m.box_hi[a]);
-      b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
-      e0[a] = E[b[a]];
-      e1[a] = E[b[a] + 1];
-    }
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
-    if (!ok) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) fix_owner(tb.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
+      const float* E = tb.edges + m.edge_off[a];
+      const int G = m.grid[a];
+      xc[a] = fminf(fmaxf(x[a], E[0]), E[G]);
+      int bb = (int)((xc[a] - E[0]) * (float)m.edge_scale[a]);
+      bb = bb < 0 ? 0 : (bb > G - 1 ? G - 1 : bb);
+      if (bb < G - 1 && E[bb + 1] <= xc[a]) ++bb;
+      else if (bb > 0 && E[bb] > xc[a]) --bb;
+      b[a] = bb;
     }
     const SortBlk& B = tb.blk[(b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double u = param_of(xc[a], B.lo[a], B.inv_ext[a]);
       const int nsp = B.nsp[a];
-      t[a] = guess_span(nsp, u) >> sh;
+      int j = (int)((xc[a] - B.lo[a]) * B.scale[a]);
+      j = j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
+      t[a] = j >> sh;
       td[a] = (nsp + (1 << sh) - 1) >> sh;
     }
     off = (uint32_t)B.tile_off;
@@ -597,7 +596,8 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTab
     const DevBlock* __restrict__ B = &m.b0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double u = param_of(clampd(x[a], m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
+      const double xa = (double)x[a];
+      const double u = param_of(clampd(xa, m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
       const int nsp = B->nsp[a];
       t[a] = guess_span<GT>(m, B, 0, a, u) >> sh;
       td[a] = (nsp + (1 << sh) - 1) >> sh;
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs
       const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
       v[u] = q + u < kHistPer && i < sa.n;
       const int64_t ic = v[u] ? i : 0;
-      const double x[3] = {(double)sa.xyz[ic], (double)sa.xyz[sa.n + ic], (double)sa.xyz[2 * sa.n + ic]};
+      const float x[3] = {sa.xyz[ic], sa.xyz[sa.n + ic], sa.xyz[2 * sa.n + ic]};
       b[u] = sort_bucket<MULTI, GT>(m, tb, x);
     }
 #pragma unroll
@@ -678,34 +678,29 @@ __device__ __forceinline__ uint32_t n_parts(uint32_t c) { return (c + kTilePoint
 
 // One workgroup: exclusive scan of the bucket counts (start[nb] = n), reset
 // of the cursors, and the list of decode items (bucket, part) in bucket
-// order.
+// order; rounds of kScanThreads buckets, one per thread, with the running
+// totals carried from round to round.
 __global__ __launch_bounds__(kScanThreads) void sort_scan_k(SortArgs sa) {
   __shared__ uint32_t wsum[kScanThreads / kWave];
-  constexpr int kPer = kMaxBuckets / kScanThreads;
-  uint32_t v[kPer], s = 0, parts = 0, tot;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int b = threadIdx.x * kPer + q;
-    v[q] = b < sa.nb ? sa.hist[b] : 0u;
-    s += v[q];
-    parts += n_parts(v[q]);
-  }
-  uint32_t run = block_scan(s, wsum, &tot);
-  uint32_t irun = block_scan(parts, wsum, &tot);
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int b = threadIdx.x * kPer + q;
+  uint32_t run0 = 0, irun0 = 0;
+  for (int r0 = 0; r0 < sa.nb; r0 += kScanThreads) {
+    const int b = r0 + threadIdx.x;
+    const uint32_t v = b < sa.nb ? sa.hist[b] : 0u;
+    const uint32_t np = n_parts(v);
+    uint32_t tot, itot;
+    const uint32_t run = run0 + block_scan(v, wsum, &tot);
+    const uint32_t irun = irun0 + block_scan(np, wsum, &itot);
     if (b < sa.nb) {
       sa.start[b] = run;
       sa.cursor[b] = 0u;
-      const uint32_t np = n_parts(v[q]);
       for (uint32_t u = 0; u < np; ++u) sa.items[irun + u] = make_int2(b, (int)u);
-      irun += np;
     }
-    run += v[q];
+    run0 += tot;
+    irun0 += itot;
+    __syncthreads();                               // wsum reused by the next round
   }
   if (threadIdx.x == 0) {
-    *sa.n_items = (int32_t)tot;
+    *sa.n_items = (int32_t)irun0;
     sa.start[sa.nb] = (uint32_t)sa.n;
   }
   if (sa.tmp && threadIdx.x < kCoarseBuckets) sa.ccursor[threadIdx.x * kCursorStride] = 0u;
@@ -782,7 +777,7 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
   if constexpr (MODE == kFine) {
     if (threadIdx.x == 0) {
       const float4 r = sa.tmp[c0];
-      const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+      const float x[3] = {r.x, r.y, r.z};
       *s_key0 = (sort_bucket<MULTI, GT>(m, tb, x) >> sa.fine_shift) << sa.fine_shift;
     }
   }
@@ -800,7 +795,7 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
     key[q] = 0xFFFFFFFFu;
     if (l < cn) {
       rec[q] = sort_input<MODE == kFine>(sa, c0 + l);
-      const double x[3] = {(double)rec[q].x, (double)rec[q].y, (double)rec[q].z};
+      const float x[3] = {rec[q].x, rec[q].y, rec[q].z};
       const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
       if constexpr (MODE == kCoarse) {
         key[q] = b >> sa.fine_shift;
@@ -906,11 +901,12 @@ __device__ __forceinline__ float4 evaluate_lds(const Loc& L, const float* Wp, in
 // span guesses with their records, as probe() computes them for B.  TR:
 // the records of the tile's spans o[a] .. o[a] + ns[a] - 1 per axis (axis a
 // from toff[a] on), or null; a guess outside them reads R.
-template <bool GT>
+template <bool GT, int NT>
 __device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* __restrict__ R,
                                              const double (&x)[3], const DevBlock* __restrict__ B,
-                                             int block, const SpanRec* TR, const int (&o)[3],
-                                             const int (&ns)[3], const int (&toff)[3]) {
+                                             int block, const SpanRec (&TR)[NT], bool tr_ok,
+                                             const int (&o)[3], const int (&ns)[3],
+                                             const int (&toff)[3]) {
   Probe q;
   q.B = B;
   q.block = block;
@@ -923,7 +919,7 @@ __device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* _
   for (int a = 0; a < 3; ++a) {
     q.j[a] = guess_span<GT>(m, B, block, a, q.u[a]);
     const int jj = q.j[a] - o[a];
-    if (TR != nullptr && jj >= 0 && jj < ns[a])
+    if (tr_ok && jj >= 0 && jj < ns[a])
       q.rec[a] = TR[toff[a] + jj];
     else
       q.rec[a] = R[B->rec_off[a] + q.j[a]];
@@ -932,6 +928,19 @@ __device__ __forceinline__ Probe probe_block(const DevModel& m, const SpanRec* _
 }
 
 constexpr int kTileRecs = 96;      // span records of a tile staged for multi-block decodes
+
+// A record read by every lane at the same address, kept as wave-uniform
+// values (scalar registers).
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  T b;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&b);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(T) / 4); ++q) dst[q] = __builtin_amdgcn_readfirstlane(src[q]);
+  return b;
+}
 
 // Basis tables of the model in LDS when they hold at most kMatsLds floats
 // (clamped uniform knots share a few span shapes); else the global pool.
@@ -980,21 +989,40 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   } else {
     MT = stage_mats(m, lmats);
   }
-  const int2 it = sa.items[item];
+  const int2 it = uniform_copy(sa.items + item);
   const int b = it.x;
-  const uint32_t b0 = sa.start[b], bcnt = sa.start[b + 1] - b0, np = n_parts(bcnt);
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(sa.start[b]);
+  const uint32_t bcnt = __builtin_amdgcn_readfirstlane(sa.start[b + 1]) - b0, np = n_parts(bcnt);
   const uint32_t s0 = b0 + (uint32_t)(((uint64_t)bcnt * (uint32_t)it.y) / np);
   const uint32_t s1 = b0 + (uint32_t)(((uint64_t)bcnt * (uint32_t)(it.y + 1)) / np);
-  const BucketWin bw = m.bwin[b];
+  const BucketWin bw = uniform_copy(m.bwin + b);
   const int w12 = bw.w[1] * bw.w[2];
   const int wn = bw.w[0] * w12;
   const bool staged = wn <= win_cap;
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
-  const DevBlock* __restrict__ B = MULTI ? m.blocks + bw.block : &m.b0;
-  // multi-block models: the span records of the tile, per axis
+  // multi-block models: the bucket's block record as uniform values (the
+  // block is the same for the whole workgroup), and the span records of
+  // the tile per axis in LDS
+  DevBlock Bu;
+  int bq[3] = {0, 0, 0};
+  double be0[3] = {0.0, 0.0, 0.0}, be1[3] = {0.0, 0.0, 0.0};
+  if constexpr (MULTI) {
+    Bu = uniform_copy(m.blocks + bw.block);
+    // the block's grid coordinates and bracketing edges, for the exact
+    // owner check of each point (the bucket was found in FP32)
+    bq[2] = bw.block % m.grid[2];
+    bq[1] = (bw.block / m.grid[2]) % m.grid[1];
+    bq[0] = bw.block / (m.grid[2] * m.grid[1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      be0[a] = uniform_copy(m.edges + m.edge_off[a] + bq[a]);
+      be1[a] = uniform_copy(m.edges + m.edge_off[a] + bq[a] + 1);
+    }
+  }
+  const DevBlock* __restrict__ B = MULTI ? &Bu : &m.b0;
   __shared__ SpanRec trec[MULTI ? kTileRecs : 1];
   int ns[3], toff[3];
-  const SpanRec* TR = nullptr;
+  bool tr_ok = false;
   if constexpr (MULTI) {
     int tot = 0;
 #pragma unroll
@@ -1003,12 +1031,12 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
       toff[a] = tot;
       tot += ns[a];
     }
-    if (tot <= kTileRecs) {
-      for (int q = threadIdx.x; q < tot; q += kBlock) {
-        const int a = q < toff[1] ? 0 : (q < toff[2] ? 1 : 2);
-        trec[q] = m.rec[B->rec_off[a] + bw.o[a] + (q - toff[a])];
-      }
-      TR = trec;
+    tr_ok = tot <= kTileRecs;
+    if (tr_ok) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        for (int q = threadIdx.x; q < ns[a]; q += kBlock)
+          trec[toff[a] + q] = m.rec[B->rec_off[a] + bw.o[a] + q];
     }
   }
   if (staged) {
@@ -1056,8 +1084,16 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
     Loc L;
     if constexpr (MULTI) {
-      Probe pr = probe_block<GT>(m, R, x, B, bw.block, TR, bw.o, ns, toff);
-      L = finish(m, R, pr);
+      bool own = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        own &= owner_ok(m.grid[a], clampd(x[a], m.box_lo[a], m.box_hi[a]), bq[a], be0[a], be1[a]);
+      if (own) {
+        Probe pr = probe_block<GT>(m, R, x, B, bw.block, trec, tr_ok, bw.o, ns, toff);
+        L = finish(m, R, pr);
+      } else {                         // within FP32 rounding of a block face
+        L = locate<P, true, GT>(m, R, x);
+      }
     } else {
       L = locate<P, false, GT>(m, R, x);
     }
@@ -1065,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     q = qn;
     if ((int64_t)i >= sa.n) continue;
     int d[3];
-    bool in = staged;
+    bool in = staged && L.block == bw.block;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       d[a] = L.j[a] - bw.o[a];

@@ -33,6 +33,7 @@ struct mfa_model_s {
   uint32_t* d_scb[2] = {nullptr, nullptr};
   mfa::BucketWin* d_bwin = nullptr;
   mfa::SortBlk* d_sblk = nullptr;
+  float* d_sedges = nullptr;
   int32_t* d_gtab = nullptr;
   int32_t* d_gmeta = nullptr;
   bool nonuniform = false;   // some axis has non-uniform knots (span guess tables)

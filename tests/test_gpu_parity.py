@@ -556,6 +556,28 @@ def test_sorted_decode_multiblock_and_scratch_regrowth(mfa, dev):
     assert_values_close(b, ref["f"], ref["grad"], max(np.abs(bl.ctrl).max() for bl in model.blocks))
 
 
+def test_sorted_decode_multiblock_points_on_faces(mfa, dev):
+    """Points at the FP32 roundings of block faces and their FP32
+    neighbours: the sort's FP32 block choice can differ from the exact FP64
+    owner there, which the decode detects and evaluates in the owner block;
+    results equal the unsorted decode bit for bit (spans and blocks too)."""
+    model = small_multiblock()
+    rng = np.random.default_rng(44)
+    pts = [rng.random((20000, 3)).astype(np.float32)]
+    for a in range(3):
+        for e in model.edges[a]:
+            e32 = np.float32(e)
+            for v in (np.nextafter(e32, np.float32(-1)), e32, np.nextafter(e32, np.float32(2))):
+                q = rng.random((300, 3)).astype(np.float32)
+                q[:, a] = v
+                pts.append(q)
+    pts = np.concatenate(pts).T.copy()
+    announce(f"sorted decode multi-block, points on faces n={pts.shape[1]}")
+    out = _sorted_matches_unsorted(mfa, dev, model, pts)
+    ref = oracle_points(model, pts.T)
+    assert_values_close(out, ref["f"], ref["grad"], max(np.abs(b.ctrl).max() for b in model.blocks))
+
+
 def test_sorted_decode_c2_1e7(mfa, dev, c2):
     pts = synth.random_points(10_000_000, seed=12)
     announce("sorted decode c2 1e7")
