@@ -146,7 +146,7 @@ mfa_status mfa_model_export_ctrl(mfa_model model, int32_t block, void* host_dst,
  *          order, each bucket's control points staged once in on-chip
  *          memory; results are still written in input order and are
  *          identical bit for bit to the unsorted call.  Uses scratch memory
- *          held by the model (16 bytes per point, 32 with more than 1024
+ *          held by the model (16 bytes per point, 36 with more than 1024
  *          buckets, plus about 20 per bucket), allocated on first use and
  *          grown when a larger n arrives (MFA_E_NOMEM if that fails).
  *          Sorted calls on one model are ordered by the library: a call
@@ -174,9 +174,9 @@ mfa_status mfa_decode_points(mfa_model model, const float* xyz, int64_t n, uint3
  * ends.  No device memory is allocated or freed by the call.  Arguments,
  * outputs and results are those of mfa_decode_points (bit-identical).
  *  n     : the scratch must hold the layout of the sorted decode: 16 bytes
- *          per point (32 with more than 1024 buckets) plus about 20 per
+ *          per point (36 with more than 1024 buckets) plus about 20 per
  *          bucket and the decode items, at most 64 MiB (about 4 million
- *          points with up to 1024 buckets, 2 million above); a larger n
+ *          points with up to 1024 buckets, 1.8 million above); a larger n
  *          returns MFA_E_ARG with the largest n accepted for this model.
  * Every call on a device shares that device's scratch, which keeps the last
  * call's contents (the kernels clear what must start at zero): calls whose

@@ -754,9 +754,10 @@ static mfa_status check_points(mfa_model m, const float* xyz, int64_t n, uint32_
 // Scratch of a sorted decode of n points over nb buckets, one region after
 // another (256-byte aligned): one 16-byte record per point, counts, starts
 // and cursors per bucket, the decode items and their count, and with the
-// two-level split the coarse cursors and a second record per point.
+// two-level split the coarse cursors, a second record per point and each
+// point's position in the coarse order.
 struct SortLayout {
-  size_t o_hist, o_start, o_cur, o_items, o_nitems, o_ccur, o_tmp, bytes;
+  size_t o_hist, o_start, o_cur, o_items, o_nitems, o_ccur, o_tmp, o_tpos, bytes;
   bool two;
   int fine_shift;
 };
@@ -776,7 +777,8 @@ static SortLayout sort_layout(int64_t n, int64_t nb) {
   L.fine_shift = 0;
   while ((nb + (1ll << L.fine_shift) - 1) >> L.fine_shift > kCoarseBuckets) ++L.fine_shift;
   L.o_tmp = L.o_ccur + al(4 * kCoarseBuckets * kCursorStride);
-  L.bytes = L.two ? L.o_tmp + al(16 * (size_t)n) : L.o_ccur;
+  L.o_tpos = L.o_tmp + al(16 * (size_t)n);
+  L.bytes = L.two ? L.o_tpos + al(4 * (size_t)n) : L.o_ccur;
   return L;
 }
 
@@ -796,6 +798,10 @@ static mfa_status sorted_decode(mfa_model m, uint8_t* w, const SortLayout& L, co
   sa.fine_shift = L.fine_shift;
   sa.tmp = L.two ? (float4*)(w + L.o_tmp) : nullptr;
   sa.ccursor = L.two ? (uint32_t*)(w + L.o_ccur) : nullptr;
+  // two levels: the results go through the coarse order (writes within one
+  // coarse key's region at a time rather than over the whole output), except
+  // with debug outputs, which are written at the input positions directly
+  sa.tpos = L.two && !dbg ? (uint32_t*)(w + L.o_tpos) : nullptr;
   hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), grad, sa, out,
                                       dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "sorted decode launch");

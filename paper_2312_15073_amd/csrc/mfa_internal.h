@@ -226,6 +226,12 @@ struct SortArgs {
   int32_t fine_shift;
   float4* tmp;           // [n] records in coarse order, or null (one level)
   uint32_t* ccursor;     // [kCoarseBuckets * kCursorStride] positions handed out per coarse key
+  // two-level split, results through the coarse order (or null): the
+  // coarse pass writes each point's position in tmp here (in input order),
+  // the bucket pass gives each record that position instead of the input
+  // index, the decode writes its results at it (into tmp, no longer read),
+  // and a last pass gathers them back into input order
+  uint32_t* tpos;        // [n]
 };
 
 struct GridArgs {

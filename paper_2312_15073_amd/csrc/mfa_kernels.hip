@@ -539,19 +539,19 @@ __host__ __device__ inline size_t sort_tabs_bytes(const DevModel& m) {
              : 0;
 }
 
-template <bool MULTI>
+// TL (tables in LDS, sort_tabs_bytes() != 0) is a compile-time choice, so
+// that the table reads compile to LDS loads rather than generic ones.
+template <bool MULTI, bool TL>
 __device__ __forceinline__ SortTabs stage_sort_tabs(const DevModel& m, float4* lds) {
   SortTabs t{m.sblk, m.sedges};
-  if constexpr (MULTI) {
-    if (sort_tabs_bytes<MULTI>(m) != 0) {
-      SortBlk* lb = reinterpret_cast<SortBlk*>(lds);
-      float* le = reinterpret_cast<float*>(lb + m.nblocks);
-      for (int q = threadIdx.x; q < m.nblocks * 3; q += blockDim.x)
-        reinterpret_cast<float4*>(lb)[q] = reinterpret_cast<const float4*>(m.sblk)[q];
-      for (int q = threadIdx.x; q < m.n_edges; q += blockDim.x) le[q] = m.sedges[q];
-      t.blk = lb;
-      t.edges = le;
-    }
+  if constexpr (MULTI && TL) {
+    SortBlk* lb = reinterpret_cast<SortBlk*>(lds);
+    float* le = reinterpret_cast<float*>(lb + m.nblocks);
+    for (int q = threadIdx.x; q < m.nblocks * 3; q += blockDim.x)
+      reinterpret_cast<float4*>(lb)[q] = reinterpret_cast<const float4*>(m.sblk)[q];
+    for (int q = threadIdx.x; q < m.n_edges; q += blockDim.x) le[q] = m.sedges[q];
+    t.blk = lb;
+    t.edges = le;
     __syncthreads();
   }
   return t;
@@ -616,11 +616,12 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
 // counter cannot overflow): two counters per LDS word (bucket b in the
 // half b & 1 of word b >> 1).  Dynamic LDS: the sort tables, then the
 // counters.
-template <bool MULTI, bool GT>
+template <bool MULTI, bool GT, bool TL>
 __global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs sa) {
   extern __shared__ float4 sdyn[];
-  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
-  uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(sdyn) + sort_tabs_bytes<MULTI>(m));
+  const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
+  uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(sdyn) +
+                                            (TL ? sort_tabs_bytes<MULTI>(m) : 0));
   const int nw = (sa.nb + 1) >> 1;
   for (int w = threadIdx.x; w < nw; w += kHistThreads) h[w] = 0u;
   __syncthreads();
@@ -795,6 +796,8 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
     key[q] = 0xFFFFFFFFu;
     if (l < cn) {
       rec[q] = sort_input<MODE == kFine>(sa, c0 + l);
+      if constexpr (MODE == kFine)
+        if (sa.tpos) rec[q].w = __uint_as_float((uint32_t)(c0 + l));   // position in tmp
       const float x[3] = {rec[q].x, rec[q].y, rec[q].z};
       const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
       if constexpr (MODE == kCoarse) {
@@ -832,6 +835,8 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
     const uint32_t sl = h[key[q]] + rank[q];
     recs[sl] = rec[q];
     keyof[sl] = (uint16_t)key[q];
+    if constexpr (MODE == kCoarse)
+      if (sa.tpos) sa.tpos[c0 + q * kBlock + threadIdx.x] = gbase[key[q]] + rank[q];
   }
   __syncthreads();
   float4* dst = MODE == kCoarse ? sa.tmp : sa.rec;
@@ -846,7 +851,7 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
 
 // The workgroups loop over the chunks (grid-stride), so the sort tables
 // are staged once per workgroup rather than once per chunk.
-template <bool MULTI, int MODE, bool GT>
+template <bool MULTI, int MODE, bool GT, bool TL>
 __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
   constexpr int kKeys = MODE == kCoarse ? kCoarseBuckets : (MODE == kOne ? kOneLevelBuckets : kFineKeys);
   static_assert(kKeys <= 4 * kBlock, "lds_scan covers 4 keys per thread");
@@ -857,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
   __shared__ uint32_t wsum[kBlock / kWave];
   __shared__ uint32_t s_key0, s_staged;
   extern __shared__ float4 sdyn[];
-  const SortTabs tb = stage_sort_tabs<MULTI>(m, sdyn);
+  const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
   for (int64_t c0 = (int64_t)blockIdx.x * kScatterChunk; c0 < sa.n;
        c0 += (int64_t)gridDim.x * kScatterChunk)
     scatter_chunk<MULTI, MODE, GT, kKeys>(m, sa, tb, c0, h, gbase, recs, keyof, wsum, &s_key0, &s_staged);
@@ -987,7 +992,11 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     MT = lm;
     W = lm + m.n_mats * m.mat_stride;
   } else {
-    MT = stage_mats(m, lmats);
+    // the launcher sends models whose tables exceed kMatsLds floats to
+    // decode_sorted_k, so that these reads are always LDS loads
+    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      lmats[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    MT = reinterpret_cast<const float*>(lmats);
   }
   const int2 it = uniform_copy(sa.items + item);
   const int b = it.x;
@@ -2219,28 +2228,46 @@ static hipError_t points_p(const DevModel& m, int kind, bool grad, const float* 
 }
 
 // Histogram, scan and scatter of the (block, tile) sort.
-template <bool MULTI, bool GT>
-static void sort_launch(const DevModel& m, const SortArgs& sa, hipStream_t st) {
-  const size_t tabs = sort_tabs_bytes<MULTI>(m);
+template <bool MULTI, bool GT, bool TL>
+static void sort_launch_tl(const DevModel& m, const SortArgs& sa, size_t tabs, hipStream_t st) {
   const unsigned gh = (unsigned)((sa.n + kHistChunk - 1) / kHistChunk);
   const size_t hist_lds = tabs + (size_t)((sa.nb + 1) / 2) * 4;
-  hipLaunchKernelGGL((sort_hist_k<MULTI, GT>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
+  hipLaunchKernelGGL((sort_hist_k<MULTI, GT, TL>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
   hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kScanThreads), 0, st, sa);
   // at most 8 workgroups per CU, each looping over chunks
   const unsigned gc = (unsigned)std::min<int64_t>((sa.n + kScatterChunk - 1) / kScatterChunk,
                                                   8 * 256);
   if (sa.tmp) {                        // two levels: coarse runs, then buckets
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, GT, TL>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, GT, TL>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
   } else {
-    hipLaunchKernelGGL((sort_scatter_k<MULTI, kOne, GT>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<MULTI, kOne, GT, TL>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
+  }
+}
+
+template <bool MULTI, bool GT>
+static void sort_launch(const DevModel& m, const SortArgs& sa, hipStream_t st) {
+  if constexpr (MULTI) {
+    const size_t tabs = sort_tabs_bytes<MULTI>(m);
+    if (tabs != 0)
+      sort_launch_tl<MULTI, GT, true>(m, sa, tabs, st);
+    else
+      sort_launch_tl<MULTI, GT, false>(m, sa, 0, st);
+  } else {
+    sort_launch_tl<MULTI, GT, false>(m, sa, 0, st);
   }
 }
 
 template <int P, Storage S, bool G>
 static void decode_sorted_g(const DevModel& m, int kind, const SortArgs& sa, float* out,
                             int32_t* dbg, hipStream_t st) {
-  if (m.win_max > kWinMax) {          // windows too large for LDS: one point per thread
+  const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
+  const size_t wb = (size_t)m.win_max * 4;
+  const bool lds_tabs = tabs <= (size_t)kLdsRecBytes && lds_fits(tabs + wb);
+  const bool ldsrec = kind != kKindMulti && lds_tabs;     // span records and tables staged together
+  // windows too large for LDS, or basis tables too large for the LDS copy
+  // of the kernels that stage the windows alone: one point per thread
+  if (m.win_max > kWinMax || (!ldsrec && m.n_mats * m.mat_stride > kMatsLds)) {
     const unsigned g = (unsigned)((sa.n + kBlock - 1) / kBlock);
     if (kind != kKindPlain)
       hipLaunchKernelGGL((decode_sorted_k<P, S, true, false, G>), dim3(g), dim3(kBlock), 0, st, m, sa,
@@ -2253,9 +2280,6 @@ static void decode_sorted_g(const DevModel& m, int kind, const SortArgs& sa, flo
   // items: at most ceil(n / kTilePoints) + nb; the surplus workgroups exit
   const unsigned gi = (unsigned)((sa.n + kTilePoints - 1) / kTilePoints + sa.nb);
   const int cap = m.win_max;
-  const size_t tabs = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
-  const size_t wb = (size_t)cap * 4;
-  const bool lds_tabs = tabs <= (size_t)kLdsRecBytes && lds_fits(tabs + wb);
   if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
     hipLaunchKernelGGL((decode_tiles_k<P, S, true, false, false, G>), dim3(gi), dim3(kBlock), wb, st, m,
                        sa, cap, out, dbg);
@@ -2270,6 +2294,34 @@ static void decode_sorted_g(const DevModel& m, int kind, const SortArgs& sa, flo
                        sa, cap, out, dbg);
 }
 
+// Results of the decode in coarse order (sa.tpos) gathered back into input
+// order: out[i] = src[tpos[i]].  The positions of consecutive points fall
+// into one short run per coarse key of their scatter chunk, so the gathers
+// read whole lines.
+constexpr int kUnsortPer = 4;
+
+template <bool G>
+__global__ __launch_bounds__(kBlock) void unsort_k(const uint32_t* __restrict__ tpos,
+                                                   const float* __restrict__ src, int64_t n,
+                                                   float* __restrict__ out) {
+  const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kUnsortPer) + threadIdx.x;
+  uint32_t k[kUnsortPer];
+#pragma unroll
+  for (int u = 0; u < kUnsortPer; ++u) {
+    const int64_t i = i0 + u * kBlock;
+    k[u] = i < n ? min(tpos[i], (uint32_t)(n - 1)) : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < kUnsortPer; ++u) {
+    const int64_t i = i0 + u * kBlock;
+    if (i >= n) continue;
+    if constexpr (G)
+      reinterpret_cast<float4*>(out)[i] = reinterpret_cast<const float4*>(src)[k[u]];
+    else
+      out[i] = src[k[u]];
+  }
+}
+
 template <int P, Storage S>
 static hipError_t sorted_p(const DevModel& m, int kind, bool grad, const SortArgs& sa, float* out,
                            int32_t* dbg, hipStream_t st) {
@@ -2282,10 +2334,18 @@ static hipError_t sorted_p(const DevModel& m, int kind, bool grad, const SortArg
     sort_launch<false, true>(m, sa, st);
   else
     sort_launch<false, false>(m, sa, st);
+  float* dout = sa.tpos ? reinterpret_cast<float*>(sa.tmp) : out;
   if (grad)
-    decode_sorted_g<P, S, true>(m, kind, sa, out, dbg, st);
+    decode_sorted_g<P, S, true>(m, kind, sa, dout, dbg, st);
   else
-    decode_sorted_g<P, S, false>(m, kind, sa, out, dbg, st);
+    decode_sorted_g<P, S, false>(m, kind, sa, dout, dbg, st);
+  if (sa.tpos) {
+    const unsigned g = (unsigned)((sa.n + kBlock * kUnsortPer - 1) / (kBlock * kUnsortPer));
+    if (grad)
+      hipLaunchKernelGGL(unsort_k<true>, dim3(g), dim3(kBlock), 0, st, sa.tpos, dout, sa.n, out);
+    else
+      hipLaunchKernelGGL(unsort_k<false>, dim3(g), dim3(kBlock), 0, st, sa.tpos, dout, sa.n, out);
+  }
   return hipGetLastError();
 }
 
