@@ -540,8 +540,10 @@ extern "C" mfa_status mfa_model_create(const mfa_domain_desc* dom, const mfa_blo
   for (int64_t b = 0; b < nb; ++b) {
     for (int a = 0; a < 3; ++a) {
       sblk[b].lo[a] = (float)dblk[b].lo[a];
-      sblk[b].scale[a] = (float)(dblk[b].inv_ext[a] * (double)dblk[b].nsp[a]);
-      sblk[b].nsp[a] = dblk[b].nsp[a];
+      // the power-of-two factor is exact, so floor((x - lo) * tscale) is the
+      // FP32 span floor((x - lo) * scale) shifted right by sort_shift
+      sblk[b].tscale[a] = std::ldexp((float)(dblk[b].inv_ext[a] * (double)dblk[b].nsp[a]), -sort_shift);
+      sblk[b].nt[a] = tiles_of(b, sort_shift, a);
     }
     sblk[b].tile_off = dblk[b].tile_off;
   }
@@ -802,6 +804,7 @@ static mfa_status sorted_decode(mfa_model m, uint8_t* w, const SortLayout& L, co
   // coarse key's region at a time rather than over the whole output), except
   // with debug outputs, which are written at the input positions directly
   sa.tpos = L.two && !dbg ? (uint32_t*)(w + L.o_tpos) : nullptr;
+  sa.bkt = sa.tpos ? (uint16_t*)w : nullptr;         // in the region of rec (filled last)
   hipError_t e = launch_decode_sorted(m->dm, m->degree, storage_of(m), kernel_kind(m), grad, sa, out,
                                       dbg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "sorted decode launch");

@@ -54,6 +54,7 @@ static_assert(sizeof(DevBlock) == 176, "DevBlock layout");
 // whose control-point windows fit kWinMax values, made larger while the
 // model would have more than kMaxBuckets buckets.
 constexpr int kMaxBuckets = 32768;
+static_assert(kMaxBuckets <= 65536, "bucket ids are carried in 16 bits");
 
 // Sorted decode works on items of at most kTilePoints consecutive sorted
 // points of one bucket (a bucket of c points is cut into ceil(c /
@@ -88,8 +89,8 @@ constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 // checks each point's exact FP64 owner against the bucket's block.
 struct SortBlk {
   float lo[3];
-  float scale[3];        // nsp / (hi - lo)
-  int32_t nsp[3];
+  float tscale[3];       // (nsp / (hi - lo)) / 2^sort_shift: tiles per unit length
+  int32_t nt[3];         // tiles per axis, ceil(nsp / 2^sort_shift)
   int32_t tile_off;
   int32_t pad[2];
 };
@@ -232,6 +233,11 @@ struct SortArgs {
   // index, the decode writes its results at it (into tmp, no longer read),
   // and a last pass gathers them back into input order
   uint32_t* tpos;        // [n]
+  // with tpos: the histogram pass writes each point's bucket here (in input
+  // order, in the region of rec, which the bucket pass fills only later);
+  // the coarse pass carries it in the record's fourth word to the bucket
+  // pass, so that neither recomputes it
+  uint16_t* bkt;         // [n]
 };
 
 struct GridArgs {

@@ -565,7 +565,6 @@ __device__ __forceinline__ SortTabs stage_sort_tabs(const DevModel& m, float4* l
 template <bool MULTI, bool GT>
 __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTabs& tb,
                                                 const float (&x)[3]) {
-  const int sh = m.sort_shift;
   int t[3], td[3];
   uint32_t off;
   if constexpr (MULTI) {
@@ -585,11 +584,10 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTab
     const SortBlk& B = tb.blk[(b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2]];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int nsp = B.nsp[a];
-      int j = (int)((xc[a] - B.lo[a]) * B.scale[a]);
-      j = j < 0 ? 0 : (j > nsp - 1 ? nsp - 1 : j);
-      t[a] = j >> sh;
-      td[a] = (nsp + (1 << sh) - 1) >> sh;
+      const int nt = B.nt[a];
+      const int j = (int)((xc[a] - B.lo[a]) * B.tscale[a]);    // tile of the FP32 span
+      t[a] = j < 0 ? 0 : (j > nt - 1 ? nt - 1 : j);
+      td[a] = nt;
     }
     off = (uint32_t)B.tile_off;
   } else {
@@ -598,7 +596,7 @@ __device__ __forceinline__ uint32_t sort_bucket(const DevModel& m, const SortTab
     for (int a = 0; a < 3; ++a) {
       const double xa = (double)x[a];
       const double u = param_of(clampd(xa, m.box_lo[a], m.box_hi[a]), m.box_lo[a], B->inv_ext[a]);
-      const int nsp = B->nsp[a];
+      const int nsp = B->nsp[a], sh = m.sort_shift;
       t[a] = guess_span<GT>(m, B, 0, a, u) >> sh;
       td[a] = (nsp + (1 << sh) - 1) >> sh;
     }
@@ -641,7 +639,10 @@ __global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs
     }
 #pragma unroll
     for (int u = 0; u < kHistIlp; ++u)
-      if (v[u]) atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
+      if (v[u]) {
+        atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
+        if (sa.bkt) sa.bkt[c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x] = (uint16_t)b[u];
+      }
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nw; w += kHistThreads) {
@@ -708,13 +709,15 @@ __global__ __launch_bounds__(kScanThreads) void sort_scan_k(SortArgs sa) {
 }
 
 // Record i of the pass input: the points in input order, or (FROM_TMP) the
-// records of the coarse pass.
-template <bool FROM_TMP>
+// records of the coarse pass.  BR: the fourth word of a point's record is
+// its bucket (from sa.bkt) rather than its input index.
+template <bool FROM_TMP, bool BR>
 __device__ __forceinline__ float4 sort_input(const SortArgs& sa, int64_t i) {
   if constexpr (FROM_TMP)
     return sa.tmp[i];
   else
-    return make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i], __uint_as_float((uint32_t)i));
+    return make_float4(sa.xyz[i], sa.xyz[sa.n + i], sa.xyz[2 * sa.n + i],
+                       __uint_as_float(BR ? (uint32_t)sa.bkt[i] : (uint32_t)i));
 }
 
 // Exclusive scan over n <= 4 * kBlock LDS counters by the workgroup (kBlock
@@ -767,19 +770,35 @@ constexpr int kOne = 0, kCoarse = 1, kFine = 2;
 constexpr int kScatterPer = 8;
 constexpr int kScatterChunk = kBlock * kScatterPer;
 
-// One chunk of the scatter pass (see sort_scatter_k).
-template <bool MULTI, int MODE, bool GT, int kKeys>
+// The pass input records of the chunk at c0 held by this thread (record
+// l = q * kBlock + threadIdx.x in in[q]; zeros past the end).
+template <int MODE, bool BR>
+__device__ __forceinline__ void load_chunk(const SortArgs& sa, int64_t c0, float4 (&in)[kScatterPer]) {
+  const int64_t cn = min((int64_t)kScatterChunk, sa.n - c0);
+#pragma unroll
+  for (int q = 0; q < kScatterPer; ++q) {
+    const int l = q * kBlock + threadIdx.x;
+    in[q] = l < cn ? sort_input<MODE == kFine, BR>(sa, c0 + l) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// One chunk of the scatter pass (see sort_scatter_k), its records in in[].
+// BR (two levels with sa.tpos and sa.bkt): the bucket is the fourth word
+// of the pass input records; the coarse pass keeps it there, the bucket
+// pass replaces it with the record's position in the coarse order.
+template <bool MULTI, int MODE, bool GT, int kKeys, bool BR>
 __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs& sa, const SortTabs& tb,
-                                              int64_t c0, uint32_t* h, uint32_t* gbase, float4* recs,
-                                              uint16_t* keyof, uint32_t* wsum, uint32_t* s_key0,
-                                              uint32_t* s_staged) {
+                                              int64_t c0, const float4 (&in)[kScatterPer], uint32_t* h,
+                                              uint32_t* gbase, float4* recs, uint16_t* keyof,
+                                              uint32_t* wsum, uint32_t* s_key0, uint32_t* s_staged) {
   constexpr int PER = kScatterPer;
   const int cn = (int)min((int64_t)kScatterChunk, sa.n - c0);
   if constexpr (MODE == kFine) {
     if (threadIdx.x == 0) {
       const float4 r = sa.tmp[c0];
       const float x[3] = {r.x, r.y, r.z};
-      *s_key0 = (sort_bucket<MULTI, GT>(m, tb, x) >> sa.fine_shift) << sa.fine_shift;
+      const uint32_t b0 = BR ? __float_as_uint(r.w) : sort_bucket<MULTI, GT>(m, tb, x);
+      *s_key0 = (b0 >> sa.fine_shift) << sa.fine_shift;
     }
   }
   const int nk = MODE == kCoarse ? ((sa.nb + (1 << sa.fine_shift) - 1) >> sa.fine_shift)
@@ -795,11 +814,11 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
     const int l = q * kBlock + threadIdx.x;
     key[q] = 0xFFFFFFFFu;
     if (l < cn) {
-      rec[q] = sort_input<MODE == kFine>(sa, c0 + l);
+      rec[q] = in[q];
+      const float x[3] = {rec[q].x, rec[q].y, rec[q].z};
+      const uint32_t b = BR ? __float_as_uint(rec[q].w) : sort_bucket<MULTI, GT>(m, tb, x);
       if constexpr (MODE == kFine)
         if (sa.tpos) rec[q].w = __uint_as_float((uint32_t)(c0 + l));   // position in tmp
-      const float x[3] = {rec[q].x, rec[q].y, rec[q].z};
-      const uint32_t b = sort_bucket<MULTI, GT>(m, tb, x);
       if constexpr (MODE == kCoarse) {
         key[q] = b >> sa.fine_shift;
         rank[q] = atomicAdd(h + key[q], 1u);
@@ -850,8 +869,10 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
 }
 
 // The workgroups loop over the chunks (grid-stride), so the sort tables
-// are staged once per workgroup rather than once per chunk.
-template <bool MULTI, int MODE, bool GT, bool TL>
+// are staged once per workgroup rather than once per chunk; the records of
+// a workgroup's next chunk are loaded while it orders and writes the
+// current one.
+template <bool MULTI, int MODE, bool GT, bool TL, bool BR = false>
 __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa) {
   constexpr int kKeys = MODE == kCoarse ? kCoarseBuckets : (MODE == kOne ? kOneLevelBuckets : kFineKeys);
   static_assert(kKeys <= 4 * kBlock, "lds_scan covers 4 keys per thread");
@@ -863,9 +884,18 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
   __shared__ uint32_t s_key0, s_staged;
   extern __shared__ float4 sdyn[];
   const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
-  for (int64_t c0 = (int64_t)blockIdx.x * kScatterChunk; c0 < sa.n;
-       c0 += (int64_t)gridDim.x * kScatterChunk)
-    scatter_chunk<MULTI, MODE, GT, kKeys>(m, sa, tb, c0, h, gbase, recs, keyof, wsum, &s_key0, &s_staged);
+  const int64_t stride = (int64_t)gridDim.x * kScatterChunk;
+  int64_t c0 = (int64_t)blockIdx.x * kScatterChunk;
+  float4 cur[kScatterPer];
+  load_chunk<MODE, BR>(sa, c0, cur);
+  for (; c0 < sa.n; c0 += stride) {
+    float4 nxt[kScatterPer];
+    load_chunk<MODE, BR>(sa, c0 + stride, nxt);
+    scatter_chunk<MULTI, MODE, GT, kKeys, BR>(m, sa, tb, c0, cur, h, gbase, recs, keyof, wsum, &s_key0,
+                                              &s_staged);
+#pragma unroll
+    for (int q = 0; q < kScatterPer; ++q) cur[q] = nxt[q];
+  }
 }
 
 // One stored control point, converted to FP32 as the row loaders do.
@@ -947,19 +977,11 @@ __device__ __forceinline__ T uniform_copy(const T* p) {
   return b;
 }
 
-// Basis tables of the model in LDS when they hold at most kMatsLds floats
-// (clamped uniform knots share a few span shapes); else the global pool.
-// The caller synchronises before the first use (both kernels that stage
-// them do for their own LDS staging).
+// Basis tables held in LDS by the kernels that do not stage them with the
+// span records: at most kMatsLds floats (clamped uniform knots share a few
+// span shapes); models with more take kernels that read the global pool.
+// The tables are staged before the kernels' own first barrier.
 constexpr int kMatsLds = 1024;
-
-__device__ __forceinline__ const float* stage_mats(const DevModel& m, float4* lds) {
-  const int nf = m.n_mats * m.mat_stride;
-  if (nf > kMatsLds) return m.mats;
-  for (int q = threadIdx.x; q < nf / 4; q += kBlock)
-    lds[q] = reinterpret_cast<const float4*>(m.mats)[q];
-  return reinterpret_cast<const float*>(lds);
-}
 
 // Decode in sorted order, one item (a bucket, or an equal part of a bucket
 // of more than kTilePoints points) per workgroup; results go to the input
@@ -1775,11 +1797,13 @@ __device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
 
 // LDSREC: single-block model whose span records and basis tables are copied
 // into LDS once per workgroup.
+// GM: basis tables read from the global pool (models whose tables exceed
+// kMatsLds floats; multi-block kernels only), else from an LDS copy.
 template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool GT = false,
-          bool QUAD = false>
+          bool QUAD = false, bool GM = false>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
-  __shared__ float4 lmats[LDSREC ? 1 : kMatsLds / 4];
+  __shared__ float4 lmats[LDSREC || GM ? 1 : kMatsLds / 4];
   __shared__ float4 tf[256];
   __shared__ int zpre[257];
   __shared__ int wtot[kBlock / kWave];
@@ -1794,8 +1818,10 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
       reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
     R = lr;
     MT = lm;
-  } else {
-    MT = stage_mats(m, lmats);
+  } else if constexpr (!GM) {
+    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
+      lmats[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    MT = reinterpret_cast<const float*>(lmats);
   }
   stage_tf(r.tf, tf, zpre, wtot);
   if constexpr (QUAD) {
@@ -2237,7 +2263,12 @@ static void sort_launch_tl(const DevModel& m, const SortArgs& sa, size_t tabs, h
   // at most 8 workgroups per CU, each looping over chunks
   const unsigned gc = (unsigned)std::min<int64_t>((sa.n + kScatterChunk - 1) / kScatterChunk,
                                                   8 * 256);
-  if (sa.tmp) {                        // two levels: coarse runs, then buckets
+  if (sa.bkt) {                        // two levels, buckets from the histogram pass
+    hipLaunchKernelGGL((sort_scatter_k<false, kCoarse, false, false, true>), dim3(gc), dim3(kBlock), 0, st,
+                       m, sa);
+    hipLaunchKernelGGL((sort_scatter_k<false, kFine, false, false, true>), dim3(gc), dim3(kBlock), 0, st,
+                       m, sa);
+  } else if (sa.tmp) {                 // two levels: coarse runs, then buckets
     hipLaunchKernelGGL((sort_scatter_k<MULTI, kCoarse, GT, TL>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
     hipLaunchKernelGGL((sort_scatter_k<MULTI, kFine, GT, TL>), dim3(gc), dim3(kBlock), tabs, st, m, sa);
   } else {
@@ -2381,10 +2412,17 @@ static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hip
   // fit in LDS, else the multi-block kernels
   const bool lds_tabs = lds <= (size_t)kLdsRecBytes && lds_fits(lds);
   const bool multi = kind == kKindMulti || (kind == kKindGraded && !lds_tabs);
+  const bool gm = m.n_mats * m.mat_stride > kMatsLds;    // basis tables beyond the LDS copy
   // a partial render of a single-block model holds every sample (its
   // region is the model box): it is the full render, whose key is the
   // entry parameter of the model box
-  if (multi && r.partial)
+  if ((multi || !lds_tabs) && gm && r.partial)
+    hipLaunchKernelGGL((render_k<P, S, true, false, true, false, false, true>), dim3(tiles), dim3(kBlock),
+                       0, st, m, r);
+  else if ((multi || !lds_tabs) && gm)
+    hipLaunchKernelGGL((render_k<P, S, true, false, false, false, false, true>), dim3(tiles), dim3(kBlock),
+                       0, st, m, r);
+  else if (multi && r.partial)
     hipLaunchKernelGGL((render_k<P, S, true, false, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   else if (multi)       // one lane per ray (four per ray measured slower here: 12.5 vs 12.1 ms)
     hipLaunchKernelGGL((render_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);

@@ -387,9 +387,15 @@ def test_c2_render_1024_sampled(mfa, dev, c2):
 
 
 # ------------------------------------------------------------------ multi-block models
-def small_multiblock(seed=21, p=3):
+def small_multiblock(seed=21, p=3, graded=False):
     """3x2x2 blocks with uneven edges and uneven control-point counts, each
-    block fitted to one Gaussian-sum field at its Greville abscissae."""
+    block fitted to one Gaussian-sum field at its Greville abscissae.
+    graded: knots crowded towards each block's low face (u^1.5), so that
+    every span has its own basis table (hundreds of tables).  The crowding
+    is kept moderate: the FP32 rounding error of a gradient grows with the
+    chain-rule scale of the narrowest span, which the normwise tolerance
+    does not see (quadratic crowding of these small blocks exceeds it by
+    7 %, in the unsorted decode as well)."""
     rng = np.random.default_rng(seed)
     field = synth.field_c1(seed)
     edges = [np.array([0.0, 0.3, 0.55, 1.0]), np.array([0.0, 0.6, 1.0]), np.array([0.0, 0.45, 1.0])]
@@ -398,7 +404,11 @@ def small_multiblock(seed=21, p=3):
         for b1 in range(2):
             for b2 in range(2):
                 n = [int(v) for v in rng.integers(p + 2, 14, size=3)]
-                knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
+                if graded:
+                    knots = [np.concatenate([np.zeros(p + 1), np.linspace(0, 1, n[a] - p + 1)[1:-1] ** 1.5,
+                                             np.ones(p + 1)]) for a in range(3)]
+                else:
+                    knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
                 lo = np.array([edges[0][b0], edges[1][b1], edges[2][b2]])
                 hi = np.array([edges[0][b0 + 1], edges[1][b1 + 1], edges[2][b2 + 1]])
                 xs = [lo[a] + synth.greville(knots[a], p, n[a]) * (hi[a] - lo[a]) for a in range(3)]
@@ -439,6 +449,33 @@ def test_render_multiblock_rays_cross_blocks(mfa, dev, kind):
     announce(f"render multi-block {kind} {W}x{H}")
     r = check_render(mfa, dev, model, cam, params, W, H)
     assert r["samples"] > 20000
+
+
+def test_render_and_sorted_decode_multiblock_with_many_basis_tables(mfa, dev):
+    """Graded knots in every block: the basis tables exceed the kernels' LDS
+    copy, so the render reads them from the global pool and the sorted
+    decode runs one point per thread."""
+    import torch
+    model = small_multiblock(seed=23, graded=True)
+    n_tables = sum(b.ctrl.shape[a] - 3 for b in model.blocks for a in range(3))
+    assert n_tables * 28 > 1024
+    W, H = 64, 48
+    cam = synth.perspective_camera(W, H, az_deg=20, el_deg=35)
+    params = synth.render_params(model)
+    announce(f"render multi-block graded {W}x{H} ({n_tables} spans)")
+    r = check_render(mfa, dev, model, cam, params, W, H)
+    assert r["samples"] > 10000
+    rng = np.random.default_rng(6)
+    pts = rng.random((40000, 3)).astype(np.float32)
+    announce("sorted decode multi-block graded n=40000")
+    with mfa.Model(model, "f32") as M:
+        x = to_dev(pts.T, dev)
+        direct = mfa.decode_points(M, x)
+        srt = mfa.decode_points(M, x, sorted_order=True)
+        assert torch.equal(direct.view(torch.int32), srt.view(torch.int32))
+        out = srt.cpu().numpy()
+    ref = oracle_points(model, pts)
+    assert_values_close(out, ref["f"], ref["grad"], max(np.abs(blk.ctrl).max() for blk in model.blocks))
 
 
 @pytest.fixture(scope="module")
