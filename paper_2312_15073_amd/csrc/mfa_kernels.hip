@@ -625,24 +625,34 @@ __global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs
   __syncthreads();
   const int64_t c0 = (int64_t)blockIdx.x * kHistChunk;
   // kHistIlp independent points per step keep several bucket computations
-  // (chains of dependent LDS loads) in flight per thread
-  for (int q = 0; q < kHistPer; q += kHistIlp) {
-    uint32_t b[kHistIlp];
-    bool v[kHistIlp];
+  // (chains of dependent LDS loads) in flight per thread.  The points of
+  // the next step are loaded before this step's bucket ids are stored: a
+  // wait for loads also waits for the stores issued before them
+  auto load = [&](int q, float (&x)[kHistIlp][3]) {
 #pragma unroll
     for (int u = 0; u < kHistIlp; ++u) {
       const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
-      v[u] = q + u < kHistPer && i < sa.n;
-      const int64_t ic = v[u] ? i : 0;
-      const float x[3] = {sa.xyz[ic], sa.xyz[sa.n + ic], sa.xyz[2 * sa.n + ic]};
-      b[u] = sort_bucket<MULTI, GT>(m, tb, x);
+      const int64_t ic = q + u < kHistPer && i < sa.n ? i : 0;
+      x[u][0] = sa.xyz[ic];
+      x[u][1] = sa.xyz[sa.n + ic];
+      x[u][2] = sa.xyz[2 * sa.n + ic];
     }
+  };
+  float x[kHistIlp][3];
+  load(0, x);
+  for (int q = 0; q < kHistPer; q += kHistIlp) {
+    uint32_t b[kHistIlp];
 #pragma unroll
-    for (int u = 0; u < kHistIlp; ++u)
-      if (v[u]) {
+    for (int u = 0; u < kHistIlp; ++u) b[u] = sort_bucket<MULTI, GT>(m, tb, x[u]);
+    if (q + kHistIlp < kHistPer) load(q + kHistIlp, x);
+#pragma unroll
+    for (int u = 0; u < kHistIlp; ++u) {
+      const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
+      if (q + u < kHistPer && i < sa.n) {
         atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
-        if (sa.bkt) sa.bkt[c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x] = (uint16_t)b[u];
+        if (sa.bkt) sa.bkt[i] = (uint16_t)b[u];
       }
+    }
   }
   __syncthreads();
   for (int w = threadIdx.x; w < nw; w += kHistThreads) {
@@ -868,7 +878,7 @@ __device__ __forceinline__ void scatter_chunk(const DevModel& m, const SortArgs&
   __syncthreads();                             // LDS reused by the next chunk
 }
 
-// The workgroups loop over the chunks (grid-stride), so the sort tables
+// The workgroups loop over chunks (see the bands below), so the sort tables
 // are staged once per workgroup rather than once per chunk; the records of
 // a workgroup's next chunk are loaded while it orders and writes the
 // current one.
@@ -884,15 +894,21 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_k(DevModel m, SortArgs sa
   __shared__ uint32_t s_key0, s_staged;
   extern __shared__ float4 sdyn[];
   const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
-  const int64_t stride = (int64_t)gridDim.x * kScatterChunk;
-  int64_t c0 = (int64_t)blockIdx.x * kScatterChunk;
+  // the chunks in eight contiguous bands, band x to the workgroups of XCD x
+  // (workgroups go to the XCDs round-robin; the grid is a multiple of 8):
+  // the runs that one key's chunks append to are then written through one
+  // L2, where their lines fill up before they are written back
+  const int64_t nch = (sa.n + kScatterChunk - 1) / kScatterChunk;
+  const int xcd = (int)(blockIdx.x & 7u), nx = (int)(gridDim.x >> 3);
+  const int64_t hi = nch * (xcd + 1) / 8;
+  int64_t c = nch * xcd / 8 + (int64_t)(blockIdx.x >> 3);
   float4 cur[kScatterPer];
-  load_chunk<MODE, BR>(sa, c0, cur);
-  for (; c0 < sa.n; c0 += stride) {
+  load_chunk<MODE, BR>(sa, c < hi ? c * kScatterChunk : sa.n, cur);
+  for (; c < hi; c += nx) {
     float4 nxt[kScatterPer];
-    load_chunk<MODE, BR>(sa, c0 + stride, nxt);
-    scatter_chunk<MULTI, MODE, GT, kKeys, BR>(m, sa, tb, c0, cur, h, gbase, recs, keyof, wsum, &s_key0,
-                                              &s_staged);
+    load_chunk<MODE, BR>(sa, c + nx < hi ? (c + nx) * kScatterChunk : sa.n, nxt);
+    scatter_chunk<MULTI, MODE, GT, kKeys, BR>(m, sa, tb, c * kScatterChunk, cur, h, gbase, recs, keyof,
+                                              wsum, &s_key0, &s_staged);
 #pragma unroll
     for (int q = 0; q < kScatterPer; ++q) cur[q] = nxt[q];
   }
@@ -2260,9 +2276,10 @@ static void sort_launch_tl(const DevModel& m, const SortArgs& sa, size_t tabs, h
   const size_t hist_lds = tabs + (size_t)((sa.nb + 1) / 2) * 4;
   hipLaunchKernelGGL((sort_hist_k<MULTI, GT, TL>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
   hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kScanThreads), 0, st, sa);
-  // at most 8 workgroups per CU, each looping over chunks
-  const unsigned gc = (unsigned)std::min<int64_t>((sa.n + kScatterChunk - 1) / kScatterChunk,
-                                                  8 * 256);
+  // at most 8 workgroups per CU, each looping over chunks; a multiple of 8
+  // (the chunk bands of sort_scatter_k)
+  const unsigned gc = ((unsigned)std::min<int64_t>((sa.n + kScatterChunk - 1) / kScatterChunk, 8 * 256) +
+                       7u) & ~7u;
   if (sa.bkt) {                        // two levels, buckets from the histogram pass
     hipLaunchKernelGGL((sort_scatter_k<false, kCoarse, false, false, true>), dim3(gc), dim3(kBlock), 0, st,
                        m, sa);
