@@ -1006,12 +1006,14 @@ extern "C" mfa_status mfa_render_volume(const mfa_volume_desc* vol, const mfa_ca
     v.lo[a] = vol->lo[a];
     v.hi[a] = vol->hi[a];
     v.h[a] = (vol->hi[a] - vol->lo[a]) / (double)(vol->dims[a] - 1);
-    v.inv_h[a] = (float)(1.0 / v.h[a]);
+    v.inv_hd[a] = 1.0 / v.h[a];
+    v.inv_h[a] = (float)v.inv_hd[a];
     hmin = std::fmin(hmin, v.h[a]);
   }
   if (vol->kind != MFA_FIELD_MARSCHNER_LOBB && !vol->samples)
     return fail(MFA_E_ARG, "null samples");
   v.v = vol->samples;
+  v.bytes = 4ll * v.n[0] * v.n[1] * v.n[2];
   RenderArgs r;
   mfa_status st = render_args_core(hmin, cam, rp, w, h, rgba, dbg, &r, true);
   if (st != MFA_OK) return st;

@@ -286,7 +286,9 @@ struct VolArgs {
   const float* v;
   int32_t n[3];
   double lo[3], hi[3], h[3];
+  double inv_hd[3];      // 1 / h (FP64 division on the host)
   float inv_h[3];
+  int64_t bytes;         // sample bytes; stencil rows by buffer loads below 4 GiB
 };
 
 // Depth-ordered compositing of up to kMaxPartials partial images.

@@ -2097,54 +2097,89 @@ __device__ __forceinline__ float4 volume_field(const VolArgs& v, const double (&
   } else {
     constexpr int K = KIND == MFA_FILTER_TRILINEAR ? 2 : 4;
     constexpr int OFF = KIND == MFA_FILTER_TRILINEAR ? 0 : -1;
-    int idx[3][K];
+    int c[3];
     float w[3][K], dw[3][K];
+    // grid coordinate in FP64 through the host's 1 / h (a cell face may go
+    // to either neighbour, between which every filter here is continuous)
+    bool inner = v.bytes < 0xFFFFFFF0ll;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double g = clampd((x[a] - v.lo[a]) / v.h[a], 0.0, (double)(v.n[a] - 1));
-      const int c = min((int)floor(g), v.n[a] - 2);
-      filter_weights<KIND, K>((float)(g - (double)c), w[a], dw[a]);
-#pragma unroll
-      for (int q = 0; q < K; ++q) idx[a][q] = min(max(c + OFF + q, 0), v.n[a] - 1);
+      const double g = clampd((x[a] - v.lo[a]) * v.inv_hd[a], 0.0, (double)(v.n[a] - 1));
+      c[a] = min((int)floor(g), v.n[a] - 2);
+      filter_weights<KIND, K>((float)(g - (double)c[a]), w[a], dw[a]);
+      inner = inner && c[a] + OFF >= 0 && c[a] + OFF + K - 1 <= v.n[a] - 1;
     }
     float f = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+    auto contract = [&](auto&& row) {
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      float y = 0.f, yy = 0.f, yz = 0.f;
+      for (int i = 0; i < K; ++i) {
+        float y = 0.f, yy = 0.f, yz = 0.f;
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const float* row = v.v + ((int64_t)idx[0][i] * v.n[1] + idx[1][j]) * (int64_t)v.n[2];
-        float z = 0.f, zd = 0.f;
+        for (int j = 0; j < K; ++j) {
+          float sv[K];
+          row(i, j, sv);
+          float z = 0.f, zd = 0.f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float sv = row[idx[2][k]];
-          z = fmaf(w[2][k], sv, z);
-          zd = fmaf(dw[2][k], sv, zd);
+          for (int k = 0; k < K; ++k) {
+            z = fmaf(w[2][k], sv[k], z);
+            zd = fmaf(dw[2][k], sv[k], zd);
+          }
+          y = fmaf(w[1][j], z, y);
+          yy = fmaf(dw[1][j], z, yy);
+          yz = fmaf(w[1][j], zd, yz);
         }
-        y = fmaf(w[1][j], z, y);
-        yy = fmaf(dw[1][j], z, yy);
-        yz = fmaf(w[1][j], zd, yz);
+        f = fmaf(w[0][i], y, f);
+        fx = fmaf(dw[0][i], y, fx);
+        fy = fmaf(w[0][i], yy, fy);
+        fz = fmaf(w[0][i], yz, fz);
       }
-      f = fmaf(w[0][i], y, f);
-      fx = fmaf(dw[0][i], y, fx);
-      fy = fmaf(w[0][i], yy, fy);
-      fz = fmaf(w[0][i], yz, fz);
+    };
+    if (inner) {
+      // the whole stencil inside the grid: rows of K consecutive samples,
+      // one vector load each at a lane offset plus a uniform row offset
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(v.v, v.bytes);
+      const uint32_t n1 = (uint32_t)v.n[1], n2 = (uint32_t)v.n[2];
+      const uint32_t e0 = ((uint32_t)(c[0] + OFF) * n1 + (uint32_t)(c[1] + OFF)) * n2 + (uint32_t)(c[2] + OFF);
+      contract([&](int i, int j, float (&sv)[K]) {
+        uint32_t wd[K];
+        load_words<K>(rs, e0 * 4u, ((uint32_t)i * n1 * n2 + (uint32_t)j * n2) * 4u, wd);
+#pragma unroll
+        for (int k = 0; k < K; ++k) sv[k] = __uint_as_float(wd[k]);
+      });
+    } else {
+      // stencil indices outside the grid repeat the edge sample
+      int idx[3][K];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < K; ++q) idx[a][q] = min(max(c[a] + OFF + q, 0), v.n[a] - 1);
+      contract([&](int i, int j, float (&sv)[K]) {
+        const float* row = v.v + ((int64_t)idx[0][i] * v.n[1] + idx[1][j]) * (int64_t)v.n[2];
+#pragma unroll
+        for (int k = 0; k < K; ++k) sv[k] = row[idx[2][k]];
+      });
     }
     return make_float4(f, fx * v.inv_h[0], fy * v.inv_h[1], fz * v.inv_h[2]);
   }
 }
 
+// Four lanes per ray, as in the model renderer: a wave holds a 4x4 pixel
+// tile, lane s of a ray's group evaluates samples s, s + 4, ..., and the
+// group composites its four shaded samples in ray order with the
+// operations of one lane stepping through them (a sample past the end of
+// the ray enters with opacity 0, which leaves the pixel exactly unchanged),
+// stopping at the same sample.
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void volume_k(VolArgs v, RenderArgs r) {
   __shared__ float4 tf[256];
   __shared__ int zpre[257];
   __shared__ int wtot[kBlock / kWave];
   stage_tf(r.tf, tf, zpre, wtot);
-  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+  const int tx = (r.w + 7) / 8, ty = (r.h + 7) / 8;
   const int tile = frame_tile(blockIdx.x, tx, ty);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
-  const int j = (tile / tx) * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, s = lane & 3;
+  const int i = (tile % tx) * 8 + (wave & 1) * 4 + ((lane >> 2) & 3);
+  const int j = (tile / tx) * 8 + (wave >> 1) * 4 + (lane >> 4);
   const bool pix = i < r.w && j < r.h;
   Ray ray;
   ray.K = 0;
@@ -2159,18 +2194,35 @@ __global__ __launch_bounds__(kBlock) void volume_k(VolArgs v, RenderArgs r) {
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
   int used = 0;
   bool done = false;
-  for (int k = 0;; ++k) {
-    const bool act = pix && !done && k < ray.K;
+  for (int kb = 0;; kb += 4) {
+    const bool act = pix && !done && kb < ray.K;     // the same in the four lanes of a ray
     if (__ballot(act) == 0) break;                 // whole wave finished
     if (!act) continue;
-    double x[3];
-    sample_point(ray, r.step, k, x);
-    const float alpha = shade_over(volume_field<KIND>(v, x), L, tf, r, C0, C1, C2, A);
-    used = k + 1;
-    if (r.alpha) r.alpha[pid * r.alpha_stride + k] = alpha;
-    done = A >= r.ert_alpha;
+    const int k = kb + s;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < ray.K) {
+      double x[3];
+      sample_point(ray, r.step, k, x);
+      q = shade_sample(volume_field<KIND>(v, x), L, tf, r);
+    }
+    const float4 q0 = quad_bcast4<0>(q), q1 = quad_bcast4<1>(q), q2 = quad_bcast4<2>(q),
+                 q3 = quad_bcast4<3>(q);
+    int stop = 0;                  // 1 + index of the terminating sample, 0: none
+    auto step = [&](float4 qt, int t) {
+      const bool live = stop == 0;
+      qt.w = live ? qt.w : 0.f;
+      over(qt, C0, C1, C2, A);
+      if (live && A >= r.ert_alpha) stop = t + 1;
+    };
+    step(q0, 0);
+    step(q1, 1);
+    step(q2, 2);
+    step(q3, 3);
+    done = stop != 0;
+    used = done ? kb + stop : min(kb + 4, ray.K);
+    if (r.alpha && k < used) r.alpha[pid * r.alpha_stride + k] = q.w;
   }
-  if (pix) {
+  if (pix && s == 0) {
     reinterpret_cast<float4*>(r.rgba)[pid] = make_float4(C0, C1, C2, A);
     if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, used);
     if (r.neval) r.neval[pid] = used;
@@ -2560,7 +2612,7 @@ hipError_t launch_iso(const DevModel& m, int p, Storage s, int kind, const Rende
 }
 
 hipError_t launch_volume(const VolArgs& v, int kind, const RenderArgs& r, hipStream_t st) {
-  const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  const int tiles = ((r.w + 7) / 8) * ((r.h + 7) / 8);     // 8x8 pixels, four lanes per ray
   switch (kind) {
     case MFA_FILTER_TRILINEAR:
       hipLaunchKernelGGL(volume_k<MFA_FILTER_TRILINEAR>, dim3(tiles), dim3(kBlock), 0, st, v, r);

@@ -5,8 +5,10 @@ Marschner-Lobb render (mfa_render_volume) against the FP64 oracle
 The acceptance is that of the MFA renders: K per ray exact; samples used
 equal to an exact FP32 replay of the kernel's own opacities, and to the
 oracle's outside the termination band (in-band rays within one sample);
-image RMSE <= 1e-5 and max-abs <= 1e-3 outside the band.  The cell of a
-sample is decided in FP64 by the same operations on both sides.
+image RMSE <= 1e-5 and max-abs <= 1e-3 outside the band.  The grid
+coordinate of a sample is taken in FP64 on both sides (the oracle divides
+by h, the kernel multiplies by the host's 1 / h): at a cell face the two
+may pick neighbouring cells, between which the filters are continuous.
 """
 import numpy as np
 import pytest
