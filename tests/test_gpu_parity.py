@@ -526,13 +526,20 @@ def test_c4_render_2048_sampled(mfa, dev, c4):
 
 # ------------------------------------------------------------------ sorted decode
 def _sorted_matches_unsorted(mfa, dev, model, pts, storage="f32"):
+    """Sorted decode against the unsorted one, bit for bit: with debug
+    outputs (results written at the input positions directly) and without
+    (above 1024 buckets the results then go through the coarse order and
+    are gathered back)."""
     with mfa.Model(model, storage) as M:
         x = to_dev(pts, dev)
         a, da = mfa.decode_points(M, x, dbg=True)
         b, db = mfa.decode_points(M, x, dbg=True, sorted_order=True)
-        a, da, b, db = a.cpu().numpy(), da.cpu().numpy(), b.cpu().numpy(), db.cpu().numpy()
+        c = mfa.decode_points(M, x, sorted_order=True)
+        a, da, b, db, c = (a.cpu().numpy(), da.cpu().numpy(), b.cpu().numpy(), db.cpu().numpy(),
+                           c.cpu().numpy())
     np.testing.assert_array_equal(b.view(np.uint32), a.view(np.uint32))   # bit for bit
     np.testing.assert_array_equal(db, da)
+    np.testing.assert_array_equal(c.view(np.uint32), a.view(np.uint32))
     return a
 
 
@@ -641,13 +648,17 @@ def test_sorted_decode_c4_2e7(mfa, dev, c4):
 
 
 # ------------------------------------------------------------------ value-only queries
-@pytest.mark.parametrize("which", ["c1", "graded", "multiblock"])
+@pytest.mark.parametrize("which", ["c1", "graded", "multiblock", "c4"])
 @pytest.mark.parametrize("sorted_order", [False, True])
-def test_decode_points_value_only(mfa, dev, which, sorted_order):
+def test_decode_points_value_only(mfa, dev, which, sorted_order, request):
     """Value-only queries (Fig. 8a): the value of the value+gradient query,
     bit for bit (the same sums; the gradient terms are dropped), and the
-    oracle's value within the FP32 tolerance."""
-    if which == "c1":
+    oracle's value within the FP32 tolerance.  The 8x8x8-block model's
+    sorted decode takes the two-level sort and the gather of its results
+    from the coarse order."""
+    if which == "c4":
+        model = request.getfixturevalue("c4")
+    elif which == "c1":
         model = synth.model_c1()
     elif which == "graded":
         p, ns = 3, (41, 37, 29)

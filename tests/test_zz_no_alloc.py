@@ -33,11 +33,14 @@ def _multiblock():
     return synth.ModelSpec([2, 2, 2], np.zeros(3), np.ones(3), edges, blocks, voxel=1.0 / 63)
 
 
-@pytest.mark.parametrize("which", ["c1", "c2", "multiblock"])
+@pytest.mark.parametrize("which", ["c1", "c2", "multiblock", "c4"])
 def test_noalloc_sorted_decode_equals_sorted_decode(dev, which):
+    """c4 (the 8x8x8-block model, more than 1024 buckets) takes the
+    two-level sort, 36 bytes of scratch per point."""
     import torch
     import paper_2312_15073_amd as mfa
-    spec = {"c1": synth.model_c1, "c2": synth.model_c2, "multiblock": _multiblock}[which]()
+    spec = {"c1": synth.model_c1, "c2": synth.model_c2, "multiblock": _multiblock,
+            "c4": synth.model_c4}[which]()
     pmax = max(np.abs(b.ctrl).max() for b in spec.blocks)
     with mfa.Model(spec, "f32") as M:
         for k, n in enumerate((1_500_000, 40_001)):        # second call smaller
