@@ -2026,7 +2026,183 @@ __device__ __forceinline__ void iso_tile(const DevModel& m, const RenderArgs& r,
   }
 }
 
-template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false>
+// Four lanes per ray (single-block full frames): lane s of a ray's group
+// decides the side of samples s, s + 4, ... (by the bounds of the first
+// cell level that decides it, else by its value), and the group takes the
+// first side change in ray order.  A group whose last sample lies in a
+// super cell wholly on one side leaps, as the one-lane search does, to the
+// estimated last sample inside that cell; the leap holds if the group's
+// next first sample lies in the same cell (every sample between then does:
+// the span index per axis is monotone along the ray) and is undone
+// otherwise.  Two lanes then evaluate the samples around the hit, and the
+// hit point is shaded as in the one-lane search.
+template <int P, Storage S, bool MULTI, bool GT = false>
+__device__ __forceinline__ void iso_tile4(const DevModel& m, const RenderArgs& r, int tile,
+                                          const SpanRec* __restrict__ R,
+                                          const float* __restrict__ MT) {
+  static_assert(!MULTI, "four lanes per ray: single-block models");
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, s = lane & 3;
+  const int tx = (r.w + 7) / 8;
+  const int i = (tile % tx) * 8 + (wave & 1) * 4 + ((lane >> 2) & 3);
+  const int j = (tile / tx) * 8 + (wave >> 1) * 4 + (lane >> 4);
+  const bool pix = i < r.w && j < r.h;
+  Ray ray;
+  ray.K = 0;
+  if (pix) ray = make_ray(m, r, i, j);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
+  const int64_t pid = (int64_t)j * r.w + i;
+  const DevBlock* __restrict__ B = &m.b0;
+  auto bcast = [](int v, int t) {
+    const float f = __int_as_float(v);
+    return __float_as_int(t == 0 ? quad_bcast<0>(f) : t == 1 ? quad_bcast<1>(f)
+                          : t == 2 ? quad_bcast<2>(f) : quad_bcast<3>(f));
+  };
+  int hit = -1, nev = 0, side_prev = -1;          // side_prev: the side of sample kb - 1
+  // cached sides of the last coarse, fine and macro cell (-1: undecided)
+  int last_c[3] = {-1, -1, -1}, side_c[3] = {-1, -1, -1};
+  // leap state of the group: first skipped sample, level and cell of a
+  // pending leap; the cell (2 * cell + level) where a leap failed
+  int kb = 0, from = -1, lvl = 0, cell = -1, noleap = -1;
+  for (;;) {
+    const bool act = pix && hit < 0 && kb < ray.K;   // the same in the four lanes of a ray
+    if (__ballot(act) == 0) break;                  // whole wave finished
+    if (!act) continue;
+    const int k = kb + s;
+    int side = -1;                                  // -1: past the end of the ray
+    int c[3] = {-1, -1, -1}, lv = 3, js[3] = {0, 0, 0};
+    if (k < ray.K) {
+      double x[3];
+      sample_point(ray, r.step, k, x);
+      const Loc Lc = locate<P, MULTI, GT>(m, R, x);
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        const int sh = m.sc_shift[l];
+        c[l] = B->sc_off[l] + (((Lc.j[0] >> sh) * B->sc[l][1] + (Lc.j[1] >> sh)) * B->sc[l][2] +
+                               (Lc.j[2] >> sh));
+      }
+      c[2] = Lc.mc;
+      uint32_t bh[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        if (c[l] != last_c[l]) bh[l] = l < 2 ? m.scb[l][c[l]] : m.mcb[c[l]];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        if (c[l] != last_c[l]) {
+          side_c[l] = iso_side(bh[l], r.iso);
+          last_c[l] = c[l];
+        }
+      lv = side_c[0] >= 0 ? 0 : (side_c[1] >= 0 ? 1 : (side_c[2] >= 0 ? 2 : 3));
+      if (lv < 3) {
+        side = side_c[lv];
+      } else {
+        side = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x >= r.iso ? 1 : 0;
+        ++nev;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) js[a] = Lc.j[a];
+    }
+    if (from >= 0) {                                // landing of a leap at level lvl
+      const int cl = bcast(lvl == 0 ? c[0] : c[1], 0);
+      if (cl != cell) {                             // left the cell: undo
+        noleap = 2 * cell + lvl;
+        kb = from;
+        from = -1;
+        continue;
+      }
+      from = -1;                                    // the samples passed had side side_prev
+    }
+    // the first side change among the group's samples, in ray order
+    int sp = side_prev, th = -1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int st = bcast(side, t);
+      if (th < 0 && st >= 0) {
+        if (kb + t > 0 && st != sp) th = t;
+        else sp = st;
+      }
+    }
+    if (th >= 0) {
+      hit = kb + th;
+      continue;
+    }
+    side_prev = sp;
+    // leap from the group's last sample when its super cell (level 0 or 1)
+    // lies wholly on one side: to the estimated last sample inside the cell
+    // (FP32 exit through the cell faces at their stored knots, less one step)
+    int kl = kb + 4;
+    const int lv3 = bcast(lv, 3);
+    const int c3 = bcast(lv == 0 ? c[0] : c[1], 3);
+    if (lv3 < 2 && 2 * c3 + lv3 != noleap) {
+      const int sh = m.sc_shift[lv3];
+      float te = __builtin_inff();
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ja = bcast(js[a], 3);
+        if (ray.d[a] == 0.0) continue;
+        const int cc = ja >> sh;
+        const int jb = ray.d[a] > 0.0 ? min((cc + 1) << sh, B->nsp[a]) : (cc << sh);
+        const float xb = fmaf(face_knot<GT>(m, R, B, 0, a, jb), (float)B->ext[a], (float)B->lo[a]);
+        te = fminf(te, (xb - (float)ray.o[a]) * __builtin_amdgcn_rcpf((float)ray.d[a]));
+      }
+      kl = max(kb + 4, (int)fminf(floorf(fmaf(te - (float)ray.t_near, (float)r.inv_step, -1.f)),
+                                  (float)(ray.K - 1)));
+    }
+    if (kl > kb + 4) {
+      from = kb + 4;
+      lvl = lv3;
+      cell = c3;
+    }
+    kb = kl;
+  }
+  // the values at the two samples around the hit (lanes 0 and 1), then the
+  // hit point, as in the one-lane search
+  float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+  double depth = __builtin_inf();
+  if (pix && hit > 0) {
+    float f = 0.f;
+    if (s < 2) {
+      double x[3];
+      sample_point(ray, r.step, hit - 1 + s, x);
+      const Loc Lc = locate<P, MULTI, GT>(m, R, x);
+      f = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat).x;
+      ++nev;
+    }
+    const float fa = quad_bcast<0>(f), fb = quad_bcast<1>(f);
+    // fa and fb lie on different sides of iso, so w is in [0, 1]
+    const float w = (r.iso - fa) / (fb - fa);
+    double xs[3];
+    {
+#pragma clang fp contract(off)
+      depth = ray.t_near + (((double)(hit - 1) + 0.5) + (double)w) * r.step;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xs[a] = ray.o[a] + depth * ray.d[a];
+    }
+    const Loc Ls = locate<P, MULTI, GT>(m, R, xs);
+    const float4 e = evaluate<P, S, !MULTI>(Ls, rs, MT, m.mat_stride, m.imat);
+    if (s == 0) ++nev;
+    const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
+    float L[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L[a] = (float)(-ray.d[a] / dn);
+    const float gg = e.y * e.y + e.z * e.z + e.w * e.w;
+    const float inv = __builtin_amdgcn_rsqf(fmaxf(gg, r.g0 * r.g0));
+    const float diff = fabsf((e.y * L[0] + e.z * L[1] + e.w * L[2]) * inv);
+    const float shade = fmaf(r.kd, diff, r.ka);
+    const float ks = r.ks * spec_pow(diff, r.shininess);
+    out = make_float4(fmaf(r.iso_rgb[0], shade, ks), fmaf(r.iso_rgb[1], shade, ks),
+                      fmaf(r.iso_rgb[2], shade, ks), 1.f);
+  }
+  // values evaluated for the ray: the sum over its four lanes
+  nev = bcast(nev, 0) + bcast(nev, 1) + bcast(nev, 2) + bcast(nev, 3);
+  if (pix && s == 0) {
+    reinterpret_cast<float4*>(r.rgba)[pid] = out;
+    if (r.key) r.key[pid] = depth;
+    if (r.nsamp) reinterpret_cast<int2*>(r.nsamp)[pid] = make_int2(ray.K, hit);
+    if (r.neval) r.neval[pid] = nev;
+  }
+}
+
+template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false, bool QUAD = false>
 __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   const SpanRec* R = m.rec;
@@ -2042,8 +2218,13 @@ __global__ __launch_bounds__(kBlock) void iso_k(DevModel m, RenderArgs r) {
     MT = lm;
     __syncthreads();
   }
-  const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-  iso_tile<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
+  if constexpr (QUAD) {
+    const int tx = (r.w + 7) / 8, ty = (r.h + 7) / 8;
+    iso_tile4<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
+  } else {
+    const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
+    iso_tile<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT);
+  }
 }
 
 // ------------------------------------------------------------------ K9: local-filter volumes
@@ -2517,14 +2698,15 @@ static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hip
 template <int P, Storage S>
 static hipError_t iso_p(const DevModel& m, int kind, const RenderArgs& r, hipStream_t st) {
   const int tiles = ((r.w + kTile - 1) / kTile) * ((r.h + kTile - 1) / kTile);
+  const int tiles8 = ((r.w + 7) / 8) * ((r.h + 7) / 8);
   const size_t lds = (size_t)m.n_rec * sizeof(SpanRec) + (size_t)m.n_mats * m.mat_stride * 4;
   const bool lds_tabs = lds <= (size_t)kLdsRecBytes && lds_fits(lds);
   if (kind == kKindMulti || (kind == kKindGraded && !lds_tabs))
     hipLaunchKernelGGL((iso_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
-  else if (kind == kKindGraded)
-    hipLaunchKernelGGL((iso_k<P, S, false, true, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
+  else if (kind == kKindGraded)        // four lanes per ray
+    hipLaunchKernelGGL((iso_k<P, S, false, true, true, true>), dim3(tiles8), dim3(kBlock), lds, st, m, r);
   else if (lds_tabs)
-    hipLaunchKernelGGL((iso_k<P, S, false, true>), dim3(tiles), dim3(kBlock), lds, st, m, r);
+    hipLaunchKernelGGL((iso_k<P, S, false, true, false, true>), dim3(tiles8), dim3(kBlock), lds, st, m, r);
   else
     hipLaunchKernelGGL((iso_k<P, S, false, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   return hipGetLastError();
