@@ -624,6 +624,96 @@ mfa_status pseudo_inverse(const double* T, int p, int n, const double* u, int N,
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// The fit's first mode product without the dense pseudo-inverse: per
+// fiber (i1, i2) of the samples, Z = B0^T F (p + 1 non-zeros per sample),
+// then the two banded triangular solves L y = Z, L^T x = y with the host's
+// Cholesky factor of B0^T B0 (bandwidth p), so x = (B0^T B0)^-1 B0^T F, the
+// fiber of F x_0 B0+.  The samples are taken in the order of their spans
+// (perm), so a control point's sum is complete once a sample past its
+// support arrives and it enters the forward solve at once; the backward
+// solve runs over the stored y.  One thread per fiber, fibers consecutive
+// across the lanes, so every sample and control-point access is one
+// coalesced row; the tables (uniform over the lanes) come through the
+// scalar cache.  O((p + 1)(N0 + 2 n0)) FP64 operations and 4 N0 + 24 n0
+// bytes per fiber, against 2 N0 n0 operations for the dense product.
+constexpr int kBand = kMaxDegree + 1;     // window of partial sums (p + 1 <= kBand)
+constexpr int kBandUnroll = 8;            // sample loads in flight per thread
+
+__global__ __launch_bounds__(256) void band_fit0_k(const float* __restrict__ f, double* __restrict__ y,
+                                                   const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ c0t,
+                                                   const double* __restrict__ bv,
+                                                   const double* __restrict__ lf,
+                                                   const double* __restrict__ inv_d,
+                                                   const int32_t* __restrict__ pdeg, int64_t M, int N0,
+                                                   int n0) {
+  const int64_t fib = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (fib >= M) return;                  // no barriers below
+  const int p = pdeg[0], w = p + 1;
+  double z[kBand];                       // partial sums of control points cn .. cn + kBand - 1
+  double yh[kBand - 1];                  // y[cn - 1 - d] at d
+#pragma unroll
+  for (int r = 0; r < kBand; ++r) z[r] = 0.0;
+#pragma unroll
+  for (int d = 0; d < kBand - 1; ++d) yh[d] = 0.0;
+  int cn = 0;                            // next control point to solve for
+  auto solve_next = [&]() {              // y[cn] = (Z[cn] - sum_d L(cn, cn - d) y[cn - d]) / L(cn, cn)
+    double v = z[0];
+#pragma unroll
+    for (int d = 1; d < kBand; ++d)
+      if (d <= p) v -= lf[(int64_t)cn * w + d] * yh[d - 1];   // L(cn, cn - d) = 0 for cn < d
+    v *= inv_d[cn];
+    y[(int64_t)cn * M + fib] = v;
+#pragma unroll
+    for (int d = kBand - 2; d > 0; --d) yh[d] = yh[d - 1];
+    yh[0] = v;
+#pragma unroll
+    for (int r = 0; r < kBand - 1; ++r) z[r] = z[r + 1];
+    z[kBand - 1] = 0.0;
+    ++cn;
+  };
+  for (int i0 = 0; i0 < N0; i0 += kBandUnroll) {
+    float fv[kBandUnroll];             // loads without branches, all in flight together
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) fv[u] = f[(int64_t)perm[min(i0 + u, N0 - 1)] * M + fib];
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) {
+      const int i = i0 + u;
+      if (i >= N0) break;
+      const int c = c0t[i];
+      while (cn < c) solve_next();       // no later sample reaches them
+      const double v = (double)fv[u];
+#pragma unroll
+      for (int r = 0; r < kBand; ++r)
+        if (r <= p) z[r] = fma(bv[(int64_t)i * w + r], v, z[r]);
+    }
+  }
+  while (cn < n0) solve_next();
+  // x[j] = (y[j] - sum_d L(j + d, j) x[j + d]) / L(j, j), from the last
+  double xh[kBand - 1];                  // x[j + 1 + d] at d
+#pragma unroll
+  for (int d = 0; d < kBand - 1; ++d) xh[d] = 0.0;
+  for (int j1 = n0 - 1; j1 >= 0; j1 -= kBandUnroll) {
+    double yv[kBandUnroll];
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) yv[u] = y[(int64_t)max(j1 - u, 0) * M + fib];
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) {
+      const int j = j1 - u;
+      if (j < 0) break;
+      double v = yv[u];
+#pragma unroll
+      for (int d = 1; d < kBand; ++d)
+        if (d <= p && j + d < n0) v -= lf[(int64_t)(j + d) * w + d] * xh[d - 1];
+      v *= inv_d[j];
+      y[(int64_t)j * M + fib] = v;
+#pragma unroll
+      for (int d = kBand - 2; d > 0; --d) xh[d] = xh[d - 1];
+      xh[0] = v;
+    }
+  }
+}
+
 // The three mode products of a fit, P = F x_0 B0+ x_1 B1+ x_2 B2+, with the
 // tables qt[a] = B_a+ transposed (N_a x n_a).  The first, by far the
 // largest (N = N1 N2 columns), runs 32 x 64 tiles per wave (fewer operand
@@ -751,16 +841,32 @@ __global__ __launch_bounds__(256) void minmax_k(const float* __restrict__ f, int
   if (threadIdx.x == 0) part[blockIdx.x] = make_float2(lo[0], hi[0]);
 }
 
-// Workspace layout (FP64): Q0, Q1, Q2 (B_a+ transposed), then Y0 = F x_0 B0+ (n0 x N1 x N2)
-// and Y1 = Y0 x_1 B1+ (stored N2 x n0 x n1).
+// Workspace layout: the banded tables of axis 0 (sample order, control
+// point of each support, basis values, Cholesky factor rows, reciprocal
+// diagonal, degree), Q1, Q2 (B_a+ transposed, FP64), then Y0 = F x_0 B0+
+// (n0 x N1 x N2) and Y1 = Y0 x_1 B1+ (stored N2 x n0 x n1).
 struct EncodeLayout {
-  size_t q[3], y0, y1, total;
+  size_t perm, c0, bv, lf, inv_d, pdeg, q[3], y0, y1, total;
 };
 
 EncodeLayout encode_layout(const int32_t res[3], const int32_t n_ctrl[3]) {
   EncodeLayout L{};
   size_t o = 0;
-  for (int a = 0; a < 3; ++a) {
+  const size_t N0 = res[0], n0 = n_ctrl[0], w = kMaxDegree + 1;
+  L.perm = o;
+  o += align256(4 * N0);
+  L.c0 = o;
+  o += align256(4 * N0);
+  L.bv = o;
+  o += align256(8 * N0 * w);
+  L.lf = o;
+  o += align256(8 * n0 * w);
+  L.inv_d = o;
+  o += align256(8 * n0);
+  L.pdeg = o;
+  o += 256;
+  L.q[0] = 0;                            // not used: axis 0 takes the banded route
+  for (int a = 1; a < 3; ++a) {
     L.q[a] = o;
     o += align256(8 * (size_t)n_ctrl[a] * (size_t)res[a]);
   }
@@ -815,6 +921,11 @@ extern "C" mfa_status mfa_encode_plan(const int32_t res[3], const double* const 
     return fail(MFA_E_ARG, "workspace of %lld bytes, %lld needed", (long long)work_bytes,
                 (long long)lay.total);
   std::vector<double> Q[3];
+  // axis 0: the samples in span order, their supports and basis values, the
+  // Cholesky factor of the Gram matrix and its reciprocal diagonal
+  std::vector<int32_t> perm, c0s;
+  std::vector<double> bvs, lf, inv_d;
+  int32_t p0 = degree[0];
   for (int a = 0; a < 3; ++a) {
     const int p = degree[a], n = n_ctrl[a], N = res[a];
     if (!axis_u[a]) return fail(MFA_E_ARG, "axis %d: null parameter table", a);
@@ -829,15 +940,42 @@ extern "C" mfa_status mfa_encode_plan(const int32_t res[3], const double* const 
     } else {
       default_knots(n, p, T.data());
     }
+    if (a == 0) {
+      std::vector<int> s;
+      std::vector<double> Bv;
+      st = gram_factor(T.data(), p, n, axis_u[a], N, a, lf, s, Bv);
+      if (st != MFA_OK) return st;
+      const int w = p + 1;
+      perm.resize(N);
+      for (int i = 0; i < N; ++i) perm[i] = i;
+      std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return s[x] < s[y]; });
+      c0s.resize(N);
+      bvs.resize((size_t)N * w);
+      for (int k = 0; k < N; ++k) {
+        c0s[k] = s[perm[k]] - p;
+        std::copy(&Bv[(size_t)perm[k] * w], &Bv[(size_t)perm[k] * w] + w, &bvs[(size_t)k * w]);
+      }
+      inv_d.resize(n);
+      for (int j = 0; j < n; ++j) inv_d[j] = 1.0 / lf[(size_t)j * w];
+      continue;
+    }
     st = pseudo_inverse(T.data(), p, n, axis_u[a], N, a, Q[a]);
     if (st != MFA_OK) return st;
   }
   hipStream_t hs = (hipStream_t)stream;
   uint8_t* wb = static_cast<uint8_t*>(work);
-  for (int a = 0; a < 3; ++a) {
-    hipError_t e = hipMemcpyAsync(wb + lay.q[a], Q[a].data(), Q[a].size() * sizeof(double),
-                                  hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(e, "encode: pseudo-inverse upload");
+  struct Up {
+    size_t off;
+    const void* src;
+    size_t bytes;
+  };
+  const Up ups[] = {{lay.perm, perm.data(), perm.size() * 4},  {lay.c0, c0s.data(), c0s.size() * 4},
+                    {lay.bv, bvs.data(), bvs.size() * 8},      {lay.lf, lf.data(), lf.size() * 8},
+                    {lay.inv_d, inv_d.data(), inv_d.size() * 8}, {lay.pdeg, &p0, 4},
+                    {lay.q[1], Q[1].data(), Q[1].size() * 8},  {lay.q[2], Q[2].data(), Q[2].size() * 8}};
+  for (const Up& u : ups) {
+    hipError_t e = hipMemcpyAsync(wb + u.off, u.src, u.bytes, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "encode: table upload");
   }
   // the host tables must outlive their upload: wait for it (and for the
   // work queued before it on the stream)
@@ -858,15 +996,27 @@ extern "C" mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctr
                 (long long)lay.total);
   hipStream_t hs = (hipStream_t)stream;
   uint8_t* wb = static_cast<uint8_t*>(work);
-  const double* dq[3];
-  for (int a = 0; a < 3; ++a) dq[a] = reinterpret_cast<const double*>(wb + lay.q[a]);
-  double* y0 = reinterpret_cast<double*>(wb + lay.y0);
-  double* y1 = reinterpret_cast<double*>(wb + lay.y1);
+  auto at = [&](size_t off) { return reinterpret_cast<double*>(wb + off); };
+  double* y0 = at(lay.y0);
+  double* y1 = at(lay.y1);
   const int64_t N0 = res[0], N1 = res[1], N2 = res[2];
   const int64_t n0 = n_ctrl[0], n1 = n_ctrl[1], n2 = n_ctrl[2];
-  // tables dq[a] are B_a+ transposed: N_a x n_a
-  const int64_t N[3] = {N0, N1, N2}, n[3] = {n0, n1, n2};
-  hipError_t e = run_fit(N, n, values, ctrl, dq, y0, y1, hs);
+  // Y0 = F x_0 B0+ by the banded route, then the x_1 and x_2 products as
+  // GEMMs with the tables B_a+ transposed (N_a x n_a)
+  const int64_t M = N1 * N2;
+  hipLaunchKernelGGL(band_fit0_k, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, hs, values, y0,
+                     reinterpret_cast<const int32_t*>(wb + lay.perm),
+                     reinterpret_cast<const int32_t*>(wb + lay.c0), at(lay.bv), at(lay.lf),
+                     at(lay.inv_d), reinterpret_cast<const int32_t*>(wb + lay.pdeg), M, (int)N0,
+                     (int)n0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "encode: banded fit launch");
+  GemmArgs g1{N2, n1, N1, n0, y0, N2, N1 * N2, at(lay.q[1]), n1, 0, y1, n0 * n1, n1, 0};
+  GemmArgs g2{n0 * n1, n2, N2, 1, y1, n0 * n1, 0, at(lay.q[2]), n2, 0, ctrl, n2, 0, 0};
+  plan_split(g1, nullptr, 0);
+  plan_split(g2, nullptr, 0);
+  e = gemm<double, true>(g1, hs);
+  if (e == hipSuccess) e = gemm<double, true>(g2, hs);
   if (e != hipSuccess) return hip_fail(e, "encode: GEMM launch");
   return MFA_OK;
 }
