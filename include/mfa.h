@@ -459,11 +459,11 @@ mfa_status mfa_server_destroy(mfa_server server);
  *     P = argmin sum_i ( f(u0[i0], u1[i1], u2[i2]; P) - F[i0][i1][i2] )^2,
  * which for a tensor grid is P = F x_0 B0+ x_1 B1+ x_2 B2+ with B_a the
  * collocation matrix N_{j,p}(u_a[i]) of axis a and B+ = (B^T B)^-1 B^T.
- * The host factors each Gram matrix B_a^T B_a (banded Cholesky, FP64).  The
- * device applies axis 0 without forming B0+: per fiber of the samples,
- * B0^T F (p + 1 non-zeros per sample) and the two banded triangular solves;
- * the products along axes 1 and 2 use the dense B_a+ tables as FP64 GEMMs
- * on the matrix cores.
+ * The host factors each Gram matrix B_a^T B_a (banded Cholesky, FP64).  With
+ * at least 2^17 fibers along axes 1 and 2 (res1 * res2) the device applies
+ * axis 0 without forming B0+: per fiber of the samples, B0^T F (p + 1
+ * non-zeros per sample) and the two banded triangular solves; the other
+ * products use the dense B_a+ tables as FP64 GEMMs on the matrix cores.
  *  res      : samples per axis, n_ctrl[a] <= res[a] <= 65536.
  *  axis_u   : host FP64 parameters of the samples, res[a] values per axis,
  *             each in [0, 1], any order.
@@ -482,10 +482,10 @@ mfa_status mfa_server_destroy(mfa_server server);
  * mfa_encode_grid = mfa_encode_plan + mfa_encode_apply: blocks of one
  * partition have equal sizes and knots (Sec. IV-A1, IV-A2), so a plan,
  * made once into work, serves every block:
- *  mfa_encode_plan  : validates the arguments, builds the tables (axis 0:
- *                     sample order, supports, basis values, Cholesky factor
- *                     and degree; axes 1, 2: B_a+) and uploads them into
- *                     work (waits for the upload);
+ *  mfa_encode_plan  : validates the arguments, builds the tables (axis 0
+ *                     by the banded route: sample order, supports, basis
+ *                     values, Cholesky factor and degree; else B_a+) and
+ *                     uploads them into work (waits for the upload);
  *  mfa_encode_apply : the three mode products of one block's values into
  *                     ctrl, left in flight; work must hold a plan made for
  *                     the same res and n_ctrl (and the apply of one block

@@ -841,32 +841,44 @@ __global__ __launch_bounds__(256) void minmax_k(const float* __restrict__ f, int
   if (threadIdx.x == 0) part[blockIdx.x] = make_float2(lo[0], hi[0]);
 }
 
-// Workspace layout: the banded tables of axis 0 (sample order, control
-// point of each support, basis values, Cholesky factor rows, reciprocal
-// diagonal, degree), Q1, Q2 (B_a+ transposed, FP64), then Y0 = F x_0 B0+
-// (n0 x N1 x N2) and Y1 = Y0 x_1 B1+ (stored N2 x n0 x n1).
+// The x_0 product takes the banded route when the samples have enough
+// fibers (res1 res2, one thread each) to hide the latency of its sequential
+// solve per fiber: at 2^18 fibers (512^2) it takes 0.48 ms against 0.92 ms
+// for the dense GEMM (512^3 -> 192^3), at 2^16 (256^2) it is slower than the
+// GEMM (0.26 against 0.17 ms for 256^3 -> 128^3).
+constexpr int64_t kBandMinFibers = int64_t(1) << 17;
+
+bool band_route(const int32_t res[3]) { return (int64_t)res[1] * res[2] >= kBandMinFibers; }
+
+// Workspace layout: with the banded route, the tables of axis 0 (sample
+// order, control point of each support, basis values, Cholesky factor rows,
+// reciprocal diagonal, degree), else Q0; Q1, Q2 (B_a+ transposed, FP64);
+// then Y0 = F x_0 B0+ (n0 x N1 x N2) and Y1 = Y0 x_1 B1+ (stored N2 x n0 x n1).
 struct EncodeLayout {
   size_t perm, c0, bv, lf, inv_d, pdeg, q[3], y0, y1, total;
+  bool band;
 };
 
 EncodeLayout encode_layout(const int32_t res[3], const int32_t n_ctrl[3]) {
   EncodeLayout L{};
   size_t o = 0;
   const size_t N0 = res[0], n0 = n_ctrl[0], w = kMaxDegree + 1;
-  L.perm = o;
-  o += align256(4 * N0);
-  L.c0 = o;
-  o += align256(4 * N0);
-  L.bv = o;
-  o += align256(8 * N0 * w);
-  L.lf = o;
-  o += align256(8 * n0 * w);
-  L.inv_d = o;
-  o += align256(8 * n0);
-  L.pdeg = o;
-  o += 256;
-  L.q[0] = 0;                            // not used: axis 0 takes the banded route
-  for (int a = 1; a < 3; ++a) {
+  L.band = band_route(res);
+  if (L.band) {
+    L.perm = o;
+    o += align256(4 * N0);
+    L.c0 = o;
+    o += align256(4 * N0);
+    L.bv = o;
+    o += align256(8 * N0 * w);
+    L.lf = o;
+    o += align256(8 * n0 * w);
+    L.inv_d = o;
+    o += align256(8 * n0);
+    L.pdeg = o;
+    o += 256;
+  }
+  for (int a = L.band ? 1 : 0; a < 3; ++a) {
     L.q[a] = o;
     o += align256(8 * (size_t)n_ctrl[a] * (size_t)res[a]);
   }
@@ -940,7 +952,7 @@ extern "C" mfa_status mfa_encode_plan(const int32_t res[3], const double* const 
     } else {
       default_knots(n, p, T.data());
     }
-    if (a == 0) {
+    if (a == 0 && lay.band) {
       std::vector<int> s;
       std::vector<double> Bv;
       st = gram_factor(T.data(), p, n, axis_u[a], N, a, lf, s, Bv);
@@ -969,10 +981,15 @@ extern "C" mfa_status mfa_encode_plan(const int32_t res[3], const double* const 
     const void* src;
     size_t bytes;
   };
-  const Up ups[] = {{lay.perm, perm.data(), perm.size() * 4},  {lay.c0, c0s.data(), c0s.size() * 4},
-                    {lay.bv, bvs.data(), bvs.size() * 8},      {lay.lf, lf.data(), lf.size() * 8},
-                    {lay.inv_d, inv_d.data(), inv_d.size() * 8}, {lay.pdeg, &p0, 4},
-                    {lay.q[1], Q[1].data(), Q[1].size() * 8},  {lay.q[2], Q[2].data(), Q[2].size() * 8}};
+  std::vector<Up> ups;
+  if (lay.band)
+    ups = {{lay.perm, perm.data(), perm.size() * 4},    {lay.c0, c0s.data(), c0s.size() * 4},
+           {lay.bv, bvs.data(), bvs.size() * 8},        {lay.lf, lf.data(), lf.size() * 8},
+           {lay.inv_d, inv_d.data(), inv_d.size() * 8}, {lay.pdeg, &p0, 4}};
+  else
+    ups = {{lay.q[0], Q[0].data(), Q[0].size() * 8}};
+  ups.push_back({lay.q[1], Q[1].data(), Q[1].size() * 8});
+  ups.push_back({lay.q[2], Q[2].data(), Q[2].size() * 8});
   for (const Up& u : ups) {
     hipError_t e = hipMemcpyAsync(wb + u.off, u.src, u.bytes, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "encode: table upload");
@@ -1001,6 +1018,13 @@ extern "C" mfa_status mfa_encode_apply(const int32_t res[3], const int32_t n_ctr
   double* y1 = at(lay.y1);
   const int64_t N0 = res[0], N1 = res[1], N2 = res[2];
   const int64_t n0 = n_ctrl[0], n1 = n_ctrl[1], n2 = n_ctrl[2];
+  if (!lay.band) {                       // three GEMMs with the tables B_a+ transposed (N_a x n_a)
+    const double* dq[3] = {at(lay.q[0]), at(lay.q[1]), at(lay.q[2])};
+    const int64_t N[3] = {N0, N1, N2}, n[3] = {n0, n1, n2};
+    hipError_t e = run_fit(N, n, values, ctrl, dq, y0, y1, hs);
+    if (e != hipSuccess) return hip_fail(e, "encode: GEMM launch");
+    return MFA_OK;
+  }
   // Y0 = F x_0 B0+ by the banded route, then the x_1 and x_2 products as
   // GEMMs with the tables B_a+ transposed (N_a x n_a)
   const int64_t M = N1 * N2;

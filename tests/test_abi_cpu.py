@@ -134,12 +134,18 @@ def test_encode_workspace_size_and_rejections():
     nb = C.c_int64()
     assert lib.mfa_encode_workspace(_i3(10, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_OK
     al = lambda v: (v + 255) // 256 * 256
-    # axis 0: sample order and supports (int32), basis values (8 per sample),
-    # factor rows (8 per control point), reciprocal diagonal, degree; axes 1
-    # and 2: B_a+ (FP64); the two intermediates
-    want = al(4 * 10) + al(4 * 10) + al(8 * 10 * 8) + al(8 * 5 * 8) + al(8 * 5) + 256 \
-        + sum(al(8 * n * r) for n, r in ((6, 12), (7, 14))) \
+    # few fibers (12 x 14): three GEMMs, tables B_a+ (FP64) and the two
+    # intermediates
+    want = sum(al(8 * n * r) for n, r in ((5, 10), (6, 12), (7, 14))) \
         + al(8 * 5 * 12 * 14) + al(8 * 5 * 6 * 14)
+    assert nb.value == want
+    # 2^17 fibers (512 x 256): axis 0 by the banded route, its tables
+    # (sample order and supports, int32; basis values, 8 per sample; factor
+    # rows, 8 per control point; reciprocal diagonal; degree) instead of B0+
+    assert lib.mfa_encode_workspace(_i3(10, 512, 256), _i3(5, 6, 7), C.byref(nb)) == L.MFA_OK
+    want = al(4 * 10) + al(4 * 10) + al(8 * 10 * 8) + al(8 * 5 * 8) + al(8 * 5) + 256 \
+        + sum(al(8 * n * r) for n, r in ((6, 512), (7, 256))) \
+        + al(8 * 5 * 512 * 256) + al(8 * 5 * 6 * 256)
     assert nb.value == want
     assert lib.mfa_encode_workspace(_i3(4, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_E_ARG
     assert lib.mfa_encode_workspace(_i3(10, 12, 14), _i3(5, 6, 7), None) == L.MFA_E_ARG

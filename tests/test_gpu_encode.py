@@ -3,7 +3,8 @@ oracle (oracle.encode.fit_grid), through the C ABI.
 
 Tolerance: both sides compute in FP64 (the samples are FP32, promoted
 exactly), by different routes (SVD pseudo-inverse and tensordot in the
-oracle; Cholesky of the Gram matrix and matrix-core GEMMs on the device).
+oracle; Cholesky of the Gram matrix, banded solves and matrix-core GEMMs on
+the device).
 The Gram matrices of these collocation matrices have condition numbers
 below ~1e4 and each control point sums at most ~1e6 products, so the two
 agree to ~1e-12 of max|F|; the bound is set at 1e-10 of max|F|, normwise.
@@ -71,6 +72,23 @@ def test_encode_ragged_sizes_random_parameters_nonuniform_knots(mfa, dev):
     knots = [spaced_knots(n_ctrl[a], degree[a], rng) for a in range(3)]
     F = rng.standard_normal(res).astype(np.float32)
     announce("encode ragged 37x50x29")
+    run_case(mfa, dev, F, axis_u, degree, n_ctrl, knots)
+
+
+@pytest.mark.parametrize("p0", [1, 3, 7])
+def test_encode_banded_first_product_many_fibers(mfa, dev, p0):
+    """2^17 fibers (512 x 256 samples along axes 1 and 2): the first mode
+    product takes the banded route (B0^T F and two banded Cholesky solves
+    per fiber) with the samples of axis 0 in shuffled order, non-uniform
+    knots and degrees up to the largest accepted; the other two products
+    stay GEMMs."""
+    rng = np.random.default_rng(30 + p0)
+    res, degree, n_ctrl = (45, 512, 256), (p0, 3, 2), (p0 + 9, 40, 33)
+    axis_u = [rng.permutation(np.linspace(0.0, 1.0, res[0])), np.linspace(0.0, 1.0, res[1]),
+              np.linspace(0.0, 1.0, res[2])]
+    knots = [spaced_knots(n_ctrl[0], p0, rng), None, None]
+    F = rng.standard_normal(res).astype(np.float32)
+    announce(f"encode banded first product 45x512x256 p0={p0}")
     run_case(mfa, dev, F, axis_u, degree, n_ctrl, knots)
 
 
