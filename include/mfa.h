@@ -460,10 +460,12 @@ mfa_status mfa_server_destroy(mfa_server server);
  * which for a tensor grid is P = F x_0 B0+ x_1 B1+ x_2 B2+ with B_a the
  * collocation matrix N_{j,p}(u_a[i]) of axis a and B+ = (B^T B)^-1 B^T.
  * The host factors each Gram matrix B_a^T B_a (banded Cholesky, FP64).  With
- * at least 2^17 fibers along axes 1 and 2 (res1 * res2) the device applies
- * axis 0 without forming B0+: per fiber of the samples, B0^T F (p + 1
- * non-zeros per sample) and the two banded triangular solves; the other
- * products use the dense B_a+ tables as FP64 GEMMs on the matrix cores.
+ * at least 2^17 fibers along axes 1 and 2 (res1 * res2), and when its bytes
+ * take less time than the dense product's work (about n0 > 48 for res0 =
+ * 512), the device applies axis 0 without forming B0+: per fiber of the
+ * samples, B0^T F (p + 1 non-zeros per sample) and the two banded
+ * triangular solves; the other products use the dense B_a+ tables as FP64
+ * GEMMs on the matrix cores.
  *  res      : samples per axis, n_ctrl[a] <= res[a] <= 65536.
  *  axis_u   : host FP64 parameters of the samples, res[a] values per axis,
  *             each in [0, 1], any order.

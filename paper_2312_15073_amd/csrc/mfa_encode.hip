@@ -843,12 +843,21 @@ __global__ __launch_bounds__(256) void minmax_k(const float* __restrict__ f, int
 
 // The x_0 product takes the banded route when the samples have enough
 // fibers (res1 res2, one thread each) to hide the latency of its sequential
-// solve per fiber: at 2^18 fibers (512^2) it takes 0.48 ms against 0.92 ms
-// for the dense GEMM (512^3 -> 192^3), at 2^16 (256^2) it is slower than the
-// GEMM (0.26 against 0.17 ms for 256^3 -> 128^3).
+// solve per fiber and when its bytes take less time than the dense
+// product's matrix work, by the rates measured on MI355X: 512^3 -> 192^3
+// (2^18 fibers) 0.48 ms banded (3.6 TB/s of its 1.75 GB) against 0.92 ms
+// for the GEMM (56 TFLOP/s); at 2^16 fibers (256^3 -> 128^3) the banded
+// route was slower, 0.26 against 0.17 ms.
 constexpr int64_t kBandMinFibers = int64_t(1) << 17;
+constexpr double kBandBytesPerS = 3.6e12, kGemmFlopPerS = 55e12;
 
-bool band_route(const int32_t res[3]) { return (int64_t)res[1] * res[2] >= kBandMinFibers; }
+bool band_route(const int32_t res[3], const int32_t n_ctrl[3]) {
+  const double M = (double)res[1] * res[2], N0 = res[0], n0 = n_ctrl[0];
+  if (M < (double)kBandMinFibers) return false;
+  const double t_band = (4.0 * N0 + 24.0 * n0) * M / kBandBytesPerS;   // F; y out, in; x out
+  const double t_gemm = 2.0 * n0 * N0 * M / kGemmFlopPerS;
+  return t_band < t_gemm;
+}
 
 // Workspace layout: with the banded route, the tables of axis 0 (sample
 // order, control point of each support, basis values, Cholesky factor rows,
@@ -863,7 +872,7 @@ EncodeLayout encode_layout(const int32_t res[3], const int32_t n_ctrl[3]) {
   EncodeLayout L{};
   size_t o = 0;
   const size_t N0 = res[0], n0 = n_ctrl[0], w = kMaxDegree + 1;
-  L.band = band_route(res);
+  L.band = band_route(res, n_ctrl);
   if (L.band) {
     L.perm = o;
     o += align256(4 * N0);

@@ -139,13 +139,19 @@ def test_encode_workspace_size_and_rejections():
     want = sum(al(8 * n * r) for n, r in ((5, 10), (6, 12), (7, 14))) \
         + al(8 * 5 * 12 * 14) + al(8 * 5 * 6 * 14)
     assert nb.value == want
-    # 2^17 fibers (512 x 256): axis 0 by the banded route, its tables
-    # (sample order and supports, int32; basis values, 8 per sample; factor
-    # rows, 8 per control point; reciprocal diagonal; degree) instead of B0+
-    assert lib.mfa_encode_workspace(_i3(10, 512, 256), _i3(5, 6, 7), C.byref(nb)) == L.MFA_OK
-    want = al(4 * 10) + al(4 * 10) + al(8 * 10 * 8) + al(8 * 5 * 8) + al(8 * 5) + 256 \
+    # 2^17 fibers (512 x 256) and 90 control points from 300 samples along
+    # axis 0: the banded route, its tables (sample order and supports, int32;
+    # basis values, 8 per sample; factor rows, 8 per control point;
+    # reciprocal diagonal; degree) instead of B0+
+    assert lib.mfa_encode_workspace(_i3(300, 512, 256), _i3(90, 6, 7), C.byref(nb)) == L.MFA_OK
+    want = al(4 * 300) + al(4 * 300) + al(8 * 300 * 8) + al(8 * 90 * 8) + al(8 * 90) + 256 \
         + sum(al(8 * n * r) for n, r in ((6, 512), (7, 256))) \
-        + al(8 * 5 * 512 * 256) + al(8 * 5 * 6 * 256)
+        + al(8 * 90 * 512 * 256) + al(8 * 90 * 6 * 256)
+    assert nb.value == want
+    # the same fibers with 20 control points along axis 0: the dense product
+    assert lib.mfa_encode_workspace(_i3(300, 512, 256), _i3(20, 6, 7), C.byref(nb)) == L.MFA_OK
+    want = sum(al(8 * n * r) for n, r in ((20, 300), (6, 512), (7, 256))) \
+        + al(8 * 20 * 512 * 256) + al(8 * 20 * 6 * 256)
     assert nb.value == want
     assert lib.mfa_encode_workspace(_i3(4, 12, 14), _i3(5, 6, 7), C.byref(nb)) == L.MFA_E_ARG
     assert lib.mfa_encode_workspace(_i3(10, 12, 14), _i3(5, 6, 7), None) == L.MFA_E_ARG

@@ -75,20 +75,20 @@ def test_encode_ragged_sizes_random_parameters_nonuniform_knots(mfa, dev):
     run_case(mfa, dev, F, axis_u, degree, n_ctrl, knots)
 
 
-@pytest.mark.parametrize("p0", [1, 3, 7])
+@pytest.mark.parametrize("p0", [1, 7])
 def test_encode_banded_first_product_many_fibers(mfa, dev, p0):
-    """2^17 fibers (512 x 256 samples along axes 1 and 2): the first mode
-    product takes the banded route (B0^T F and two banded Cholesky solves
-    per fiber) with the samples of axis 0 in shuffled order, non-uniform
-    knots and degrees up to the largest accepted; the other two products
-    stay GEMMs."""
+    """2^17 fibers (512 x 256 samples along axes 1 and 2) and 90 control
+    points along axis 0: the first mode product takes the banded route
+    (B0^T F and two banded Cholesky solves per fiber) with the samples of
+    axis 0 in shuffled order, non-uniform knots and the smallest and
+    largest degree accepted; the other two products stay GEMMs."""
     rng = np.random.default_rng(30 + p0)
-    res, degree, n_ctrl = (45, 512, 256), (p0, 3, 2), (p0 + 9, 40, 33)
+    res, degree, n_ctrl = (300, 512, 256), (p0, 3, 2), (90, 40, 33)
     axis_u = [rng.permutation(np.linspace(0.0, 1.0, res[0])), np.linspace(0.0, 1.0, res[1]),
               np.linspace(0.0, 1.0, res[2])]
     knots = [spaced_knots(n_ctrl[0], p0, rng), None, None]
     F = rng.standard_normal(res).astype(np.float32)
-    announce(f"encode banded first product 45x512x256 p0={p0}")
+    announce(f"encode banded first product 300x512x256 p0={p0}")
     run_case(mfa, dev, F, axis_u, degree, n_ctrl, knots)
 
 
