@@ -999,6 +999,22 @@ __device__ __forceinline__ T uniform_copy(const T* p) {
 // The tables are staged before the kernels' own first barrier.
 constexpr int kMatsLds = 1024;
 
+// Copy of n float4 from global memory into LDS by a whole workgroup, four
+// loads per thread in flight before their LDS writes (a loop that writes
+// each value as it arrives waits out one memory latency per value).  Slots
+// past the end repeat the last element, which lands where its own copy
+// does, so every load and write is unconditional.
+__device__ __forceinline__ void stage_lds(float4* dst, const float4* __restrict__ src, int n) {
+  constexpr int U = 4;
+  for (int q0 = threadIdx.x; q0 < n; q0 += U * kBlock) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[min(q0 + u * kBlock, n - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[min(q0 + u * kBlock, n - 1)] = v[u];
+  }
+}
+
 // Decode in sorted order, one item (a bucket, or an equal part of a bucket
 // of more than kTilePoints points) per workgroup; results go to the input
 // positions.  The bucket's window of control points (the tile's spans plus
@@ -1022,18 +1038,16 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   if constexpr (LDSREC) {
     SpanRec* lr = reinterpret_cast<SpanRec*>(dyn);
     float* lm = reinterpret_cast<float*>(lr + m.n_rec);
-    for (int q = threadIdx.x; q < m.n_rec * 2; q += kBlock)
-      reinterpret_cast<float4*>(lr)[q] = reinterpret_cast<const float4*>(m.rec)[q];
-    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
-      reinterpret_cast<float4*>(lm)[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    stage_lds(reinterpret_cast<float4*>(lr), reinterpret_cast<const float4*>(m.rec), m.n_rec * 2);
+    stage_lds(reinterpret_cast<float4*>(lm), reinterpret_cast<const float4*>(m.mats),
+              m.n_mats * m.mat_stride / 4);
     R = lr;
     MT = lm;
     W = lm + m.n_mats * m.mat_stride;
   } else {
     // the launcher sends models whose tables exceed kMatsLds floats to
     // decode_sorted_k, so that these reads are always LDS loads
-    for (int q = threadIdx.x; q < m.n_mats * m.mat_stride / 4; q += kBlock)
-      lmats[q] = reinterpret_cast<const float4*>(m.mats)[q];
+    stage_lds(lmats, reinterpret_cast<const float4*>(m.mats), m.n_mats * m.mat_stride / 4);
     MT = reinterpret_cast<const float*>(lmats);
   }
   const int2 it = uniform_copy(sa.items + item);
@@ -1092,25 +1106,36 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     const uint32_t n1 = (uint32_t)B->n[1], rs1 = (uint32_t)B->rs1;
     const int w1 = bw.w[1], w2 = bw.w[2], rows = bw.w[0] * w1;
     if (w2 <= kWave) {
+      // U rows per lane per pass, their loads in flight together.  A slot
+      // past the last row reads and writes the last row's value, and a lane
+      // past rpi rows (sub >= rpi) reads and writes a row another wave
+      // covers: duplicate writes of equal values, so none is conditional.
+      constexpr int U = 4;
       const int rpi = kWave / w2, lane = threadIdx.x & (kWave - 1);
       const int sub = lane / w2, k = lane - sub * w2;
       const int step = rpi * (kBlock / kWave);
       int row = (threadIdx.x / kWave) * rpi + sub;
       int i = row / w1, j = row - i * w1;
       const int di = step / w1, dj = step - di * w1;
-      for (; row < rows; row += step) {
-        if (sub < rpi) {
+      for (; row < rows; row += U * step) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool ok = row + u * step < rows;
           const uint32_t e = (uint32_t)B->ctrl_off +
-                             ((uint32_t)(bw.o[0] + i) * n1 + (uint32_t)(bw.o[1] + j)) * rs1 +
+                             ((uint32_t)(bw.o[0] + (ok ? i : bw.w[0] - 1)) * n1 +
+                              (uint32_t)(bw.o[1] + (ok ? j : w1 - 1))) * rs1 +
                              (uint32_t)(bw.o[2] + k);
-          W[row * w2 + k] = load_one<S>(rs, e);
+          v[u] = load_one<S>(rs, e);
+          i += di;
+          j += dj;
+          if (j >= w1) {
+            j -= w1;
+            ++i;
+          }
         }
-        i += di;
-        j += dj;
-        if (j >= w1) {
-          j -= w1;
-          ++i;
-        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) W[min(row + u * step, rows - 1) * w2 + k] = v[u];
       }
     } else {
       for (int q = threadIdx.x; q < wn; q += kBlock) {
@@ -1124,11 +1149,26 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   }
   __syncthreads();                 // window and tile records staged
   if (s0 >= s1) return;
+  // Loads and stores share one completion counter here, and a wait for a
+  // load with a store in flight waits for everything.  So each step first
+  // takes its record (loaded one step earlier; the empty asm is the point
+  // where the compiler waits for it, and no memory access moves above it),
+  // then stores the previous step's result and loads the next record: the
+  // one wait of the next step finds that store and load a whole step old.
+  constexpr uint32_t kNone = 0xffffffffu;
+  uint32_t pi = kNone;             // input position of the pending result
+  float4 pres = make_float4(0.f, 0.f, 0.f, 0.f);
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4* __restrict__ rec4 = reinterpret_cast<const f32x4*>(sa.rec);
   uint32_t t = s0 + threadIdx.x;
-  float4 q = sa.rec[min(t, s1 - 1)];
+  f32x4 q = rec4[min(t, s1 - 1)];
   for (; t < s1; t += kBlock) {
-    const float4 qn = sa.rec[min(t + kBlock, s1 - 1)];   // next record in flight
+    asm volatile("" : "+v"(q) : : "memory");
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
+    const uint32_t i = __float_as_uint(q.w);
+    if (pi != kNone) put_result<G>(out, pi, pres);
+    pi = kNone;
+    q = rec4[min(t + kBlock, s1 - 1)];
     Loc L;
     if constexpr (MULTI) {
       bool own = true;
@@ -1144,8 +1184,6 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
     } else {
       L = locate<P, false, GT>(m, R, x);
     }
-    const uint32_t i = __float_as_uint(q.w);
-    q = qn;
     if ((int64_t)i >= sa.n) continue;
     int d[3];
     bool in = staged && L.block == bw.block;
@@ -1160,9 +1198,11 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
                             m.mat_stride, m.imat);
     else
       res = evaluate<P, S, !MULTI>(L, rs, MT, m.mat_stride, m.imat);
-    put_result<G>(out, i, res);
+    pres = res;
+    pi = i;
     if (dbg) reinterpret_cast<int4*>(dbg)[i] = make_int4(L.j[0] + P, L.j[1] + P, L.j[2] + P, L.block);
   }
+  if (pi != kNone) put_result<G>(out, pi, pres);
 }
 
 // Sorted decode for models whose bucket windows exceed the LDS budget: one
