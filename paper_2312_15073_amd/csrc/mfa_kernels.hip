@@ -2625,21 +2625,34 @@ template <bool G>
 __global__ __launch_bounds__(kBlock) void unsort_k(const uint32_t* __restrict__ tpos,
                                                    const float* __restrict__ src, int64_t n,
                                                    float* __restrict__ out) {
+  // every load is unconditional (indices clamped into range) so that all
+  // of a thread's loads are in flight together; only the stores are masked
   const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kUnsortPer) + threadIdx.x;
   uint32_t k[kUnsortPer];
 #pragma unroll
-  for (int u = 0; u < kUnsortPer; ++u) {
-    const int64_t i = i0 + u * kBlock;
-    k[u] = i < n ? min(tpos[i], (uint32_t)(n - 1)) : 0u;
-  }
+  for (int u = 0; u < kUnsortPer; ++u)
+    k[u] = min(tpos[min(i0 + u * kBlock, n - 1)], (uint32_t)(n - 1));
+  // A slot past n repeats element n - 1 (its tpos entry, its value and its
+  // destination), a duplicate write of an equal value.  The empty asm takes
+  // all gathered values before the first store, so no store is in flight
+  // while the loads are waited for.
+  if constexpr (G) {
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    f32x4 v[kUnsortPer];
 #pragma unroll
-  for (int u = 0; u < kUnsortPer; ++u) {
-    const int64_t i = i0 + u * kBlock;
-    if (i >= n) continue;
-    if constexpr (G)
-      reinterpret_cast<float4*>(out)[i] = reinterpret_cast<const float4*>(src)[k[u]];
-    else
-      out[i] = src[k[u]];
+    for (int u = 0; u < kUnsortPer; ++u) v[u] = reinterpret_cast<const f32x4*>(src)[k[u]];
+    static_assert(kUnsortPer == 4, "one asm operand per value");
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : : "memory");
+#pragma unroll
+    for (int u = 0; u < kUnsortPer; ++u)
+      reinterpret_cast<f32x4*>(out)[min(i0 + u * kBlock, n - 1)] = v[u];
+  } else {
+    float v[kUnsortPer];
+#pragma unroll
+    for (int u = 0; u < kUnsortPer; ++u) v[u] = src[k[u]];
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : : "memory");
+#pragma unroll
+    for (int u = 0; u < kUnsortPer; ++u) out[min(i0 + u * kBlock, n - 1)] = v[u];
   }
 }
 
