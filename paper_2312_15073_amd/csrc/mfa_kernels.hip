@@ -127,10 +127,11 @@ struct Row<P, Storage::F16> : Halves<P> {
   }
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Streaming 16-byte store: the line bypasses the caches.  Only for outputs
 // written in whole lines (scattered 16-byte writes become twice as slow).
 __device__ __forceinline__ void store_stream(float4* p, float4 v) {
-  typedef float f32x4 __attribute__((ext_vector_type(4)));
   const f32x4 w = {v.x, v.y, v.z, v.w};
   __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
 }
@@ -1023,9 +1024,11 @@ __device__ __forceinline__ void stage_lds(float4* dst, const float4* __restrict_
 // global memory.  Both paths sum in the same order.  LDSREC: the span
 // records and basis tables of a single-block model are staged too, ahead of
 // the window.  Multi-block models: every point of the bucket lies in the
-// bucket's block, whose record the workgroup reads as uniform data.
+// bucket's block, whose record the workgroup reads as uniform data.  For
+// those at degree <= 3 the launch bounds ask for four waves per SIMD: left
+// alone the compiler takes 133 registers (three waves) where 105 suffice.
 template <int P, Storage S, bool MULTI, bool LDSREC, bool GT = false, bool G = true>
-__global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
+__global__ __launch_bounds__(kBlock, (MULTI && P <= 3) ? 4 : 1) void decode_tiles_k(DevModel m, SortArgs sa, int win_cap,
                                                          float* __restrict__ out,
                                                          int32_t* __restrict__ dbg) {
   extern __shared__ float4 dyn[];
@@ -1158,7 +1161,6 @@ __global__ __launch_bounds__(kBlock) void decode_tiles_k(DevModel m, SortArgs sa
   constexpr uint32_t kNone = 0xffffffffu;
   uint32_t pi = kNone;             // input position of the pending result
   float4 pres = make_float4(0.f, 0.f, 0.f, 0.f);
-  typedef float f32x4 __attribute__((ext_vector_type(4)));
   const f32x4* __restrict__ rec4 = reinterpret_cast<const f32x4*>(sa.rec);
   uint32_t t = s0 + threadIdx.x;
   f32x4 q = rec4[min(t, s1 - 1)];
@@ -2637,7 +2639,6 @@ __global__ __launch_bounds__(kBlock) void unsort_k(const uint32_t* __restrict__ 
   // all gathered values before the first store, so no store is in flight
   // while the loads are waited for.
   if constexpr (G) {
-    typedef float f32x4 __attribute__((ext_vector_type(4)));
     f32x4 v[kUnsortPer];
 #pragma unroll
     for (int u = 0; u < kUnsortPer; ++u) v[u] = reinterpret_cast<const f32x4*>(src)[k[u]];
