@@ -519,7 +519,6 @@ constexpr int kFineKeys = 1024;                    // LDS keys of a fine-pass ch
 constexpr int kHistThreads = 1024;                 // histogram workgroup
 constexpr int kHistPer = 63;                       // points per thread: at most 65535 per chunk
 constexpr int kHistChunk = kHistThreads * kHistPer;
-constexpr int kHistIlp = 4;
 constexpr int kScanThreads = 1024;
 
 // Sort tables of a multi-block model in LDS: block edges (FP32), then one
@@ -616,7 +615,11 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
 // half b & 1 of word b >> 1).  Dynamic LDS: the sort tables, then the
 // counters.
 template <bool MULTI, bool GT, bool TL>
-__global__ __launch_bounds__(kHistThreads) void sort_hist_k(DevModel m, SortArgs sa) {
+__global__ __launch_bounds__(kHistThreads, MULTI ? 8 : 1) void sort_hist_k(DevModel m, SortArgs sa) {
+  // Multi-block models hold up to kMaxBuckets 16-bit counters (64 KB of
+  // LDS), so two workgroups fit a CU only at eight waves per SIMD, i.e. at
+  // most 64 registers: two points per step there, four otherwise.
+  constexpr int kHistIlp = MULTI ? 2 : 4;
   extern __shared__ float4 sdyn[];
   const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
   uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(sdyn) +
