@@ -365,10 +365,11 @@ __device__ __forceinline__ int macro_cell(const DevModel& m, const DevBlock* __r
   return B->mc_off + (((j[0] >> sh) * B->mc[1] + (j[1] >> sh)) * B->mc[2] + (j[2] >> sh));
 }
 
-// R: span records (global pool or its LDS copy).
+// R: span records (global pool or its LDS copy); EDG: the block edges
+// (m.edges or an LDS copy).
 template <bool MULTI, bool GT = false>
 __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restrict__ R,
-                                       const double (&x)[3]) {
+                                       const double (&x)[3], const double* __restrict__ EDG) {
   Probe q;
   q.B = &m.b0;
   if constexpr (MULTI) {
@@ -376,7 +377,7 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
     double xc[3], e0[3], e1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double* E = m.edges + m.edge_off[a];
+      const double* E = EDG + m.edge_off[a];
       xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
       b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
       e0[a] = E[b[a]];
@@ -387,7 +388,7 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
     for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
     if (!ok) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) fix_owner(m.edges + m.edge_off[a], m.grid[a], xc[a], b[a]);
+      for (int a = 0; a < 3; ++a) fix_owner(EDG + m.edge_off[a], m.grid[a], xc[a], b[a]);
     }
     q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
     q.B = m.blocks + q.block;
@@ -409,6 +410,12 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
     q.rec[a] = R[q.B->rec_off[a] + q.j[a]];
   }
   return q;
+}
+
+template <bool MULTI, bool GT = false>
+__device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restrict__ R,
+                                       const double (&x)[3]) {
+  return probe<MULTI, GT>(m, R, x, m.edges);
 }
 
 // Exact spans (a walk only where a guess fails its check), local
@@ -441,9 +448,15 @@ __device__ __forceinline__ Loc finish(const DevModel& m, const SpanRec* __restri
 
 template <int P, bool MULTI, bool GT = false>
 __device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
-                                      const double (&x)[3]) {
-  Probe q = probe<MULTI, GT>(m, R, x);
+                                      const double (&x)[3], const double* __restrict__ EDG) {
+  Probe q = probe<MULTI, GT>(m, R, x, EDG);
   return finish(m, R, q);
+}
+
+template <int P, bool MULTI, bool GT = false>
+__device__ __forceinline__ Loc locate(const DevModel& m, const SpanRec* __restrict__ R,
+                                      const double (&x)[3]) {
+  return locate<P, MULTI, GT>(m, R, x, m.edges);
 }
 
 // Value and world gradient at a located point: the control-row loads are
@@ -1577,13 +1590,14 @@ __device__ __forceinline__ float shade_over(const float4 e, const float (&L)[3],
 template <int P, bool MULTI, bool GT = false>
 __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs& r,
                                              const SpanRec* __restrict__ R, const Ray& ray,
-                                             const int* zpre, int k_lo, int k_hi) {
+                                             const int* zpre, int k_lo, int k_hi,
+                                             const double* __restrict__ EDG) {
   int k = k_lo, from = -1, lvl = 0, cell = -1, noleap = -1, last_c0 = -1;
   bool c0_empty = false;
   while (k < k_hi) {
     double x[3];
     sample_point(ray, r.step, k, x);
-    const Loc Lc = locate<P, MULTI, GT>(m, R, x);
+    const Loc Lc = locate<P, MULTI, GT>(m, R, x, EDG);
     const DevBlock* __restrict__ B = MULTI ? m.blocks + Lc.block : &m.b0;
     int c[2];
 #pragma unroll
@@ -1639,11 +1653,12 @@ __device__ __forceinline__ int first_visible(const DevModel& m, const RenderArgs
 
 // One 16x16 pixel tile of a frame: one ray per thread.  R, MT: span records
 // and basis tables (global pool or an LDS copy); tf, zpre staged in LDS.
+// EDG: the block edges (m.edges or an LDS copy).
 template <int P, Storage S, bool MULTI, bool PARTIAL = false, bool GT = false>
 __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs& r, int tile,
                                             const SpanRec* __restrict__ R,
                                             const float* __restrict__ MT, const float4* tf,
-                                            const int* zpre) {
+                                            const int* zpre, const double* __restrict__ EDG) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int tx = (r.w + kTile - 1) / kTile;
   const int i = (tile % tx) * kTile + (wave & 1) * 8 + (lane & 7);
@@ -1666,7 +1681,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
   if constexpr (PARTIAL) {
     if (pix) region_range(r, ray, k_lo, k_hi, t_in);
   }
-  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, k_lo, k_hi) : 0;
+  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, k_lo, k_hi, EDG) : 0;
   if (r.alpha)
     for (int q = 0; q < k0; ++q) r.alpha[pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
@@ -1679,7 +1694,7 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, k, x);
-    Probe q = probe<MULTI, GT>(m, R, x);
+    Probe q = probe<MULTI, GT>(m, R, x, EDG);
     // Skip the evaluation where the transfer function is zero over the
     // value bounds of the macro cell: such a sample has alpha = 0 exactly
     // and leaves C and A unchanged.  The verdict is kept while the ray
@@ -1762,7 +1777,7 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
   const int64_t pid = (int64_t)j * r.w + i;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
   const int k_hi = ray.K;
-  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, 0, k_hi) : 0;
+  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, 0, k_hi, m.edges) : 0;
   if (r.alpha && pix)
     for (int q = s; q < k0; q += 4) r.alpha[pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
@@ -1860,14 +1875,24 @@ __device__ __forceinline__ int frame_tile(int bid, int tx, int ty) {
 // into LDS once per workgroup.
 // GM: basis tables read from the global pool (models whose tables exceed
 // kMatsLds floats; multi-block kernels only), else from an LDS copy.
+// EL: multi-block model whose block edges (at most kEdgesLds values) are
+// copied into LDS, so that each sample's owner check reads them there.
+constexpr int kEdgesLds = 256;
+
 template <int P, Storage S, bool MULTI, bool LDSREC, bool PARTIAL = false, bool GT = false,
-          bool QUAD = false, bool GM = false>
+          bool QUAD = false, bool GM = false, bool EL = false>
 __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
   extern __shared__ float4 dyn[];
   __shared__ float4 lmats[LDSREC || GM ? 1 : kMatsLds / 4];
   __shared__ float4 tf[256];
   __shared__ int zpre[257];
   __shared__ int wtot[kBlock / kWave];
+  __shared__ double ledges[EL ? kEdgesLds : 1];
+  const double* EDG = m.edges;
+  if constexpr (EL) {
+    for (int q = threadIdx.x; q < m.n_edges; q += kBlock) ledges[q] = m.edges[q];
+    EDG = ledges;                  // read after stage_tf's barriers
+  }
   const SpanRec* R = m.rec;
   const float* MT = m.mats;
   if constexpr (LDSREC) {
@@ -1891,7 +1916,7 @@ __global__ __launch_bounds__(kBlock) void render_k(DevModel m, RenderArgs r) {
     render_tile4<P, S, MULTI, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
   } else {
     const int tx = (r.w + kTile - 1) / kTile, ty = (r.h + kTile - 1) / kTile;
-    render_tile<P, S, MULTI, PARTIAL, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre);
+    render_tile<P, S, MULTI, PARTIAL, GT>(m, r, frame_tile(blockIdx.x, tx, ty), R, MT, tf, zpre, EDG);
   }
 }
 
@@ -2484,7 +2509,7 @@ __global__ __launch_bounds__(kBlock) void serve_k(const DevModel* __restrict__ m
         stage_tf(Q->ra.tf, tf, zpre, wtot);
         staged = I.req;
       }
-      render_tile<P, S, MULTI>(m, Q->ra, I.index, m.rec, m.mats, tf, zpre);
+      render_tile<P, S, MULTI>(m, Q->ra, I.index, m.rec, m.mats, tf, zpre, m.edges);
       __syncthreads();                             // tf may be restaged by the next item
     } else {
       const int64_t i = (int64_t)I.index * kBlock + threadIdx.x;
@@ -2731,7 +2756,10 @@ static hipError_t render_p(const DevModel& m, int kind, const RenderArgs& r, hip
                        0, st, m, r);
   else if (multi && r.partial)
     hipLaunchKernelGGL((render_k<P, S, true, false, true>), dim3(tiles), dim3(kBlock), 0, st, m, r);
-  else if (multi)       // one lane per ray (four per ray measured slower here: 12.5 vs 12.1 ms)
+  else if (multi && m.n_edges <= kEdgesLds)   // one lane per ray (four per ray measured slower here)
+    hipLaunchKernelGGL((render_k<P, S, true, false, false, false, false, false, true>), dim3(tiles),
+                       dim3(kBlock), 0, st, m, r);
+  else if (multi)
     hipLaunchKernelGGL((render_k<P, S, true, false>), dim3(tiles), dim3(kBlock), 0, st, m, r);
   else if (kind == kKindGraded && r.partial)
     hipLaunchKernelGGL((render_k<P, S, false, true, false, true>), dim3(tiles), dim3(kBlock), lds, st,
