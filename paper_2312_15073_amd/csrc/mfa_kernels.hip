@@ -365,6 +365,48 @@ __device__ __forceinline__ int macro_cell(const DevModel& m, const DevBlock* __r
   return B->mc_off + (((j[0] >> sh) * B->mc[1] + (j[1] >> sh)) * B->mc[2] + (j[2] >> sh));
 }
 
+// Owning block of a point of a multi-block model (EDG: the block edges,
+// m.edges or an LDS copy): q.block and q.b, and the clamped coordinates.
+__device__ __forceinline__ void probe_owner(const DevModel& m, const double (&x)[3],
+                                            const double* __restrict__ EDG, Probe& q,
+                                            double (&xc)[3]) {
+  int b[3];
+  double e0[3], e1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double* E = EDG + m.edge_off[a];
+    xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
+    b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
+    e0[a] = E[b[a]];
+    e1[a] = E[b[a] + 1];
+  }
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
+  if (!ok) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) fix_owner(EDG + m.edge_off[a], m.grid[a], xc[a], b[a]);
+  }
+  q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q.b[a] = b[a];
+}
+
+// The rest of the probe once the point's block record B is known: the
+// parameters and the guessed spans with their records (loads issued).
+template <bool GT = false>
+__device__ __forceinline__ void probe_spans(const DevModel& m, const SpanRec* __restrict__ R,
+                                            const double (&xc)[3], const DevBlock* B, Probe& q) {
+  q.B = B;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q.u[a] = param_of(xc[a], B->lo[a], B->inv_ext[a]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.j[a] = guess_span<GT>(m, B, q.block, a, q.u[a]);
+    q.rec[a] = R[B->rec_off[a] + q.j[a]];
+  }
+}
+
 // R: span records (global pool or its LDS copy); EDG: the block edges
 // (m.edges or an LDS copy).
 template <bool MULTI, bool GT = false>
@@ -373,29 +415,10 @@ __device__ __forceinline__ Probe probe(const DevModel& m, const SpanRec* __restr
   Probe q;
   q.B = &m.b0;
   if constexpr (MULTI) {
-    int b[3];
-    double xc[3], e0[3], e1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double* E = EDG + m.edge_off[a];
-      xc[a] = clampd(x[a], E[0], E[m.grid[a]]);
-      b[a] = guess_owner(E, m.grid[a], m.edge_scale[a], xc[a]);
-      e0[a] = E[b[a]];
-      e1[a] = E[b[a] + 1];
-    }
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) ok &= owner_ok(m.grid[a], xc[a], b[a], e0[a], e1[a]);
-    if (!ok) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) fix_owner(EDG + m.edge_off[a], m.grid[a], xc[a], b[a]);
-    }
-    q.block = (b[0] * m.grid[1] + b[1]) * m.grid[2] + b[2];
-    q.B = m.blocks + q.block;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) q.b[a] = b[a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) q.u[a] = param_of(xc[a], q.B->lo[a], q.B->inv_ext[a]);
+    double xc[3];
+    probe_owner(m, x, EDG, q, xc);
+    probe_spans<GT>(m, R, xc, m.blocks + q.block, q);
+    return q;
   } else {
     q.block = 0;
 #pragma unroll
@@ -1694,17 +1717,39 @@ __device__ __forceinline__ void render_tile(const DevModel& m, const RenderArgs&
     if (!act) continue;
     double x[3];
     sample_point(ray, r.step, k, x);
-    Probe q = probe<MULTI, GT>(m, R, x, EDG);
     // Skip the evaluation where the transfer function is zero over the
     // value bounds of the macro cell: such a sample has alpha = 0 exactly
     // and leaves C and A unchanged.  The verdict is kept while the ray
     // stays in the same cell.  The bounds of the cell of the guessed spans
     // are fetched while the guesses are checked (reloaded in the rare case
     // that the exact spans lie in another cell).
-    const int mcg = macro_cell(m, q.B, q.j);
+    Probe q;
+    int mcg;
     uint32_t bh = 0;
-    if (mcg != last_mc) bh = m.mcb[mcg];
-    const Loc Lc = finish(m, R, q);
+    Loc Lc;
+    auto locate_in = [&](const DevBlock* B, const double (&xc)[3]) {
+      probe_spans<GT>(m, R, xc, B, q);
+      mcg = macro_cell(m, q.B, q.j);
+      if (mcg != last_mc) bh = m.mcb[mcg];
+      Lc = finish(m, R, q);
+    };
+    if constexpr (MULTI) {
+      // Most waves have all their samples of this step in one block: then
+      // its record is read once for the wave, through the scalar cache,
+      // instead of by every lane.
+      double xc[3];
+      probe_owner(m, x, EDG, q, xc);
+      const int bu = __builtin_amdgcn_readfirstlane(q.block);
+      if (__builtin_amdgcn_ballot_w64(q.block != bu) == 0)
+        locate_in(m.blocks + bu, xc);
+      else
+        locate_in(m.blocks + q.block, xc);
+    } else {
+      q = probe<MULTI, GT>(m, R, x, EDG);
+      mcg = macro_cell(m, q.B, q.j);
+      if (mcg != last_mc) bh = m.mcb[mcg];
+      Lc = finish(m, R, q);
+    }
     if (Lc.mc != last_mc) {
       if (Lc.mc != mcg) bh = m.mcb[Lc.mc];
       last_empty = transparent(bh, r, zpre);
