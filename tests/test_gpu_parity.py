@@ -451,6 +451,32 @@ def test_render_multiblock_rays_cross_blocks(mfa, dev, kind):
     assert r["samples"] > 20000
 
 
+def test_render_multiblock_more_edges_than_the_lds_copy(mfa, dev):
+    """254 x 1 x 1 blocks: 259 block edges, more than the render's LDS copy
+    holds, so the frame takes the kernel that reads the edges from global
+    memory; rays cross many blocks along axis 0."""
+    rng = np.random.default_rng(23)
+    p = 3
+    field = synth.field_c1(23)
+    g0 = 254
+    edges = [np.linspace(0.0, 1.0, g0 + 1), np.array([0.0, 1.0]), np.array([0.0, 1.0])]
+    blocks = []
+    for b0 in range(g0):
+        n = [int(v) for v in rng.integers(p + 1, p + 3, size=3)]
+        knots = [synth.clamped_uniform_knots(n[a], p) for a in range(3)]
+        lo = np.array([edges[0][b0], 0.0, 0.0])
+        hi = np.array([edges[0][b0 + 1], 1.0, 1.0])
+        xs = [lo[a] + synth.greville(knots[a], p, n[a]) * (hi[a] - lo[a]) for a in range(3)]
+        blocks.append(synth.BlockSpec([p] * 3, knots, field.value_separable(*xs)))
+    model = synth.ModelSpec([g0, 1, 1], np.zeros(3), np.ones(3), edges, blocks, voxel=1.0 / 63)
+    W, H = 48, 40
+    cam = synth.perspective_camera(W, H, az_deg=20, el_deg=15)
+    params = synth.render_params(model)
+    announce(f"render multi-block {g0}x1x1 {W}x{H}")
+    r = check_render(mfa, dev, model, cam, params, W, H)
+    assert r["samples"] > 10000
+
+
 def test_render_and_sorted_decode_multiblock_with_many_basis_tables(mfa, dev):
     """Graded knots in every block: the basis tables exceed the kernels' LDS
     copy, so the render reads them from the global pool and the sorted
