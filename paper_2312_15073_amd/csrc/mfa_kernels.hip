@@ -1822,7 +1822,20 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
   const int64_t pid = (int64_t)j * r.w + i;
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
   const int k_hi = ray.K;
-  const int k0 = pix ? first_visible<P, MULTI, GT>(m, r, R, ray, zpre, 0, k_hi, m.edges) : 0;
+  // The four lanes of a ray search a quarter of it each for the first
+  // sample in a non-transparent fine super cell (the segment's end if none);
+  // the first of the four results is that of the whole ray.
+  int kv = k_hi;
+  if (pix) {
+    const int seg = (k_hi + 3) >> 2;
+    const int lo = min(k_hi, s * seg), hi = min(k_hi, lo + seg);
+    const int f = first_visible<P, MULTI, GT>(m, r, R, ray, zpre, lo, hi, m.edges);
+    kv = f < hi ? f : k_hi;
+  }
+  const int k0 = min(min(__float_as_int(quad_bcast<0>(__int_as_float(kv))),
+                         __float_as_int(quad_bcast<1>(__int_as_float(kv)))),
+                     min(__float_as_int(quad_bcast<2>(__int_as_float(kv))),
+                         __float_as_int(quad_bcast<3>(__int_as_float(kv)))));
   if (r.alpha && pix)
     for (int q = s; q < k0; q += 4) r.alpha[pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
