@@ -53,8 +53,8 @@ FRAME = 1024
 TRAFFIC = {
     # 1024^2 frame of the 128^3 model; copy reference: 512 MiB read + 512 MiB
     # written, FETCH_SIZE 262162 KiB (scale 2.0), WRITE_SIZE 524288 KiB (1.0)
-    "render": {"kernels_sha256": "2b10d10eb4137c23fb372bf493e06e78ad0fb0e8c8c315c9fef9446166f2b00b",
-               "fetch_kib": 37286.9, "fetch_scale": 2.0, "write_kib": 16398.2, "write_scale": 1.0},
+    "render": {"kernels_sha256": "8573795eed3240805626e2fd7486135d958eb053fd269191f7573b181a3a9ae6",
+               "fetch_kib": 37541.7, "fetch_scale": 2.0, "write_kib": 16399.0, "write_scale": 1.0},
 }
 
 
