@@ -1812,44 +1812,59 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
   Ray ray;
   ray.K = 0;
   if (pix) ray = make_ray(m, r, i, j);
-  float L[3] = {0.f, 0.f, 0.f};
-  if (pix) {
+  // the ray's headlight direction, kept in LDS (read once per evaluated
+  // sample) rather than in three registers for the whole loop
+  __shared__ float4 lray[kBlock / 4];
+  if (pix && s == 0) {
     const double dn = sqrt(ray.d[0] * ray.d[0] + ray.d[1] * ray.d[1] + ray.d[2] * ray.d[2]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) L[a] = (float)(-ray.d[a] / dn);
+    lray[threadIdx.x >> 2] = make_float4((float)(-ray.d[0] / dn), (float)(-ray.d[1] / dn),
+                                         (float)(-ray.d[2] / dn), 0.f);
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(m.ctrl, m.ctrl_bytes);
-  const int64_t pid = (int64_t)j * r.w + i;
+  const int pid = j * r.w + i;                     // w, h <= 16384
   float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f;
   const int k_hi = ray.K;
   // The four lanes of a ray search a quarter of it each for the first
-  // sample in a non-transparent fine super cell (the segment's end if none);
-  // the first of the four results is that of the whole ray.
-  int kv = k_hi;
+  // sample in a non-transparent fine super cell (the quarter's end if
+  // none): the first of the four results is that of the whole ray, and the
+  // quarters at the ray's end with no such sample are left out of the loop
+  // (k_end), their samples all having alpha = 0.
+  const int seg = (k_hi + 3) >> 2;
+  int kv = k_hi, emp = 1;
   if (pix) {
-    const int seg = (k_hi + 3) >> 2;
     const int lo = min(k_hi, s * seg), hi = min(k_hi, lo + seg);
     const int f = first_visible<P, MULTI, GT>(m, r, R, ray, zpre, lo, hi, m.edges);
     kv = f < hi ? f : k_hi;
+    emp = f < hi ? 0 : 1;
   }
   const int k0 = min(min(__float_as_int(quad_bcast<0>(__int_as_float(kv))),
                          __float_as_int(quad_bcast<1>(__int_as_float(kv)))),
                      min(__float_as_int(quad_bcast<2>(__int_as_float(kv))),
                          __float_as_int(quad_bcast<3>(__int_as_float(kv)))));
+  const int e = (__float_as_int(quad_bcast<0>(__int_as_float(emp)))) |
+                (__float_as_int(quad_bcast<1>(__int_as_float(emp))) << 1) |
+                (__float_as_int(quad_bcast<2>(__int_as_float(emp))) << 2) |
+                (__float_as_int(quad_bcast<3>(__int_as_float(emp))) << 3);
+  // first quarter from which every later one is empty (4: none)
+  const int qe = (e & 8) ? ((e & 4) ? ((e & 2) ? ((e & 1) ? 0 : 1) : 2) : 3) : 4;
+  const int k_end = min(k_hi, qe * seg);
   if (r.alpha && pix)
-    for (int q = s; q < k0; q += 4) r.alpha[pid * r.alpha_stride + q] = 0.f;
+    for (int q = s; q < k0; q += 4) r.alpha[(int64_t)pid * r.alpha_stride + q] = 0.f;
   int used = k0, nev = 0;
   bool done = false;
   int last_mc = -1;
   bool last_empty = false;
   for (int kb = k0;; kb += 4) {
-    const bool act = pix && !done && kb < k_hi;      // the same in the four lanes of a ray
+    const bool act = pix && !done && kb < k_end;     // the same in the four lanes of a ray
     if (__ballot(act) == 0) break;
     if (!act) continue;
     const int k = kb + s;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     bool ev = false;
-    if (k < k_hi) {
+    if (k < k_end) {
       double x[3];
       sample_point(ray, r.step, k, x);
       Probe pr = probe<MULTI, GT>(m, R, x);
@@ -1863,7 +1878,10 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
         last_mc = Lc.mc;
       }
       if (!last_empty) {
-        q = shade_sample(evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat), L, tf, r);
+        const float4 e = evaluate<P, S, !MULTI>(Lc, rs, MT, m.mat_stride, m.imat);
+        const float4 l4 = lray[threadIdx.x >> 2];   // written by lane 0 of the ray, same wave
+        const float L[3] = {l4.x, l4.y, l4.z};
+        q = shade_sample(e, L, tf, r);
         ev = true;
       }
     }
@@ -1889,12 +1907,17 @@ __device__ __forceinline__ void render_tile4(const DevModel& m, const RenderArgs
       step(q2, 2);
       step(q3, 3);
       done = stop != 0;
-      used = done ? kb + stop : min(kb + 4, k_hi);
+      used = done ? kb + stop : min(kb + 4, k_end);
     } else {
-      used = min(kb + 4, k_hi);
+      used = min(kb + 4, k_end);
     }
     nev += (ev && k < used) ? 1 : 0;
-    if (r.alpha && k < used) r.alpha[pid * r.alpha_stride + k] = ev ? q.w : 0.f;
+    if (r.alpha && k < used) r.alpha[(int64_t)pid * r.alpha_stride + k] = ev ? q.w : 0.f;
+  }
+  if (pix && !done) {               // the transparent quarters at the end leave C and A as they are
+    if (r.alpha)
+      for (int q = k_end + s; q < k_hi; q += 4) r.alpha[(int64_t)pid * r.alpha_stride + q] = 0.f;
+    used = k_hi;
   }
   // evaluated samples of the ray: the sum over its four lanes
   {
