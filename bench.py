@@ -53,8 +53,8 @@ FRAME = 1024
 TRAFFIC = {
     # 1024^2 frame of the 128^3 model; copy reference: 512 MiB read + 512 MiB
     # written, FETCH_SIZE 262162 KiB (scale 2.0), WRITE_SIZE 524288 KiB (1.0)
-    "render": {"kernels_sha256": "8573795eed3240805626e2fd7486135d958eb053fd269191f7573b181a3a9ae6",
-               "fetch_kib": 37541.7, "fetch_scale": 2.0, "write_kib": 16399.0, "write_scale": 1.0},
+    "render": {"kernels_sha256": "70e72733195c2fe2f9ead7f21fcc43d38cc7d05353f00682755084369c83af29",
+               "fetch_kib": 36009.2, "fetch_scale": 2.0, "write_kib": 16397.0, "write_scale": 1.0},
 }
 
 
