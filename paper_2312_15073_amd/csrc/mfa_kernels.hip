@@ -553,8 +553,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
 // keys relative to the chunk's first coarse key fit a small LDS table.
 constexpr int kFineKeys = 1024;                    // LDS keys of a fine-pass chunk
 constexpr int kHistThreads = 1024;                 // histogram workgroup
-constexpr int kHistPer = 63;                       // points per thread: at most 65535 per chunk
-constexpr int kHistChunk = kHistThreads * kHistPer;
+// Points per thread and chunk of the histogram (a chunk < 65536 points):
+// measured best at 63 for single blocks, 16 for multi-block models.
+template <bool MULTI>
+constexpr int hist_per() { return MULTI ? 16 : 63; }
+template <bool MULTI>
+constexpr int hist_chunk() { return kHistThreads * hist_per<MULTI>(); }
+constexpr int kHistGrid = 2 * 256;                 // two workgroups per CU, each with a range of chunks
 constexpr int kScanThreads = 1024;
 
 // Sort tables of a multi-block model in LDS: block edges (FP32), then one
@@ -646,16 +651,22 @@ __global__ __launch_bounds__(kBlock) void fill_u32_k(uint32_t* __restrict__ p, i
   if (i < n) p[i] = 0u;
 }
 
-// Bucket counts of one chunk of kHistChunk points (< 65536, so a 16-bit
-// counter cannot overflow): two counters per LDS word (bucket b in the
-// half b & 1 of word b >> 1).  Dynamic LDS: the sort tables, then the
-// counters.
+// Bucket counts of an equal range of points per workgroup, taken in chunks
+// of at most hist_chunk() points: 16-bit counters, two per LDS word
+// (bucket b in the half b & 1 of word b >> 1), added to the global counts
+// at the end.  Before each later chunk a counter above kSafe (which the
+// chunk could take past 65535) is moved to the global counts first.
+// Few workgroups, each with many points, keep the final global additions
+// (one per bucket and workgroup) few.  Dynamic LDS: the sort tables, then
+// the counters.
 template <bool MULTI, bool GT, bool TL>
 __global__ __launch_bounds__(kHistThreads, MULTI ? 8 : 1) void sort_hist_k(DevModel m, SortArgs sa) {
   // Multi-block models hold up to kMaxBuckets 16-bit counters (64 KB of
   // LDS), so two workgroups fit a CU only at eight waves per SIMD, i.e. at
   // most 64 registers: two points per step there, four otherwise.
   constexpr int kHistIlp = MULTI ? 2 : 4;
+  constexpr int kHistPer = hist_per<MULTI>(), kHistChunk = hist_chunk<MULTI>();
+  constexpr uint32_t kSafe = 65535u - (uint32_t)kHistChunk;
   extern __shared__ float4 sdyn[];
   const SortTabs tb = stage_sort_tabs<MULTI, TL>(m, sdyn);
   uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(sdyn) +
@@ -663,34 +674,54 @@ __global__ __launch_bounds__(kHistThreads, MULTI ? 8 : 1) void sort_hist_k(DevMo
   const int nw = (sa.nb + 1) >> 1;
   for (int w = threadIdx.x; w < nw; w += kHistThreads) h[w] = 0u;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kHistChunk;
-  // kHistIlp independent points per step keep several bucket computations
-  // (chains of dependent LDS loads) in flight per thread.  The points of
-  // the next step are loaded before this step's bucket ids are stored: a
-  // wait for loads also waits for the stores issued before them
-  auto load = [&](int q, float (&x)[kHistIlp][3]) {
-#pragma unroll
-    for (int u = 0; u < kHistIlp; ++u) {
-      const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
-      const int64_t ic = q + u < kHistPer && i < sa.n ? i : 0;
-      x[u][0] = sa.xyz[ic];
-      x[u][1] = sa.xyz[sa.n + ic];
-      x[u][2] = sa.xyz[2 * sa.n + ic];
+  // the workgroup's range [r0, r1): a multiple of kHistThreads points
+  const int64_t per = ((sa.n + gridDim.x - 1) / gridDim.x + kHistThreads - 1) / kHistThreads * kHistThreads;
+  const int64_t r0 = min(sa.n, (int64_t)blockIdx.x * per), r1 = min(sa.n, r0 + per);
+  for (int64_t c0 = r0; c0 < r1; c0 += kHistChunk) {
+    if (c0 != r0) {
+      // the previous chunk's LDS additions must have landed before the
+      // counters are read: the compiler leaves this barrier (reached over
+      // the loop's back edge) without that wait, so it is made explicit
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      __syncthreads();
+      for (int w = threadIdx.x; w < nw; w += kHistThreads) {
+        const uint32_t v = h[w], lo = v & 0xFFFFu, hi = v >> 16;
+        if (lo > kSafe || hi > kSafe) {
+          if (lo > kSafe) atomicAdd(sa.hist + 2 * w, lo);
+          if (hi > kSafe) atomicAdd(sa.hist + 2 * w + 1, hi);
+          h[w] = (lo > kSafe ? 0u : lo) | ((hi > kSafe ? 0u : hi) << 16);
+        }
+      }
+      __syncthreads();
     }
-  };
-  float x[kHistIlp][3];
-  load(0, x);
-  for (int q = 0; q < kHistPer; q += kHistIlp) {
-    uint32_t b[kHistIlp];
+    // kHistIlp independent points per step keep several bucket computations
+    // (chains of dependent LDS loads) in flight per thread.  The points of
+    // the next step are loaded before this step's bucket ids are stored: a
+    // wait for loads also waits for the stores issued before them
+    auto load = [&](int q, float (&x)[kHistIlp][3]) {
 #pragma unroll
-    for (int u = 0; u < kHistIlp; ++u) b[u] = sort_bucket<MULTI, GT>(m, tb, x[u]);
-    if (q + kHistIlp < kHistPer) load(q + kHistIlp, x);
+      for (int u = 0; u < kHistIlp; ++u) {
+        const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
+        const int64_t ic = q + u < kHistPer && i < r1 ? i : 0;
+        x[u][0] = sa.xyz[ic];
+        x[u][1] = sa.xyz[sa.n + ic];
+        x[u][2] = sa.xyz[2 * sa.n + ic];
+      }
+    };
+    float x[kHistIlp][3];
+    load(0, x);
+    for (int q = 0; q < kHistPer; q += kHistIlp) {
+      uint32_t b[kHistIlp];
 #pragma unroll
-    for (int u = 0; u < kHistIlp; ++u) {
-      const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
-      if (q + u < kHistPer && i < sa.n) {
-        atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
-        if (sa.bkt) sa.bkt[i] = (uint16_t)b[u];
+      for (int u = 0; u < kHistIlp; ++u) b[u] = sort_bucket<MULTI, GT>(m, tb, x[u]);
+      if (q + kHistIlp < kHistPer) load(q + kHistIlp, x);
+#pragma unroll
+      for (int u = 0; u < kHistIlp; ++u) {
+        const int64_t i = c0 + (int64_t)(q + u) * kHistThreads + threadIdx.x;
+        if (q + u < kHistPer && i < r1) {
+          atomicAdd(h + (b[u] >> 1), 1u << ((b[u] & 1u) * 16u));
+          if (sa.bkt) sa.bkt[i] = (uint16_t)b[u];
+        }
       }
     }
   }
@@ -2656,7 +2687,10 @@ static hipError_t points_p(const DevModel& m, int kind, bool grad, const float* 
 // Histogram, scan and scatter of the (block, tile) sort.
 template <bool MULTI, bool GT, bool TL>
 static void sort_launch_tl(const DevModel& m, const SortArgs& sa, size_t tabs, hipStream_t st) {
-  const unsigned gh = (unsigned)((sa.n + kHistChunk - 1) / kHistChunk);
+  // a chunk per workgroup, at most kHistGrid workgroups (each then takes
+  // several chunks: fewer final additions to the global counts)
+  const unsigned gh =
+      (unsigned)std::min<int64_t>((sa.n + hist_chunk<MULTI>() - 1) / hist_chunk<MULTI>(), kHistGrid);
   const size_t hist_lds = tabs + (size_t)((sa.nb + 1) / 2) * 4;
   hipLaunchKernelGGL((sort_hist_k<MULTI, GT, TL>), dim3(gh), dim3(kHistThreads), hist_lds, st, m, sa);
   hipLaunchKernelGGL(sort_scan_k, dim3(1), dim3(kScanThreads), 0, st, sa);

@@ -654,6 +654,19 @@ def test_sorted_decode_c2_1e7(mfa, dev, c2):
     _sorted_matches_unsorted(mfa, dev, c2, pts)
 
 
+def test_sorted_decode_one_bucket_several_chunks_per_workgroup(mfa, dev, c1):
+    """The 16^3 model is one sort bucket.  34e6 points exceed 512 histogram
+    workgroups of one 64512-point chunk each, so every workgroup counts two
+    chunks and, before the second, moves its (64512-point) bucket counter to
+    the global counts: totals and results must come out as in the unsorted
+    decode, bit for bit."""
+    n = 34_000_000
+    assert n > 512 * 1024 * 63
+    pts = synth.random_points(n, seed=16, lo=(-0.05,) * 3, hi=(1.05,) * 3)
+    announce(f"sorted decode c1 one bucket n={n}")
+    _sorted_matches_unsorted(mfa, dev, c1, pts)
+
+
 @pytest.mark.parametrize("n", [1, 777, 5000, 300001])
 def test_sorted_decode_c4_small_inputs(mfa, dev, c4, n):
     """Few points over the 8x8x8-block model's ~18k buckets: the coarse runs
