@@ -2763,7 +2763,8 @@ static void decode_sorted_g(const DevModel& m, int kind, const SortArgs& sa, flo
 // Results of the decode in coarse order (sa.tpos) gathered back into input
 // order: out[i] = src[tpos[i]].  The positions of consecutive points fall
 // into one short run per coarse key of their scatter chunk, so the gathers
-// read whole lines.
+// read whole lines.  tpos is read once and out written once in whole
+// lines: streaming loads and stores.
 constexpr int kUnsortPer = 4;
 
 template <bool G>
@@ -2776,7 +2777,7 @@ __global__ __launch_bounds__(kBlock) void unsort_k(const uint32_t* __restrict__ 
   uint32_t k[kUnsortPer];
 #pragma unroll
   for (int u = 0; u < kUnsortPer; ++u)
-    k[u] = min(tpos[min(i0 + u * kBlock, n - 1)], (uint32_t)(n - 1));
+    k[u] = min(__builtin_nontemporal_load(tpos + min(i0 + u * kBlock, n - 1)), (uint32_t)(n - 1));
   // A slot past n repeats element n - 1 (its tpos entry, its value and its
   // destination), a duplicate write of an equal value.  The empty asm takes
   // all gathered values before the first store, so no store is in flight
@@ -2789,14 +2790,14 @@ __global__ __launch_bounds__(kBlock) void unsort_k(const uint32_t* __restrict__ 
     asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : : "memory");
 #pragma unroll
     for (int u = 0; u < kUnsortPer; ++u)
-      reinterpret_cast<f32x4*>(out)[min(i0 + u * kBlock, n - 1)] = v[u];
+      __builtin_nontemporal_store(v[u], reinterpret_cast<f32x4*>(out) + min(i0 + u * kBlock, n - 1));
   } else {
     float v[kUnsortPer];
 #pragma unroll
     for (int u = 0; u < kUnsortPer; ++u) v[u] = src[k[u]];
     asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : : "memory");
 #pragma unroll
-    for (int u = 0; u < kUnsortPer; ++u) out[min(i0 + u * kBlock, n - 1)] = v[u];
+    for (int u = 0; u < kUnsortPer; ++u) __builtin_nontemporal_store(v[u], out + min(i0 + u * kBlock, n - 1));
   }
 }
 
