@@ -1233,14 +1233,15 @@ __global__ __launch_bounds__(kBlock, (MULTI && P <= 3) ? 4 : 1) void decode_tile
   float4 pres = make_float4(0.f, 0.f, 0.f, 0.f);
   const f32x4* __restrict__ rec4 = reinterpret_cast<const f32x4*>(sa.rec);
   uint32_t t = s0 + threadIdx.x;
-  f32x4 q = rec4[min(t, s1 - 1)];
+  // each record is read once: streaming loads
+  f32x4 q = __builtin_nontemporal_load(rec4 + min(t, s1 - 1));
   for (; t < s1; t += kBlock) {
     asm volatile("" : "+v"(q) : : "memory");
     const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
     const uint32_t i = __float_as_uint(q.w);
     if (pi != kNone) put_result<G>(out, pi, pres);
     pi = kNone;
-    q = rec4[min(t + kBlock, s1 - 1)];
+    q = __builtin_nontemporal_load(rec4 + min(t + kBlock, s1 - 1));
     Loc L;
     if constexpr (MULTI) {
       bool own = true;
